@@ -1,0 +1,183 @@
+"""Benchmark: interval-SVD solves per second on one MI355X.
+
+One "step" is one full ``csvd_solve_interval`` call (Algorithm 1: shifted
+solves and moments, low-rank step, QR of A V~, SVD of B and the residual
+check) on a synthetic sparse matrix already resident in HBM.
+
+Default workload (--config c2): random sparse A, m = 200000, n = 100000, 10
+nonzeros per column at uniform random rows, N(0,1) values, CSR FP64; the
+interval holds about 64 singular values near the median of the spectrum
+(located on a 25x smaller same-distribution instance); N = 32, L = 64,
+M = 8, FP64.  --config c1 runs the 1200 x 1000 Givens-rotated matrix with
+exactly known singular values on [0.40, 0.45] (N = 16, L = 16, M = 8).
+
+Prints one JSON line (see the field list at the end of main()).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def workload(name):
+    import numpy as np
+    import synth
+    if name == "c1":
+        I = synth.givens_known()
+        return dict(I=I, a=I.a, b=I.b, L=16, M=8, N=16, ell=2, norm_a=1.0,
+                    desc="givens_1200x1000_linspace_sigma_[0.40,0.45]")
+    if name == "c2":
+        m, n = 200000, 100000
+        I = synth.random_sparse(m, n, 10, config=2)
+        a, b, lq, dens = synth.interval_from_sample(m, n, 10, 64, config=2)
+        return dict(I=I, a=a, b=b, L=64, M=8, N=32, ell=1, norm_a=0.0,
+                    desc=f"random_sparse_{m}x{n}_10nnz_per_col_interval_64_near_median")
+    raise SystemExit(f"unknown config {name}")
+
+
+def cpu_baseline(W, iters_gpu, seconds=15.0):
+    """The oracle's per-shift COCG timed on the host for a bounded number of
+    iterations on the same matrix and right-hand sides, scaled to one full
+    solve (N/2 shifts x the iteration count the GPU needed)."""
+    import numpy as np
+    import synth
+    from oracle import krylov, quadrature as Q
+    I = W["I"]
+    shifts, c = Q.moment_coeffs(W["a"], W["b"], W["N"], W["M"], 0.1, Q.PLAIN)
+    V = synth.v_in(I.n, W["L"], 2, 0)
+    j = 0
+    t0 = time.perf_counter()
+    _, it, res, sec = krylov.cocg(I, shifts[j], V, tol=1e-300, maxit=10 ** 9, time_limit=seconds)
+    per_it = sec / max(it, 1)
+    per_solve = per_it * iters_gpu * (W["N"] // 2) * W.get("ell", 1)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1,
+            "kind": "oracle",
+            "sample": (f"oracle COCG (scipy CSR products, single-threaded) on shift 1 of {W['N'] // 2}, "
+                       f"all {W['L']} columns, {it} iterations in {sec:.1f}s on the full matrix; "
+                       f"scaled by {W['N'] // 2} shifts x {iters_gpu} iterations (extrapolated); "
+                       f"OMP_NUM_THREADS={threads}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--max-iters", type=int, default=0)
+    ap.add_argument("--window", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the path is single-GPU by design "
+              "(shift sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2109_13655_amd as cs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    W = workload(args.config)
+    I = W["I"]
+    log("workload", W["desc"], "nnz", I.nnz, "interval", W["a"], W["b"])
+    ctx = cs.csvd_create(I.m, I.n, I.rowptr, I.colidx, I.vals, hip_stream=stream.cuda_stream)
+    p = cs.csvd_params_default(L=W["L"], M=W["M"], N=W["N"], ell=W["ell"], norm_a=W["norm_a"],
+                               precision=cs.CSVD_MIXED if args.precision == "mixed" else cs.CSVD_FP64,
+                               window=args.window)
+    if args.max_iters:
+        p.max_iters = args.max_iters
+    import synth
+    V = synth.v_in(I.n, W["L"], 2, 0)
+    for i in range(args.warmup):
+        cs.csvd_solve_interval(ctx, W["a"], W["b"], p, V)
+        log("warmup", i, "done")
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status = []
+    for i in range(args.steps):
+        s0 = time.perf_counter()
+        status.append(cs.csvd_solve_interval(ctx, W["a"], W["b"], p, V))
+        lat.append(time.perf_counter() - s0)
+        info = cs.csvd_get_info(ctx)
+        log(f"step {i}: {lat[-1]:.3f}s status {status[-1]} iters {info.iterations_total} t_hat {info.t_hat} "
+            f"max resid {info.max_triplet_resid:.2e}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = cs.csvd_get_info(ctx)
+    sigma, _, _, resid = cs.csvd_get_triplets(ctx, I.m, I.n, want_vectors=False)
+    cs.csvd_destroy(ctx)
+
+    elapsed = t1 - t0
+    value = args.steps / elapsed
+    at_gbs = info.spmm_at_bytes / (info.spmm_at_ms * 1e-3) / 1e9 if info.spmm_at_ms > 0 else None
+    a_gbs = info.spmm_a_bytes / (info.spmm_a_ms * 1e-3) / 1e9 if info.spmm_a_ms > 0 else None
+    lat_ms = sorted(x * 1e3 for x in lat)
+
+    def pct(q):
+        return lat_ms[min(len(lat_ms) - 1, int(math.ceil(q * len(lat_ms))) - 1)]
+
+    out = {
+        "metric": "interval-SVD solves/sec + SpMM HBM GB/s at rel. residual <=1e-8; p50/p99 latency",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": W["desc"], "m": I.m, "n": I.n, "nnz": I.nnz, "interval": [W["a"], W["b"]],
+                   "N": W["N"], "L": W["L"], "M": W["M"], "ell": W["ell"], "precision": args.precision,
+                   "window": info.window},
+        "p50_ms": pct(0.5),
+        "p99_ms": pct(0.99),
+        "spmm_hbm_gbs": at_gbs,
+        "spmm_a_gbs": a_gbs,
+        "max_rel_residual": float(resid.max()) if resid.size else None,
+        "t_hat": int(info.t_hat),
+        "lanczos_steps": int(info.iterations_total),
+        "converged": bool(info.converged),
+        "status": status,
+        "phase_ms": {"solve": info.t_solve_ms, "lowrank": info.t_lowrank_ms, "qr": info.t_qr_ms,
+                     "extract": info.t_extract_ms},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k2_spmm_lanczos (A^T product + Lanczos update + window store)",
+            "achieved": at_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": (at_gbs / HBM_PEAK_GBS) if at_gbs else None,
+            "traffic": None,
+            "bytes_per_launch": info.spmm_at_bytes,
+            "avg_launch_ms": info.spmm_at_ms,
+            "samples": int(info.spmm_samples),
+        },
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle COCG sample)")
+        out["cpu_baseline"] = cpu_baseline(W, info.iterations_total)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -18,8 +18,9 @@ method      Algorithms 1 and 2 step by step with dense direct shifted solves,
 truth       dense LAPACK SVD truth and triplet residual certificates.
 krylov      a plain per-shift COCG solver for sizes where dense solves do not
             fit (used for CPU timing samples and moderate-size checks).
+sparse      CSR transpose and row-sampled products by their definitions.
 
 Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``
 against closed forms, invariants or exact spectra; none is "parity unpinned".
 """
-from . import quadrature, method, truth, krylov  # noqa: F401
+from . import quadrature, method, truth, krylov, sparse  # noqa: F401

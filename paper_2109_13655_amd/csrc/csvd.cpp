@@ -1,0 +1,1140 @@
+// C ABI of the interior singular triplet solver: argument checking, the
+// quadrature rule, the round structure of Algorithms 1/2 (eq. iter1/iter2)
+// around the batched Lanczos engine, and the dense steps 3-5.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "engine.h"
+
+using namespace csvd;
+
+namespace {
+
+// ------------------------------------------------------------------ errors
+int set_err(csvd_ctx *c, int code, const std::string &msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_code(hipError_t e) { return e == hipErrorOutOfMemory ? CSVD_ENOMEM : CSVD_EDEVICE; }
+
+#define HIPCHK(ctx, expr)                                                                              \
+  do {                                                                                                 \
+    hipError_t _e = (expr);                                                                            \
+    if (_e != hipSuccess)                                                                              \
+      return set_err((ctx), hip_code(_e), std::string("HIP error '") + hipGetErrorString(_e) + "' in " \
+                                              + #expr);                                                \
+  } while (0)
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// --------------------------------------------------------------- quadrature
+// Sec. 4: theta_j = 2 pi (j - 1/2) / N; point t_j = gamma + rho (cos + i alpha sin);
+// plain: shift z_j = t_j, weight omega_j = rho/N (alpha cos + i sin);
+// exp:   shift exp(t_j), weight psi_j = rho/N exp(t_j) (alpha cos + i sin).
+// Only j = 1..N/2 are kept (the other half are conjugates, Sec. 3.1).
+void quadrature(double a, double b, int N, int M, double alpha, int transform, SolveSpec *out) {
+  const int S = N / 2;
+  double gamma, rho;
+  if (transform == CSVD_PLAIN) {
+    gamma = 0.5 * (a * a + b * b);
+    rho = 0.5 * (b * b - a * a);
+  } else {
+    gamma = std::log(a) + std::log(b);
+    rho = std::log(b) - std::log(a);
+  }
+  out->S = S;
+  out->shift_re.assign(S, 0.0);
+  out->shift_im.assign(S, 0.0);
+  out->c_re.assign((size_t)S * (M + 1), 0.0);
+  out->c_im.assign((size_t)S * (M + 1), 0.0);
+  for (int j = 0; j < S; ++j) {
+    const double th = 2.0 * M_PI / N * (j + 0.5);
+    const double ct = std::cos(th), st = std::sin(th);
+    const double tr = gamma + rho * ct, ti = rho * alpha * st;  // point t_j
+    double dr = rho / N * alpha * ct, di = rho / N * st;        // rho/N (alpha cos + i sin)
+    double sr = tr, si = ti;
+    if (transform == CSVD_EXP) {
+      const double ex = std::exp(tr);
+      sr = ex * std::cos(ti);
+      si = ex * std::sin(ti);
+      const double wr = dr * sr - di * si, wi = dr * si + di * sr;  // times exp(t_j)
+      dr = wr;
+      di = wi;
+    }
+    out->shift_re[j] = sr;
+    out->shift_im[j] = si;
+    double pr = 1.0, pi = 0.0;  // t_j^k
+    for (int k = 0; k <= M; ++k) {
+      out->c_re[(size_t)j * (M + 1) + k] = dr * pr - di * pi;
+      out->c_im[(size_t)j * (M + 1) + k] = dr * pi + di * pr;
+      const double nr = pr * tr - pi * ti, ni = pr * ti + pi * tr;
+      pr = nr;
+      pi = ni;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- V_in RNG
+// Counter-based N(0,1): SplitMix64 (Steele, Lea, Flood 2014) output k of the
+// stream seeded with s is mix(s + (k+1) * 0x9E3779B97F4A7C15); entry e of
+// the column-major n x L block uses outputs 2e and 2e+1 as u1, u2 (top 53
+// bits / 2^53) and the Box-Muller value sqrt(-2 ln(1-u1)) cos(2 pi u2).
+uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+void gaussian_block(uint64_t seed, int64_t count, double *out) {
+  const uint64_t g = 0x9E3779B97F4A7C15ULL;
+  for (int64_t e = 0; e < count; ++e) {
+    const uint64_t k1 = 2 * (uint64_t)e, k2 = k1 + 1;
+    const double u1 = (double)(mix64(seed + (k1 + 1) * g) >> 11) * 0x1.0p-53;
+    const double u2 = (double)(mix64(seed + (k2 + 1) * g) >> 11) * 0x1.0p-53;
+    out[e] = std::sqrt(-2.0 * std::log1p(-u1)) * std::cos(2.0 * M_PI * u2);
+  }
+}
+
+// --------------------------------------------------------- small host math
+// largest eigenvalue of a symmetric tridiagonal (diag d, off e) by bisection
+double tridiag_max_eig(const std::vector<double> &d, const std::vector<double> &e) {
+  const int k = (int)d.size();
+  if (k == 0) return 0.0;
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < k; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(e[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  auto count_below = [&](double x) {  // Sturm count of eigenvalues < x
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < k; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(1.0, std::fabs(hi)); ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= k) hi = mid; else lo = mid;
+  }
+  return hi;
+}
+
+int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
+  if (!p) return set_err(ctx, CSVD_EINVAL, "params is NULL");
+  if (!(std::isfinite(a) && std::isfinite(b)) || !(0.0 <= a && a < b))
+    return set_err(ctx, CSVD_EINVAL, "need 0 <= a < b (finite)");
+  if (p->N < 2 || p->N % 2 || p->N / 2 > kMaxShifts)
+    return set_err(ctx, CSVD_EINVAL, "N must be even, 2 <= N <= 128");
+  if (p->L < 1 || p->L > kMaxLp) return set_err(ctx, CSVD_EINVAL, "L must be in 1..256");
+  if (p->M < 1) return set_err(ctx, CSVD_EINVAL, "M must be >= 1");
+  if ((int64_t)p->L * p->M > ctx->n) return set_err(ctx, CSVD_EINVAL, "L*M must not exceed n");
+  if (p->ell < 1) return set_err(ctx, CSVD_EINVAL, "ell must be >= 1");
+  if (p->transform != CSVD_PLAIN && p->transform != CSVD_EXP)
+    return set_err(ctx, CSVD_EINVAL, "transform must be CSVD_PLAIN or CSVD_EXP");
+  if (p->transform == CSVD_EXP && !(a > 0.0))
+    return set_err(ctx, CSVD_EINVAL, "the exp transform needs a > 0");
+  if (p->precision != CSVD_FP64 && p->precision != CSVD_MIXED)
+    return set_err(ctx, CSVD_EINVAL, "precision must be CSVD_FP64 or CSVD_MIXED");
+  if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) return set_err(ctx, CSVD_EINVAL, "alpha must be > 0");
+  if (!(p->delta >= 0.0) || !(p->solve_rtol > 0.0) || !(p->spurious_eps >= 0.0))
+    return set_err(ctx, CSVD_EINVAL, "delta, spurious_eps must be >= 0 and solve_rtol > 0");
+  if (p->max_iters < 1) return set_err(ctx, CSVD_EINVAL, "max_iters must be >= 1");
+  if (p->window < 0 || p->window > kMaxWindow) return set_err(ctx, CSVD_EINVAL, "window must be 0..64");
+  if (!(p->norm_a >= 0.0)) return set_err(ctx, CSVD_EINVAL, "norm_a must be >= 0");
+  return CSVD_OK;
+}
+
+int pick_window(const csvd_params *p) {
+  int w = p->window > 0 ? p->window : 32;
+  return w;
+}
+
+int pad_L(int L) {
+  int lp = 1;
+  while (lp < L) lp <<= 1;
+  return lp;
+}
+
+}  // namespace
+
+// ============================================================================
+// Solve state machine shared by the solo, batched and served paths.
+namespace csvd {
+
+struct SolveRun {
+  csvd_ctx *ctx = nullptr;
+  SolveSpec spec;
+  int round = 0;
+  DevBuf d_rhs;           // current right-hand side block, column-major
+  int64_t rhs_ld = 0;
+  DevBuf d_coef;          // S x (M+1) moment coefficients (double2)
+  std::unique_ptr<Job> job;
+  int64_t iters_total = 0;
+  bool all_converged = true;
+  double max_res_est = 0.0;
+  int status = CSVD_OK;
+  double t_start = 0, t_solve_end = 0;
+  std::vector<double> hist;  // column-0 Lanczos scalars of the first round
+};
+
+int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params *p, const double *V_host,
+              int W, bool mixed) {
+  R.ctx = ctx;
+  int rc = check_params(ctx, a, b, p);
+  if (rc) return rc;
+  R.t_start = now_ms();
+  R.spec = SolveSpec();
+  R.spec.a = a;
+  R.spec.b = b;
+  R.spec.p = *p;
+  quadrature(a, b, p->N, p->M, p->alpha, p->transform, &R.spec);
+  R.spec.Lp = pad_L(p->L);
+  R.spec.W = W;
+  const int S = R.spec.S, M = p->M, L = p->L;
+  const int64_t n = ctx->n;
+  // host V_in (column-major n x L)
+  std::vector<double> V((size_t)n * L);
+  if (V_host) {
+    std::memcpy(V.data(), V_host, sizeof(double) * V.size());
+    for (double x : V)
+      if (!std::isfinite(x)) return set_err(ctx, CSVD_ENUMERIC, "V_in has a non-finite entry");
+  } else {
+    gaussian_block(p->seed, (int64_t)V.size(), V.data());
+  }
+  HIPCHK(ctx, R.d_rhs.alloc(sizeof(double) * V.size()));
+  HIPCHK(ctx, hipMemcpyAsync(R.d_rhs.p, V.data(), sizeof(double) * V.size(), hipMemcpyHostToDevice, ctx->st));
+  R.rhs_ld = n;
+  std::vector<double> cc(2 * (size_t)S * (M + 1));
+  for (size_t i = 0; i < (size_t)S * (M + 1); ++i) {
+    cc[2 * i] = R.spec.c_re[i];
+    cc[2 * i + 1] = R.spec.c_im[i];
+  }
+  HIPCHK(ctx, R.d_coef.alloc(sizeof(double) * cc.size()));
+  HIPCHK(ctx, hipMemcpyAsync(R.d_coef.p, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice, ctx->st));
+  R.job.reset(new Job());
+  HIPCHK(ctx, R.job->create(ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(), ctx->rpT.as<int>(),
+                            ctx->ciT.as<int>(), ctx->vaT.as<double>(), ctx->m, n, ctx->nnz, L, R.spec.Lp, S, W, mixed,
+                            p->solve_rtol, R.spec.shift_re, R.spec.shift_im, ctx->st));
+  R.job->max_iters = p->max_iters;
+  HIPCHK(ctx, launch_job_init(R.job->h, R.d_rhs.as<double>(), R.rhs_ld, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));  // host V goes out of scope
+  R.round = 0;
+  R.iters_total = 0;
+  R.all_converged = true;
+  R.max_res_est = 0;
+  return CSVD_OK;
+}
+
+// Reads the exit state of the finished job (residual estimates, history).
+static int harvest_job(SolveRun &R) {
+  csvd_ctx *ctx = R.ctx;
+  Job &J = *R.job;
+  const int S = J.h.S, Lp = J.h.Lp, L = J.h.L;
+  std::vector<double> res((size_t)S * Lp);
+  HIPCHK(ctx, hipMemcpyAsync(res.data(), J.h.res, sizeof(double) * res.size(), hipMemcpyDeviceToHost, ctx->st));
+  std::vector<double> hist(2 * kHist);
+  HIPCHK(ctx, hipMemcpyAsync(hist.data(), J.h.nrm_hist, sizeof(double) * hist.size(), hipMemcpyDeviceToHost,
+                             ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  double mx = 0;
+  for (int s = 0; s < S; ++s)
+    for (int l = 0; l < L; ++l) mx = std::max(mx, res[(size_t)s * Lp + l]);
+  R.max_res_est = std::max(R.max_res_est, mx);
+  R.iters_total += J.iters;
+  if (!J.converged) R.all_converged = false;
+  if (R.round == 0) {
+    const int64_t k = std::min<int64_t>(J.iters, kHist);
+    R.hist.assign(hist.begin(), hist.begin() + 2 * k);
+  }
+  return CSVD_OK;
+}
+
+// Called when the job of the current round has finished.  Returns 1 in *more
+// when another round was started (the caller must re-add the job).
+int run_after_round(SolveRun &R, bool *more) {
+  csvd_ctx *ctx = R.ctx;
+  int rc = harvest_job(R);
+  if (rc) return rc;
+  *more = false;
+  const csvd_params &p = R.spec.p;
+  if (R.round + 1 < p.ell) {
+    // eq. iter1: S_0^(nu) = 2 sum_j Re(w_j Y_j) becomes the next right-hand side
+    const int64_t npad = R.job->h.npad;
+    DevBuf nr;
+    HIPCHK(ctx, nr.alloc(sizeof(double) * npad * p.L));
+    // the k = 0 coefficients are the first entries of each shift's row: gather
+    std::vector<double> c0(2 * (size_t)R.spec.S);
+    for (int s = 0; s < R.spec.S; ++s) {
+      c0[2 * s] = R.spec.c_re[(size_t)s * (p.M + 1)];
+      c0[2 * s + 1] = R.spec.c_im[(size_t)s * (p.M + 1)];
+    }
+    DevBuf dc0;
+    HIPCHK(ctx, dc0.alloc(sizeof(double) * c0.size()));
+    HIPCHK(ctx, hipMemcpyAsync(dc0.p, c0.data(), sizeof(double) * c0.size(), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(ctx, launch_moments(R.job->h, dc0.as<double2>(), 1, nr.as<double>(), ctx->st));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+    std::swap(R.d_rhs.p, nr.p);
+    std::swap(R.d_rhs.bytes, nr.bytes);
+    R.rhs_ld = npad;
+    R.round += 1;
+    R.job->iters = 0;
+    R.job->finished = false;
+    R.job->converged = false;
+    HIPCHK(ctx, launch_job_init(R.job->h, R.d_rhs.as<double>(), R.rhs_ld, ctx->st));
+    *more = true;
+  }
+  return CSVD_OK;
+}
+
+// Steps 1-2 (moments) and 3-5 (dense) after the last round.
+int run_finalize(SolveRun &R) {
+  csvd_ctx *ctx = R.ctx;
+  hipStream_t st = ctx->st;
+  const csvd_params &p = R.spec.p;
+  const int L = p.L, M = p.M, S = R.spec.S;
+  const int64_t m = ctx->m, n = ctx->n;
+  const int64_t npad = round_up(n, kRowPad), mpad = round_up(m, kRowPad);
+  Job &J = *R.job;
+  ctx->L = L;
+  ctx->M = M;
+  ctx->N = p.N;
+  ctx->S = S;
+  ctx->npad = npad;
+  ctx->mpad = mpad;
+  csvd_info &info = ctx->info;
+  std::memset(&info, 0, sizeof(info));
+  // ---- moments S_k, k = 0..M (step 2 and the extra moment of Sec. 3.4.1)
+  HIPCHK(ctx, ctx->d_S.alloc(sizeof(double) * npad * (size_t)(M + 1) * L));
+  HIPCHK(ctx, hipMemsetAsync(ctx->d_S.p, 0, ctx->d_S.bytes, st));
+  HIPCHK(ctx, launch_moments(J.h, R.d_coef.as<double2>(), M + 1, ctx->d_S.as<double>(), st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  R.t_solve_end = now_ms();
+  double t0 = R.t_solve_end;
+  const int LM = L * M;
+  // ---- step 3: QR of S-hat (Householder), SVD of R by one-sided Jacobi on R^T
+  DevBuf Xq, tau1;
+  HIPCHK(ctx, Xq.alloc(sizeof(double) * npad * LM));
+  HIPCHK(ctx, tau1.alloc(sizeof(double) * LM));
+  HIPCHK(ctx, hipMemcpyAsync(Xq.p, ctx->d_S.p, sizeof(double) * npad * LM, hipMemcpyDeviceToDevice, st));
+  HIPCHK(ctx, launch_hh_make(Xq.as<double>(), npad, (int)n, 0, tau1.as<double>(), st));
+  for (int j = 0; j + 1 < LM; ++j) HIPCHK(ctx, launch_hh_step(Xq.as<double>(), npad, (int)n, LM, j, tau1.as<double>(), st));
+  // R (LM x LM upper) to the host, R^T back as a column-major LMe x LMe block
+  const int LMe = LM + (LM & 1);
+  std::vector<double> Rh((size_t)LM * LM);
+  HIPCHK(ctx, hipMemcpy2DAsync(Rh.data(), sizeof(double) * LM, Xq.p, sizeof(double) * npad, sizeof(double) * LM, LM,
+                               hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  std::vector<double> Rt((size_t)LMe * LMe, 0.0), Jm((size_t)LMe * LMe, 0.0);
+  for (int c = 0; c < LM; ++c)
+    for (int r = 0; r <= c; ++r) Rt[(size_t)r * LMe + c] = Rh[(size_t)c * LM + r];  // Rt[c, r] = R[r, c]
+  for (int i = 0; i < LMe; ++i) Jm[(size_t)i * LMe + i] = 1.0;
+  DevBuf dRt, dJ, dcnt, dnorm;
+  HIPCHK(ctx, dRt.alloc(sizeof(double) * Rt.size()));
+  HIPCHK(ctx, dJ.alloc(sizeof(double) * Jm.size()));
+  HIPCHK(ctx, dcnt.alloc(sizeof(int)));
+  HIPCHK(ctx, dnorm.alloc(sizeof(double) * (LMe + 1)));
+  HIPCHK(ctx, hipMemcpyAsync(dRt.p, Rt.data(), sizeof(double) * Rt.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, hipMemcpyAsync(dJ.p, Jm.data(), sizeof(double) * Jm.size(), hipMemcpyHostToDevice, st));
+  auto jacobi = [&](double *A, int rows, int ncol_even, double *V, int vrows) -> int {
+    for (int sweep = 0; sweep < 60; ++sweep) {
+      HIPCHK(ctx, hipMemsetAsync(dcnt.p, 0, sizeof(int), st));
+      for (int s2 = 0; s2 + 1 < ncol_even; ++s2)
+        HIPCHK(ctx, launch_jacobi_step(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, 1e-15,
+                                       dcnt.as<int>(), st));
+      int cnt = 0;
+      HIPCHK(ctx, hipMemcpyAsync(&cnt, dcnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      if (cnt == 0) return CSVD_OK;
+    }
+    return CSVD_OK;  // 60 sweeps: accept (reported through residuals)
+  };
+  int rc = jacobi(dRt.as<double>(), LMe, LMe, dJ.as<double>(), LMe);
+  if (rc) return rc;
+  std::vector<double> sS(LMe);
+  HIPCHK(ctx, launch_col_norms(dRt.as<double>(), LMe, LMe, LMe, dnorm.as<double>(), st));
+  HIPCHK(ctx, hipMemcpyAsync(sS.data(), dnorm.p, sizeof(double) * LMe, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(Jm.data(), dJ.p, sizeof(double) * Jm.size(), hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  std::vector<int> perm(LMe);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return sS[x] > sS[y]; });
+  const double s1 = sS[perm[0]];
+  int r = 0;
+  if (s1 > 0)
+    for (int i = 0; i < LM; ++i)
+      if (sS[perm[i]] > p.delta * s1) ++r;
+  info.sigma_s1 = s1;
+  info.rank = r;
+  // V~ = Q [U_R(:, perm[0:r]); 0]
+  DevBuf Vt;
+  HIPCHK(ctx, Vt.alloc(sizeof(double) * npad * std::max(r, 1)));
+  HIPCHK(ctx, hipMemsetAsync(Vt.p, 0, Vt.bytes, st));
+  if (r > 0) {
+    std::vector<double> Z((size_t)LM * r);
+    for (int c = 0; c < r; ++c)
+      for (int i = 0; i < LM; ++i) Z[(size_t)c * LM + i] = Jm[(size_t)perm[c] * LMe + i];
+    HIPCHK(ctx, hipMemcpy2DAsync(Vt.p, sizeof(double) * npad, Z.data(), sizeof(double) * LM, sizeof(double) * LM, r,
+                                 hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, launch_hh_apply(Xq.as<double>(), npad, (int)n, -LM, tau1.as<double>(), Vt.as<double>(), npad, r, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+  }
+  double t1 = now_ms();
+  // ---- step 4: X = A V~, [U~, B] = qr(X)
+  const int re = r + (r & 1);
+  DevBuf Vrow, Xrow, Xa, tau2;
+  std::vector<double> Bh;
+  if (r > 0) {
+    HIPCHK(ctx, Vrow.alloc(sizeof(double) * n * r));
+    HIPCHK(ctx, Xrow.alloc(sizeof(double) * m * r));
+    HIPCHK(ctx, Xa.alloc(sizeof(double) * mpad * r));
+    HIPCHK(ctx, tau2.alloc(sizeof(double) * r));
+    HIPCHK(ctx, hipMemsetAsync(Xa.p, 0, Xa.bytes, st));
+    HIPCHK(ctx, launch_col_to_row((int)n, r, Vt.as<double>(), npad, Vrow.as<double>(), r, st));
+    HIPCHK(ctx, launch_spmm_rowmajor((int)m, r, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
+                                     Vrow.as<double>(), Xrow.as<double>(), st));
+    HIPCHK(ctx, launch_row_to_col((int)m, r, Xrow.as<double>(), r, Xa.as<double>(), mpad, st));
+    HIPCHK(ctx, launch_hh_make(Xa.as<double>(), mpad, (int)m, 0, tau2.as<double>(), st));
+    for (int j = 0; j + 1 < r; ++j) HIPCHK(ctx, launch_hh_step(Xa.as<double>(), mpad, (int)m, r, j, tau2.as<double>(), st));
+    Bh.assign((size_t)r * r, 0.0);
+    std::vector<double> Rb((size_t)r * r);
+    HIPCHK(ctx, hipMemcpy2DAsync(Rb.data(), sizeof(double) * r, Xa.p, sizeof(double) * mpad, sizeof(double) * r, r,
+                                 hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    for (int c = 0; c < r; ++c)
+      for (int i = 0; i <= c; ++i) Bh[(size_t)c * r + i] = Rb[(size_t)c * r + i];
+  }
+  double t2 = now_ms();
+  // ---- step 5: SVD of B = P Phi Q^T by one-sided Jacobi (B J = P Phi, Q = J)
+  std::vector<int> sel;
+  std::vector<double> phi, tauv;
+  std::vector<double> Bj, Jb;
+  if (r > 0) {
+    std::vector<double> Be((size_t)re * re, 0.0), Ie((size_t)re * re, 0.0);
+    for (int c = 0; c < r; ++c)
+      for (int i = 0; i < r; ++i) Be[(size_t)c * re + i] = Bh[(size_t)c * r + i];
+    for (int i = 0; i < re; ++i) Ie[(size_t)i * re + i] = 1.0;
+    DevBuf dB, dQ;
+    HIPCHK(ctx, dB.alloc(sizeof(double) * Be.size()));
+    HIPCHK(ctx, dQ.alloc(sizeof(double) * Ie.size()));
+    HIPCHK(ctx, hipMemcpyAsync(dB.p, Be.data(), sizeof(double) * Be.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(dQ.p, Ie.data(), sizeof(double) * Ie.size(), hipMemcpyHostToDevice, st));
+    rc = jacobi(dB.as<double>(), re, re, dQ.as<double>(), re);
+    if (rc) return rc;
+    phi.assign(re, 0.0);
+    HIPCHK(ctx, launch_col_norms(dB.as<double>(), re, re, re, dnorm.as<double>(), st));
+    HIPCHK(ctx, hipMemcpyAsync(phi.data(), dnorm.p, sizeof(double) * re, hipMemcpyDeviceToHost, st));
+    Bj.assign((size_t)re * re, 0.0);
+    Jb.assign((size_t)re * re, 0.0);
+    HIPCHK(ctx, hipMemcpyAsync(Bj.data(), dB.p, sizeof(double) * Bj.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(Jb.data(), dQ.p, sizeof(double) * Jb.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    // spurious index tau_i = q^T q / q^T Sigma_S1^{-1} q  (Sec. 3.4.2), q = Q(:, i)
+    tauv.assign(re, 0.0);
+    for (int i = 0; i < re; ++i) {
+      double num = 0, den = 0;
+      for (int j = 0; j < r; ++j) {
+        const double q = Jb[(size_t)i * re + j];
+        num += q * q;
+        den += q * q / sS[perm[j]];
+      }
+      tauv[i] = den > 0 ? num / den : 0.0;
+    }
+    for (int i = 0; i < re; ++i) {
+      if (phi[i] >= R.spec.a && phi[i] <= R.spec.b && tauv[i] >= p.spurious_eps * s1 && phi[i] > 0.0) sel.push_back(i);
+    }
+    std::stable_sort(sel.begin(), sel.end(), [&](int x, int y) { return phi[x] < phi[y]; });
+  }
+  const int t = (int)sel.size();
+  ctx->sigma.assign(t, 0.0);
+  ctx->resid.assign(t, 0.0);
+  HIPCHK(ctx, ctx->d_U.alloc(sizeof(double) * mpad * std::max(t, 1)));
+  HIPCHK(ctx, ctx->d_V.alloc(sizeof(double) * npad * std::max(t, 1)));
+  double normA = p.norm_a;
+  if (!(normA > 0)) {
+    std::vector<double> d, e;
+    for (size_t k = 0; k + 1 < R.hist.size(); k += 2) d.push_back(R.hist[k]);
+    for (size_t k = 0; k + 1 < R.hist.size() && e.size() + 1 < d.size(); k += 2) e.push_back(R.hist[k + 1]);
+    normA = std::sqrt(std::max(tridiag_max_eig(d, e), 0.0));
+  }
+  info.norm_a = normA;
+  if (t > 0) {
+    std::vector<double> Qs((size_t)r * t), Ps((size_t)r * t);
+    for (int c = 0; c < t; ++c) {
+      const int i = sel[c];
+      ctx->sigma[c] = phi[i];
+      for (int j = 0; j < r; ++j) {
+        Qs[(size_t)c * r + j] = Jb[(size_t)i * re + j];
+        Ps[(size_t)c * r + j] = Bj[(size_t)i * re + j] / phi[i];
+      }
+    }
+    DevBuf dQs, dPs, dsig;
+    HIPCHK(ctx, dQs.alloc(sizeof(double) * Qs.size()));
+    HIPCHK(ctx, dsig.alloc(sizeof(double) * t));
+    HIPCHK(ctx, hipMemcpyAsync(dQs.p, Qs.data(), sizeof(double) * Qs.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipMemcpyAsync(dsig.p, ctx->sigma.data(), sizeof(double) * t, hipMemcpyHostToDevice, st));
+    // V-hat = V~ Q_sel (MFMA GEMM);  U-hat = Q_X [P_sel; 0]
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_V.p, 0, ctx->d_V.bytes, st));
+    HIPCHK(ctx, launch_gemm((int)npad, t, r, 1.0, Vt.as<double>(), npad, dQs.as<double>(), r, 0.0,
+                            ctx->d_V.as<double>(), npad, st));
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_U.p, 0, ctx->d_U.bytes, st));
+    HIPCHK(ctx, hipMemcpy2DAsync(ctx->d_U.p, sizeof(double) * mpad, Ps.data(), sizeof(double) * r, sizeof(double) * r,
+                                 t, hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, launch_hh_apply(Xa.as<double>(), mpad, (int)m, -r, tau2.as<double>(), ctx->d_U.as<double>(), mpad, t, st));
+    HIPCHK(ctx, launch_sign_fix(ctx->d_U.as<double>(), mpad, (int)m, ctx->d_V.as<double>(), npad, (int)n, t, st));
+    // residuals: ||A v - s u|| and ||A^T u - s v||
+    DevBuf vr, ur, av, atu, o1, o2;
+    HIPCHK(ctx, vr.alloc(sizeof(double) * n * t));
+    HIPCHK(ctx, ur.alloc(sizeof(double) * m * t));
+    HIPCHK(ctx, av.alloc(sizeof(double) * m * t));
+    HIPCHK(ctx, atu.alloc(sizeof(double) * n * t));
+    HIPCHK(ctx, o1.alloc(sizeof(double) * t));
+    HIPCHK(ctx, o2.alloc(sizeof(double) * t));
+    HIPCHK(ctx, launch_col_to_row((int)n, t, ctx->d_V.as<double>(), npad, vr.as<double>(), t, st));
+    HIPCHK(ctx, launch_col_to_row((int)m, t, ctx->d_U.as<double>(), mpad, ur.as<double>(), t, st));
+    HIPCHK(ctx, launch_spmm_rowmajor((int)m, t, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
+                                     vr.as<double>(), av.as<double>(), st));
+    HIPCHK(ctx, launch_spmm_rowmajor((int)n, t, ctx->rpT.as<int>(), ctx->ciT.as<int>(), ctx->vaT.as<double>(),
+                                     ur.as<double>(), atu.as<double>(), st));
+    HIPCHK(ctx, launch_resid_cols(av.as<double>(), ctx->d_U.as<double>(), mpad, dsig.as<double>(), (int)m, t,
+                                  o1.as<double>(), st));
+    HIPCHK(ctx, launch_resid_cols(atu.as<double>(), ctx->d_V.as<double>(), npad, dsig.as<double>(), (int)n, t,
+                                  o2.as<double>(), st));
+    std::vector<double> h1(t), h2(t);
+    HIPCHK(ctx, hipMemcpyAsync(h1.data(), o1.p, sizeof(double) * t, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(h2.data(), o2.p, sizeof(double) * t, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    for (int c = 0; c < t; ++c) {
+      ctx->resid[c] = std::sqrt(std::max(h1[c], h2[c])) / (normA > 0 ? normA : 1.0);
+      info.max_triplet_resid = std::max(info.max_triplet_resid, ctx->resid[c]);
+    }
+  }
+  double t3 = now_ms();
+  info.iterations = J.iters;
+  info.iterations_total = R.iters_total;
+  info.t_hat = t;
+  info.converged = R.all_converged ? 1 : 0;
+  info.n_shift = S;
+  info.max_solve_resid_est = R.max_res_est;
+  info.t_solve_ms = R.t_solve_end - R.t_start;
+  info.t_lowrank_ms = t1 - t0;
+  info.t_qr_ms = t2 - t1;
+  info.t_extract_ms = t3 - t2;
+  info.t_total_ms = t3 - R.t_start;
+  info.window = J.h.W;
+  info.L_padded = J.h.Lp;
+  const double Lp = J.h.Lp;
+  int64_t nnz = ctx->nnz;
+  info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
+  info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + 4.0 * n);
+  info.window_bytes = 8.0 * J.h.W * L * n + 64.0 * S * L * n;
+  ctx->solved = true;
+  return CSVD_OK;
+}
+
+// Optional: true FP64 residual of every shifted solve, max over (shift, column)
+// of ||V - (z I - A^T A) Y|| / ||V||.
+int check_solves(SolveRun &R) {
+  csvd_ctx *ctx = R.ctx;
+  hipStream_t st = ctx->st;
+  Job &J = *R.job;
+  const int L = J.h.L, S = J.h.S;
+  const int64_t n = ctx->n, m = ctx->m;
+  DevBuf re, im, rowb, ub, gb;
+  HIPCHK(ctx, re.alloc(sizeof(double) * n * L));
+  HIPCHK(ctx, im.alloc(sizeof(double) * n * L));
+  HIPCHK(ctx, rowb.alloc(sizeof(double) * n * 2 * L));
+  HIPCHK(ctx, ub.alloc(sizeof(double) * m * 2 * L));
+  HIPCHK(ctx, gb.alloc(sizeof(double) * n * 2 * L));
+  std::vector<double> V((size_t)n * L), G((size_t)n * 2 * L), Yr((size_t)n * L), Yi((size_t)n * L);
+  HIPCHK(ctx, hipMemcpy2DAsync(V.data(), sizeof(double) * n, R.d_rhs.p, sizeof(double) * R.rhs_ld, sizeof(double) * n,
+                               L, hipMemcpyDeviceToHost, st));
+  double worst = 0;
+  for (int s = 0; s < S; ++s) {
+    HIPCHK(ctx, launch_get_solution(J.h, s, re.as<double>(), im.as<double>(), st));
+    // [Re | Im] as one row-major n x 2L block, formed on the host
+    HIPCHK(ctx, hipMemcpyAsync(Yr.data(), re.p, sizeof(double) * Yr.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(Yi.data(), im.p, sizeof(double) * Yi.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    std::vector<double> Yrow((size_t)n * 2 * L);
+    for (int64_t i = 0; i < n; ++i)
+      for (int l = 0; l < L; ++l) {
+        Yrow[(size_t)i * 2 * L + l] = Yr[(size_t)l * n + i];
+        Yrow[(size_t)i * 2 * L + L + l] = Yi[(size_t)l * n + i];
+      }
+    HIPCHK(ctx, hipMemcpyAsync(rowb.p, Yrow.data(), sizeof(double) * Yrow.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, launch_spmm_rowmajor((int)m, 2 * L, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
+                                     rowb.as<double>(), ub.as<double>(), st));
+    HIPCHK(ctx, launch_spmm_rowmajor((int)n, 2 * L, ctx->rpT.as<int>(), ctx->ciT.as<int>(), ctx->vaT.as<double>(),
+                                     ub.as<double>(), gb.as<double>(), st));
+    HIPCHK(ctx, hipMemcpyAsync(G.data(), gb.p, sizeof(double) * G.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    const double zr = R.spec.shift_re[s], zi = R.spec.shift_im[s];
+    for (int l = 0; l < L; ++l) {
+      double rn = 0, vn = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        const double yr = Yr[(size_t)l * n + i], yi = Yi[(size_t)l * n + i];
+        const double gr = G[(size_t)i * 2 * L + l], gi = G[(size_t)i * 2 * L + L + l];
+        const double v = V[(size_t)l * n + i];
+        const double rr = v - (zr * yr - zi * yi - gr);
+        const double ri = -(zr * yi + zi * yr - gi);
+        rn += rr * rr + ri * ri;
+        vn += v * v;
+      }
+      if (vn > 0) worst = std::max(worst, std::sqrt(rn / vn));
+    }
+  }
+  ctx->info.max_solve_resid_true = worst;
+  return CSVD_OK;
+}
+
+}  // namespace csvd
+
+// ============================================================================
+// ABI
+extern "C" {
+
+int csvd_params_default(csvd_params *p) {
+  if (!p) return CSVD_EINVAL;
+  std::memset(p, 0, sizeof(*p));
+  p->L = 16;
+  p->M = 8;
+  p->N = 32;
+  p->ell = 1;
+  p->delta = 1e-20;
+  p->alpha = 0.1;
+  p->transform = CSVD_PLAIN;
+  p->precision = CSVD_FP64;
+  p->solve_rtol = 1e-11;
+  p->max_iters = 1000000;
+  p->spurious_eps = 1e-12;
+  p->seed = 2109;
+  p->norm_a = 0.0;
+  p->window = 0;
+  p->check_solves = 0;
+  return CSVD_OK;
+}
+
+int csvd_create(csvd_ctx **out, int64_t m, int64_t n, int64_t nnz, const int32_t *rowptr, const int32_t *colidx,
+                const double *vals, int32_t on_device, void *hip_stream) {
+  if (!out) return CSVD_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<csvd_ctx> ctx(new csvd_ctx());
+  csvd_ctx *c = ctx.get();
+  if (n < 1 || m < n) return CSVD_EINVAL;
+  if (nnz < 0 || nnz >= (int64_t)1 << 31 || m >= (int64_t)1 << 31) return CSVD_EINVAL;
+  if (!rowptr || (nnz > 0 && (!colidx || !vals))) return CSVD_EINVAL;
+  c->m = m;
+  c->n = n;
+  c->nnz = nnz;
+  c->st = (hipStream_t)hip_stream;
+  if (!on_device) {
+    if (rowptr[0] != 0 || rowptr[m] != nnz) return CSVD_EINVAL;
+    for (int64_t i = 0; i < m; ++i) {
+      if (rowptr[i + 1] < rowptr[i]) return CSVD_EINVAL;
+      for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        if (colidx[k] < 0 || colidx[k] >= n) return CSVD_EINVAL;
+        if (k > rowptr[i] && colidx[k] <= colidx[k - 1]) return CSVD_EINVAL;
+        if (!std::isfinite(vals[k])) return CSVD_ENUMERIC;
+      }
+    }
+  }
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (c->rp.alloc(sizeof(int) * (m + 1)) || c->ci.alloc(sizeof(int) * std::max<int64_t>(nnz, 1)) ||
+      c->va.alloc(sizeof(double) * std::max<int64_t>(nnz, 1)) || c->rpT.alloc(sizeof(int) * (n + 1)) ||
+      c->ciT.alloc(sizeof(int) * std::max<int64_t>(nnz, 1)) || c->vaT.alloc(sizeof(double) * std::max<int64_t>(nnz, 1)) ||
+      c->work.alloc(sizeof(int) * (n + 8)))
+    return CSVD_ENOMEM;
+  if (hipMemcpyAsync(c->rp.p, rowptr, sizeof(int) * (m + 1), kind, c->st) != hipSuccess) return CSVD_EDEVICE;
+  if (nnz > 0) {
+    if (hipMemcpyAsync(c->ci.p, colidx, sizeof(int) * nnz, kind, c->st) != hipSuccess) return CSVD_EDEVICE;
+    if (hipMemcpyAsync(c->va.p, vals, sizeof(double) * nnz, kind, c->st) != hipSuccess) return CSVD_EDEVICE;
+  }
+  if (on_device) {
+    if (launch_check_csr((int)m, (int)n, c->rp.as<int>(), c->ci.as<int>(), c->va.as<double>(), (int)nnz,
+                         c->work.as<int>(), c->st) != hipSuccess)
+      return CSVD_EDEVICE;
+    int flags[3] = {0, 0, 0};
+    if (hipMemcpyAsync(flags, c->work.p, sizeof(flags), hipMemcpyDeviceToHost, c->st) != hipSuccess) return CSVD_EDEVICE;
+    if (hipStreamSynchronize(c->st) != hipSuccess) return CSVD_EDEVICE;
+    if (flags[0] || flags[1]) return CSVD_EINVAL;
+    if (flags[2]) return CSVD_ENUMERIC;
+  }
+  if (launch_csr_transpose((int)m, (int)n, (int)nnz, c->rp.as<int>(), c->ci.as<int>(), c->va.as<double>(),
+                           c->rpT.as<int>(), c->ciT.as<int>(), c->vaT.as<double>(), c->work.as<int>(),
+                           c->st) != hipSuccess)
+    return CSVD_EDEVICE;
+  if (hipStreamSynchronize(c->st) != hipSuccess) return CSVD_EDEVICE;
+  *out = ctx.release();
+  return CSVD_OK;
+}
+
+void csvd_destroy(csvd_ctx *ctx) { delete ctx; }
+
+const char *csvd_last_error(const csvd_ctx *ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p, const double *V_in) {
+  if (!ctx) return CSVD_EINVAL;
+  ctx->err.clear();
+  ctx->solved = false;
+  std::unique_ptr<SolveRun> R(new SolveRun());
+  const bool mixed = p && p->precision == CSVD_MIXED;
+  const int W = p ? pick_window(p) : 32;
+  int rc = run_begin(*R, ctx, a, b, p, V_in, W, mixed);
+  if (rc) return rc;
+  Engine eng(ctx->st, W, mixed);
+  HIPCHK(ctx, eng.init());
+  KernelTimer timer;
+  HIPCHK(ctx, eng.add(R->job.get()));
+  while (true) {
+    HIPCHK(ctx, eng.run_window(&timer, 64));
+    std::vector<Job *> fin;
+    HIPCHK(ctx, eng.collect(&fin));
+    if (!fin.empty()) {
+      bool more = false;
+      rc = run_after_round(*R, &more);
+      if (rc) return rc;
+      if (more) {
+        HIPCHK(ctx, eng.add(R->job.get()));
+        continue;
+      }
+      break;
+    }
+  }
+  rc = run_finalize(*R);
+  if (rc) return rc;
+  if (p->check_solves) {
+    rc = check_solves(*R);
+    if (rc) return rc;
+  }
+  double avg[3];
+  int64_t cnt[3];
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  timer.summarize(avg, cnt);
+  ctx->info.spmm_a_ms = avg[0];
+  ctx->info.spmm_at_ms = avg[1];
+  ctx->info.window_ms = avg[2];
+  ctx->info.spmm_samples = cnt[0];
+  ctx->job = std::move(R->job);
+  ctx->spec = R->spec;
+  ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
+  if (!ctx->info.converged) ctx->err = "shifted solves reached max_iters before solve_rtol";
+  return ctx->last_status;
+}
+
+int csvd_get_triplets(csvd_ctx *ctx, int64_t *t_hat, int64_t capacity, double *sigma, double *U, double *V,
+                      double *resid) {
+  if (!ctx || !t_hat) return CSVD_EINVAL;
+  if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
+  const int64_t t = (int64_t)ctx->sigma.size();
+  *t_hat = t;
+  if (capacity == 0) return CSVD_OK;
+  if (capacity < t) return set_err(ctx, CSVD_EINVAL, "capacity smaller than t_hat");
+  if (sigma) std::memcpy(sigma, ctx->sigma.data(), sizeof(double) * t);
+  if (resid) std::memcpy(resid, ctx->resid.data(), sizeof(double) * t);
+  if (t > 0 && U)
+    HIPCHK(ctx, hipMemcpy2DAsync(U, sizeof(double) * ctx->m, ctx->d_U.p, sizeof(double) * ctx->mpad,
+                                 sizeof(double) * ctx->m, t, hipMemcpyDeviceToHost, ctx->st));
+  if (t > 0 && V)
+    HIPCHK(ctx, hipMemcpy2DAsync(V, sizeof(double) * ctx->n, ctx->d_V.p, sizeof(double) * ctx->npad,
+                                 sizeof(double) * ctx->n, t, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
+
+int csvd_get_info(csvd_ctx *ctx, csvd_info *info) {
+  if (!ctx || !info) return CSVD_EINVAL;
+  if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
+  *info = ctx->info;
+  return CSVD_OK;
+}
+
+int csvd_get_moment(csvd_ctx *ctx, int32_t k, double *S_k) {
+  if (!ctx || !S_k) return CSVD_EINVAL;
+  if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
+  if (k < 0 || k > ctx->M) return set_err(ctx, CSVD_EINVAL, "moment index out of range");
+  const double *src = ctx->d_S.as<double>() + (size_t)k * ctx->L * ctx->npad;
+  HIPCHK(ctx, hipMemcpy2DAsync(S_k, sizeof(double) * ctx->n, src, sizeof(double) * ctx->npad, sizeof(double) * ctx->n,
+                               ctx->L, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
+
+int csvd_get_solution(csvd_ctx *ctx, int32_t j, double *Y_re, double *Y_im) {
+  if (!ctx || !Y_re || !Y_im) return CSVD_EINVAL;
+  if (!ctx->solved || !ctx->job) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
+  if (j < 0 || j >= ctx->S) return set_err(ctx, CSVD_EINVAL, "shift index out of range");
+  DevBuf re, im;
+  HIPCHK(ctx, re.alloc(sizeof(double) * ctx->n * ctx->L));
+  HIPCHK(ctx, im.alloc(sizeof(double) * ctx->n * ctx->L));
+  HIPCHK(ctx, launch_get_solution(ctx->job->h, j, re.as<double>(), im.as<double>(), ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(Y_re, re.p, sizeof(double) * ctx->n * ctx->L, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(Y_im, im.p, sizeof(double) * ctx->n * ctx->L, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
+
+int csvd_quadrature(double a, double b, const csvd_params *p, double *shift_re, double *shift_im, double *w_re,
+                    double *w_im, double *c_re, double *c_im) {
+  if (!p) return CSVD_EINVAL;
+  if (!(0.0 <= a && a < b) || p->N < 2 || p->N % 2 || p->M < 0 || !(p->alpha > 0)) return CSVD_EINVAL;
+  if (p->transform == CSVD_EXP && !(a > 0)) return CSVD_EINVAL;
+  SolveSpec s;
+  quadrature(a, b, p->N, p->M, p->alpha, p->transform, &s);
+  for (int j = 0; j < s.S; ++j) {
+    if (shift_re) shift_re[j] = s.shift_re[j];
+    if (shift_im) shift_im[j] = s.shift_im[j];
+    if (w_re) w_re[j] = s.c_re[(size_t)j * (p->M + 1)];
+    if (w_im) w_im[j] = s.c_im[(size_t)j * (p->M + 1)];
+  }
+  for (size_t i = 0; i < s.c_re.size(); ++i) {
+    if (c_re) c_re[i] = s.c_re[i];
+    if (c_im) c_im[i] = s.c_im[i];
+  }
+  return CSVD_OK;
+}
+
+int csvd_spmm(csvd_ctx *ctx, int32_t transpose, int64_t k, const double *X, double *Y) {
+  if (!ctx || !X || !Y || k < 1) return CSVD_EINVAL;
+  const int64_t rows_out = transpose ? ctx->n : ctx->m;
+  const int64_t rows_in = transpose ? ctx->m : ctx->n;
+  DevBuf xc, xr, yr, yc;
+  HIPCHK(ctx, xc.alloc(sizeof(double) * rows_in * k));
+  HIPCHK(ctx, xr.alloc(sizeof(double) * rows_in * k));
+  HIPCHK(ctx, yr.alloc(sizeof(double) * rows_out * k));
+  HIPCHK(ctx, yc.alloc(sizeof(double) * rows_out * k));
+  HIPCHK(ctx, hipMemcpyAsync(xc.p, X, sizeof(double) * rows_in * k, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(ctx, launch_col_to_row((int)rows_in, (int)k, xc.as<double>(), rows_in, xr.as<double>(), k, ctx->st));
+  if (transpose)
+    HIPCHK(ctx, launch_spmm_rowmajor((int)ctx->n, k, ctx->rpT.as<int>(), ctx->ciT.as<int>(), ctx->vaT.as<double>(),
+                                     xr.as<double>(), yr.as<double>(), ctx->st));
+  else
+    HIPCHK(ctx, launch_spmm_rowmajor((int)ctx->m, k, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
+                                     xr.as<double>(), yr.as<double>(), ctx->st));
+  HIPCHK(ctx, launch_row_to_col((int)rows_out, (int)k, yr.as<double>(), k, yc.as<double>(), rows_out, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(Y, yc.p, sizeof(double) * rows_out * k, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
+
+int csvd_dense_gemm(int64_t R, int64_t N, int64_t K, const double *A, const double *B, double *Cm) {
+  if (R < 1 || N < 1 || K < 1 || !A || !B || !Cm) return CSVD_EINVAL;
+  DevBuf a, b, c;
+  if (a.alloc(sizeof(double) * R * K) || b.alloc(sizeof(double) * K * N) || c.alloc(sizeof(double) * R * N))
+    return CSVD_ENOMEM;
+  if (hipMemcpy(a.p, A, sizeof(double) * R * K, hipMemcpyHostToDevice) != hipSuccess) return CSVD_EDEVICE;
+  if (hipMemcpy(b.p, B, sizeof(double) * K * N, hipMemcpyHostToDevice) != hipSuccess) return CSVD_EDEVICE;
+  if (launch_gemm((int)R, (int)N, (int)K, 1.0, a.as<double>(), R, b.as<double>(), K, 0.0, c.as<double>(), R,
+                  nullptr) != hipSuccess)
+    return CSVD_EDEVICE;
+  if (hipMemcpy(Cm, c.p, sizeof(double) * R * N, hipMemcpyDeviceToHost) != hipSuccess) return CSVD_EDEVICE;
+  return CSVD_OK;
+}
+
+int csvd_get_transpose(csvd_ctx *ctx, int32_t *rowptr, int32_t *colidx, double *vals) {
+  if (!ctx || !rowptr) return CSVD_EINVAL;
+  HIPCHK(ctx, hipMemcpyAsync(rowptr, ctx->rpT.p, sizeof(int) * (ctx->n + 1), hipMemcpyDeviceToHost, ctx->st));
+  if (ctx->nnz > 0 && colidx)
+    HIPCHK(ctx, hipMemcpyAsync(colidx, ctx->ciT.p, sizeof(int) * ctx->nnz, hipMemcpyDeviceToHost, ctx->st));
+  if (ctx->nnz > 0 && vals)
+    HIPCHK(ctx, hipMemcpyAsync(vals, ctx->vaT.p, sizeof(double) * ctx->nnz, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// Batched solves and the serving loop.
+extern "C" {
+
+int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, const double *b,
+                     const csvd_params *params, const double *const *V_in, int32_t *status) {
+  if (count < 1 || !ctxs || !a || !b || !params || !status) return CSVD_EINVAL;
+  for (int i = 0; i < count; ++i)
+    if (!ctxs[i]) return CSVD_EINVAL;
+  hipStream_t st = ctxs[0]->st;
+  const int W = pick_window(&params[0]);
+  const bool mixed = params[0].precision == CSVD_MIXED;
+  std::vector<std::unique_ptr<SolveRun>> runs(count);
+  std::map<Job *, int> owner;
+  Engine eng(st, W, mixed);
+  if (eng.init() != hipSuccess) return CSVD_EDEVICE;
+  for (int i = 0; i < count; ++i) {
+    status[i] = CSVD_OK;
+    ctxs[i]->err.clear();
+    ctxs[i]->solved = false;
+    if (ctxs[i]->st != st || (params[i].precision == CSVD_MIXED) != mixed || pick_window(&params[i]) != W) {
+      status[i] = set_err(ctxs[i], CSVD_EINVAL, "batched problems must share stream, precision and window");
+      continue;
+    }
+    runs[i].reset(new SolveRun());
+    int rc = run_begin(*runs[i], ctxs[i], a[i], b[i], &params[i], V_in ? V_in[i] : nullptr, W, mixed);
+    if (rc) {
+      status[i] = rc;
+      runs[i].reset();
+      continue;
+    }
+    owner[runs[i]->job.get()] = i;
+    if (eng.add(runs[i]->job.get()) != hipSuccess) return CSVD_EDEVICE;
+  }
+  while (eng.active() > 0) {
+    if (eng.run_window(nullptr, 0) != hipSuccess) return CSVD_EDEVICE;
+    std::vector<Job *> fin;
+    if (eng.collect(&fin) != hipSuccess) return CSVD_EDEVICE;
+    for (Job *j : fin) {
+      const int i = owner[j];
+      SolveRun &R = *runs[i];
+      bool more = false;
+      int rc = run_after_round(R, &more);
+      if (rc) {
+        status[i] = rc;
+        continue;
+      }
+      if (more) {
+        if (eng.add(j) != hipSuccess) return CSVD_EDEVICE;
+        continue;
+      }
+      rc = run_finalize(R);
+      if (!rc && R.spec.p.check_solves) rc = check_solves(R);
+      if (rc) {
+        status[i] = rc;
+        continue;
+      }
+      csvd_ctx *ctx = ctxs[i];
+      ctx->job = std::move(R.job);
+      ctx->spec = R.spec;
+      ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
+      status[i] = ctx->last_status;
+    }
+  }
+  return CSVD_OK;
+}
+
+}  // extern "C"
+
+struct csvd_server {
+  hipStream_t st = nullptr;
+  int64_t budget = 0;
+  int32_t max_batch = 0;
+  int64_t used = 0;
+  std::string err;
+  std::unique_ptr<Engine> eng[2];  // FP64, MIXED
+  struct Req {
+    csvd_ctx *ctx = nullptr;
+    double a = 0, b = 0;
+    csvd_params p{};
+    std::vector<double> V;
+    bool hasV = false;
+    int state = 0;  // 0 queued, 1 running, 2 done, 3 cancelled
+    int status = CSVD_OK;
+    int64_t bytes = 0;
+    std::unique_ptr<SolveRun> run;
+  };
+  std::map<int64_t, Req> reqs;
+  std::deque<int64_t> queue;
+  std::map<Job *, int64_t> owner;
+  int64_t next_id = 0;
+};
+
+static int64_t request_bytes(const csvd_ctx *ctx, const csvd_params *p) {
+  const int Lp = pad_L(p->L), S = p->N / 2, W = pick_window(p);
+  const int64_t npad = round_up(ctx->n, kRowPad), mpad = round_up(ctx->m, kRowPad);
+  const int64_t LM = (int64_t)p->L * p->M;
+  int64_t b = (int64_t)Job::bytes_needed(ctx->m, ctx->n, ctx->nnz, Lp, S, W, p->precision == CSVD_MIXED);
+  // moments + QR copy + V~ + A V~ (row and column) + triplet vectors
+  b += 8 * npad * (p->M + 1) * (int64_t)p->L + 8 * npad * LM * 2 + 8 * (mpad + ctx->m) * LM + 8 * ctx->n * LM;
+  b += 8 * (mpad + npad) * LM;
+  return b;
+}
+
+static int srv_err(csvd_server *s, int code, const std::string &m) {
+  if (s) s->err = m;
+  return code;
+}
+
+static int srv_admit(csvd_server *s) {
+  int running = 0;
+  for (auto &kv : s->reqs)
+    if (kv.second.state == 1) ++running;
+  while (!s->queue.empty() && running < s->max_batch) {
+    const int64_t id = s->queue.front();
+    auto &R = s->reqs[id];
+    if (s->used + R.bytes > s->budget) break;  // FIFO: wait for memory
+    s->queue.pop_front();
+    const bool mixed = R.p.precision == CSVD_MIXED;
+    Engine *e = s->eng[mixed ? 1 : 0].get();
+    R.run.reset(new SolveRun());
+    int rc = run_begin(*R.run, R.ctx, R.a, R.b, &R.p, R.hasV ? R.V.data() : nullptr, e->W(), mixed);
+    if (rc) {
+      R.state = 2;
+      R.status = rc;
+      R.run.reset();
+      continue;
+    }
+    s->used += R.bytes;
+    R.state = 1;
+    s->owner[R.run->job.get()] = id;
+    if (e->add(R.run->job.get()) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "engine add failed");
+    ++running;
+  }
+  return CSVD_OK;
+}
+
+static void srv_release(csvd_server *s, csvd_server::Req &R) {
+  s->used -= R.bytes;
+  for (auto it = s->owner.begin(); it != s->owner.end();) {
+    if (R.run && it->first == R.run->job.get()) it = s->owner.erase(it);
+    else ++it;
+  }
+}
+
+extern "C" {
+
+int csvd_server_create(csvd_server **srv, int64_t budget_bytes, int32_t max_batch, void *hip_stream) {
+  if (!srv || budget_bytes <= 0 || max_batch < 1) return CSVD_EINVAL;
+  std::unique_ptr<csvd_server> s(new csvd_server());
+  s->st = (hipStream_t)hip_stream;
+  s->budget = budget_bytes;
+  s->max_batch = max_batch;
+  for (int i = 0; i < 2; ++i) {
+    s->eng[i].reset(new Engine(s->st, 32, i == 1));
+    if (s->eng[i]->init() != hipSuccess) return CSVD_EDEVICE;
+  }
+  *srv = s.release();
+  return CSVD_OK;
+}
+
+int csvd_server_submit(csvd_server *s, csvd_ctx *ctx, double a, double b, const csvd_params *p, const double *V_in,
+                       int64_t *req) {
+  if (!s || !ctx || !p || !req) return CSVD_EINVAL;
+  int rc = check_params(ctx, a, b, p);
+  if (rc) return srv_err(s, rc, ctx->err);
+  if (pick_window(p) != 32) return srv_err(s, CSVD_EINVAL, "served requests use the server's window (0 or 32)");
+  if (ctx->st != s->st) return srv_err(s, CSVD_EINVAL, "context stream differs from the server stream");
+  const int64_t bytes = request_bytes(ctx, p);
+  if (bytes > s->budget) return srv_err(s, CSVD_ENOMEM, "request footprint exceeds the server budget");
+  const int64_t id = s->next_id++;
+  auto &R = s->reqs[id];
+  R.ctx = ctx;
+  R.a = a;
+  R.b = b;
+  R.p = *p;
+  R.bytes = bytes;
+  if (V_in) {
+    R.V.assign(V_in, V_in + (size_t)ctx->n * p->L);
+    R.hasV = true;
+  }
+  s->queue.push_back(id);
+  *req = id;
+  return CSVD_OK;
+}
+
+int csvd_server_step(csvd_server *s, int32_t steps, int32_t *n_active) {
+  if (!s) return CSVD_EINVAL;
+  int rc = srv_admit(s);
+  if (rc) return rc;
+  int done_steps = 0;
+  do {
+    bool any = false;
+    for (int ei = 0; ei < 2; ++ei) {
+      Engine &e = *s->eng[ei];
+      if (e.active() == 0) continue;
+      any = true;
+      if (e.run_window(nullptr, 0) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "window launch failed");
+      std::vector<Job *> fin;
+      if (e.collect(&fin) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "collect failed");
+      for (Job *j : fin) {
+        auto it = s->owner.find(j);
+        if (it == s->owner.end()) continue;
+        const int64_t rid = it->second;
+        auto &R = s->reqs[rid];
+        s->owner.erase(it);
+        bool more = false;
+        int r2 = run_after_round(*R.run, &more);
+        if (!r2 && more) {
+          s->owner[j] = rid;
+          if (e.add(j) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "engine add failed");
+          continue;
+        }
+        if (!r2) r2 = run_finalize(*R.run);
+        if (!r2 && R.p.check_solves) r2 = check_solves(*R.run);
+        if (!r2) {
+          R.ctx->job = std::move(R.run->job);
+          R.ctx->spec = R.run->spec;
+          R.ctx->last_status = R.ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
+          r2 = R.ctx->last_status;
+        }
+        R.status = r2;
+        R.state = 2;
+        srv_release(s, R);
+        R.run.reset();
+      }
+    }
+    rc = srv_admit(s);
+    if (rc) return rc;
+    if (!any) break;
+    done_steps += 32;
+  } while (done_steps < steps);
+  if (n_active) {
+    int na = 0;
+    for (auto &kv : s->reqs)
+      if (kv.second.state == 0 || kv.second.state == 1) ++na;
+    *n_active = na;
+  }
+  return CSVD_OK;
+}
+
+int csvd_server_poll(csvd_server *s, int64_t req, int32_t *done, int32_t *status) {
+  if (!s || !done) return CSVD_EINVAL;
+  auto it = s->reqs.find(req);
+  if (it == s->reqs.end()) return srv_err(s, CSVD_EINVAL, "unknown request id");
+  *done = it->second.state >= 2 ? 1 : 0;
+  if (status) *status = it->second.state == 3 ? CSVD_ESTATE : it->second.status;
+  return CSVD_OK;
+}
+
+int csvd_server_cancel(csvd_server *s, int64_t req) {
+  if (!s) return CSVD_EINVAL;
+  auto it = s->reqs.find(req);
+  if (it == s->reqs.end()) return srv_err(s, CSVD_EINVAL, "unknown request id");
+  auto &R = it->second;
+  if (R.state == 0) {
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), req), s->queue.end());
+  } else if (R.state == 1) {
+    for (int ei = 0; ei < 2; ++ei) s->eng[ei]->remove(R.run->job.get());
+    srv_release(s, R);
+    R.run.reset();
+  } else {
+    return CSVD_OK;
+  }
+  R.state = 3;
+  R.status = CSVD_ESTATE;
+  return CSVD_OK;
+}
+
+const char *csvd_server_last_error(const csvd_server *s) { return s ? s->err.c_str() : "null server"; }
+
+void csvd_server_destroy(csvd_server *s) { delete s; }
+
+}  // extern "C"

@@ -324,3 +324,54 @@ def serving_pool(count: int = 32, n_lo: float = 1e4, n_hi: float = 3e5, config: 
         inst.name = f"serve{i}_{m}x{n}"
         out.append(inst)
     return out
+
+
+def splitmix_normal(seed: int, n: int, L: int) -> np.ndarray:
+    """N(0,1) block (n x L, column-major) from the counter-based generator the
+    GPU library uses when it is given no V_in: SplitMix64 (Steele, Lea and
+    Flood, 2014), output k of the stream seeded with s being
+    mix(s + (k+1) * 0x9E3779B97F4A7C15); entry e (column-major) takes outputs
+    2e and 2e+1 as u1, u2 = top 53 bits / 2^53 and the Box-Muller value
+    sqrt(-2 ln(1 - u1)) cos(2 pi u2)."""
+    M64 = (1 << 64) - 1
+    g = 0x9E3779B97F4A7C15
+
+    def mix(z):
+        z = z & M64
+        z = ((z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)) & M64
+        z = ((z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)) & M64
+        return z ^ (z >> np.uint64(31))
+
+    count = n * L
+    e = np.arange(count, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        k1 = np.uint64(2) * e
+        z1 = np.uint64(seed) + (k1 + np.uint64(1)) * np.uint64(g)
+        z2 = np.uint64(seed) + (k1 + np.uint64(2)) * np.uint64(g)
+        u1 = (mix(z1) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        u2 = (mix(z2) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    x = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)
+    return np.asfortranarray(x.reshape(L, n).T)
+
+
+def interval_from_sample(m: int, n: int, nnz_per_col: int, count: int, scale: int = 25, config: int = 2,
+                         quantile: float = 0.5):
+    """Interval [a, b] expected to hold about ``count`` singular values of a
+    random sparse m x n matrix (k nonzeros per column, N(0,1)) around the
+    ``quantile`` of its spectrum.
+
+    The spectrum is read off a same-distribution instance of size
+    (m/scale) x (n/scale): dense eigenvalues of its A^T A give the quantile
+    lambda_q and the local eigenvalue density (eigenvalues per unit lambda in
+    a window of 5% of the spectrum around lambda_q); the full-size density is
+    ``scale`` times larger, so the interval in lambda is count / (scale *
+    density) wide.  Returns (a, b, lambda_q, density)."""
+    ms, ns = max(m // scale, 2), max(n // scale, 1)
+    I = random_sparse(ms, ns, nnz_per_col, config=config, instance=99)
+    A = I.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    lq = float(np.quantile(ev, quantile))
+    w = 0.05 * (ev[-1] - ev[0])
+    dens = np.sum(np.abs(ev - lq) <= w / 2) / w
+    width = count / (scale * dens)
+    return math.sqrt(lq - width / 2), math.sqrt(lq + width / 2), lq, dens
