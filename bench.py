@@ -117,6 +117,7 @@ def main():
         lat.append(time.perf_counter() - s0)
         info = cs.csvd_get_info(ctx)
         log(f"step {i}: {lat[-1]:.3f}s status {status[-1]} iters {info.iterations_total} t_hat {info.t_hat} "
+            f"rank {info.rank} sigma_s1 {info.sigma_s1:.3e} deflated {info.deflated} solver {info.solver} "
             f"max resid {info.max_triplet_resid:.2e}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()

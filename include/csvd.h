@@ -71,11 +71,22 @@ typedef struct {
                           /* tridiagonal; used to make residuals relative                */
   int32_t window;         /* Lanczos steps per basis window, 1..64 (0 -> automatic)      */
   int32_t check_solves;   /* 1: compute the true FP64 residual of every shifted solve    */
+  int32_t solver;         /* CSVD_SOLVER_BLOCK: one block Lanczos basis of width L (padded */
+                          /* to a power of two <= 64) for all shifts, two passes; needs   */
+                          /* CSVD_FP64 (else CSVD_EINVAL);                                 */
+                          /* CSVD_SOLVER_SINGLE: one Lanczos basis per column with        */
+                          /* windowed per-shift updates (any L <= 256);                    */
+                          /* CSVD_SOLVER_AUTO: BLOCK when it applies and n >= 64 x padded  */
+                          /* L (smaller matrices exhaust the block space in a few steps), */
+                          /* else SINGLE                                                  */
 } csvd_params;
+
+enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
 
 /* Fills *p with the paper's defaults: L=16, M=8, N=32, ell=1, delta=1e-20,
  * alpha=0.1, PLAIN, FP64, solve_rtol=1e-11, max_iters=1000000,
- * spurious_eps=1e-12, seed=2109, norm_a=0, window=0, check_solves=0. */
+ * spurious_eps=1e-12, seed=2109, norm_a=0, window=0, check_solves=0,
+ * solver=CSVD_SOLVER_AUTO. */
 int csvd_params_default(csvd_params *p);
 
 /* Creates a context holding a device copy of A in CSR form (and of A^T,
@@ -131,8 +142,11 @@ typedef struct {
   double  spmm_a_bytes;      /* algorithmic bytes of one A-product launch              */
   double  spmm_at_bytes;     /* algorithmic bytes of one A^T-product launch            */
   double  window_bytes;      /* algorithmic bytes of one window-apply launch           */
-  int32_t window;            /* Lanczos steps per window used                          */
+  int32_t window;            /* Lanczos steps per window used (0: block solver)        */
   int32_t L_padded;          /* block width used on the device                         */
+  int32_t solver;            /* solver that ran                                        */
+  int32_t deflated;          /* basis directions dropped from the newest block (block solver) */
+  double  rest_ms;           /* average duration of the rest of a block step (sampled) */
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);

@@ -23,12 +23,14 @@ __all__ = [
     "csvd_server_create", "csvd_server_submit", "csvd_server_step", "csvd_server_poll",
     "csvd_server_cancel", "csvd_server_last_error", "csvd_server_destroy",
     "CSVD_OK", "CSVD_EINVAL", "CSVD_ENOMEM", "CSVD_ENOTCONV", "CSVD_EDEVICE", "CSVD_ESTATE",
-    "CSVD_ENUMERIC", "CSVD_PLAIN", "CSVD_EXP", "CSVD_FP64", "CSVD_MIXED",
+    "CSVD_ENUMERIC", "CSVD_PLAIN", "CSVD_EXP", "CSVD_FP64", "CSVD_MIXED", "CSVD_SOLVER_AUTO",
+    "CSVD_SOLVER_BLOCK", "CSVD_SOLVER_SINGLE",
 ]
 
 CSVD_OK, CSVD_EINVAL, CSVD_ENOMEM, CSVD_ENOTCONV, CSVD_EDEVICE, CSVD_ESTATE, CSVD_ENUMERIC = 0, -1, -2, -3, -4, -5, -6
 CSVD_PLAIN, CSVD_EXP = 0, 1
 CSVD_FP64, CSVD_MIXED = 0, 1
+CSVD_SOLVER_AUTO, CSVD_SOLVER_BLOCK, CSVD_SOLVER_SINGLE = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(_HERE, "libcsvd.so")
@@ -41,7 +43,7 @@ class csvd_params(C.Structure):
         ("transform", C.c_int32), ("precision", C.c_int32),
         ("solve_rtol", C.c_double), ("max_iters", C.c_int32),
         ("spurious_eps", C.c_double), ("seed", C.c_uint64), ("norm_a", C.c_double),
-        ("window", C.c_int32), ("check_solves", C.c_int32),
+        ("window", C.c_int32), ("check_solves", C.c_int32), ("solver", C.c_int32),
     ]
 
 
@@ -56,7 +58,8 @@ class csvd_info(C.Structure):
         ("spmm_a_ms", C.c_double), ("spmm_at_ms", C.c_double), ("window_ms", C.c_double),
         ("spmm_samples", C.c_int64),
         ("spmm_a_bytes", C.c_double), ("spmm_at_bytes", C.c_double), ("window_bytes", C.c_double),
-        ("window", C.c_int32), ("L_padded", C.c_int32),
+        ("window", C.c_int32), ("L_padded", C.c_int32), ("solver", C.c_int32), ("deflated", C.c_int32),
+        ("rest_ms", C.c_double),
     ]
 
     def as_dict(self):

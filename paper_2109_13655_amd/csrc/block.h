@@ -1,0 +1,60 @@
+// Host side of the block Lanczos engine (see k_block.hip for the method).
+#pragma once
+
+#include <vector>
+
+#include "engine.h"
+
+namespace csvd {
+
+// One block Lanczos problem: device histories, work blocks and the pass
+// state.  Pass 1 builds the block tridiagonal matrix and monitors every
+// (shift, column) residual; pass 2 regenerates the basis and accumulates the
+// moments into Sout.
+struct BlockJob {
+  BJobDesc h{};
+  DevBuf mem, d_shift, d_cmom, d_desc, d_toff;
+  BBatch solo{};
+  int pass = 0;            // 0 idle, 1 building the basis, 2 accumulating moments, 3 done
+  int K = 0;               // block steps used by the solution
+  int Kcap = 0;
+  bool converged = false;
+  int64_t steps_total = 0; // over all passes and rounds
+  int64_t steps_last = 0;  // pass-1 steps of the last round
+  static size_t bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int Kcap, int L, int Kmom);
+  hipError_t create(const int *rp, const int *ci, const double *va, const int *rpT, const int *ciT,
+                    const double *vaT, int64_t m, int64_t n, int64_t nnz, int L, int Lp, int S, int Kcap, int Kmom,
+                    double tol, const std::vector<double> &sre, const std::vector<double> &sim,
+                    const std::vector<double> &cre, const std::vector<double> &cim, int cstride, hipStream_t st);
+  // copies the host descriptor to the device copy used by solo launches
+  hipError_t sync_desc(hipStream_t st);
+};
+
+class BEngine {
+ public:
+  explicit BEngine(hipStream_t st) : st_(st) {}
+  hipError_t init();
+  // starts pass 1 of a job whose Vpad and Sout are ready (runs its set-up)
+  hipError_t start(BlockJob *j);
+  // one block step of every running job
+  hipError_t step(KernelTimer *timer, bool sample);
+  // after a few steps: moves converged pass-1 jobs to pass 2 and reports
+  // jobs whose pass 2 is complete
+  hipError_t poll(std::vector<BlockJob *> *finished);
+  void remove(BlockJob *j);
+  size_t active() const { return p1_.size() + p2_.size(); }
+  int64_t clock() const { return clock_; }
+
+ private:
+  hipError_t rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &dt, BBatch &b);
+  hipError_t enter_pass2(BlockJob *j);
+  hipStream_t st_;
+  int64_t clock_ = 0;
+  DevBuf d_clock_;
+  std::vector<BlockJob *> p1_, p2_;
+  DevBuf dj1_, dt1_, dj2_, dt2_;
+  BBatch b1_{}, b2_{};
+  bool dirty1_ = true, dirty2_ = true;
+};
+
+}  // namespace csvd

@@ -13,6 +13,7 @@
 #include <string>
 #include <vector>
 
+#include "block.h"
 #include "engine.h"
 
 using namespace csvd;
@@ -33,6 +34,44 @@ int hip_code(hipError_t e) { return e == hipErrorOutOfMemory ? CSVD_ENOMEM : CSV
     if (_e != hipSuccess)                                                                              \
       return set_err((ctx), hip_code(_e), std::string("HIP error '") + hipGetErrorString(_e) + "' in " \
                                               + #expr);                                                \
+  } while (0)
+
+// Column blocks between a device array with leading dimension ld and a
+// contiguous host array (rows x cols, column-major).  Strided transfers go
+// through a packed device copy and a plain 1-D transfer.
+static int d2h_cols(csvd_ctx *ctx, double *host, const double *dev, int64_t ld, int64_t rows, int cols,
+                    hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return CSVD_OK;
+  const size_t bytes = sizeof(double) * (size_t)rows * cols;
+  if (ld == rows) {
+    HIPCHK(ctx, hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return CSVD_OK;
+  }
+  DevBuf tmp;
+  HIPCHK(ctx, tmp.alloc(bytes));
+  HIPCHK(ctx, launch_copy_block(dev, ld, tmp.as<double>(), rows, rows, cols, st));
+  HIPCHK(ctx, hipMemcpyAsync(host, tmp.p, bytes, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return CSVD_OK;
+}
+
+static int h2d_cols(csvd_ctx *ctx, double *dev, int64_t ld, const double *host, int64_t rows, int cols,
+                    hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return CSVD_OK;
+  const size_t bytes = sizeof(double) * (size_t)rows * cols;
+  DevBuf tmp;
+  HIPCHK(ctx, tmp.alloc(bytes));
+  HIPCHK(ctx, hipMemcpyAsync(tmp.p, host, bytes, hipMemcpyHostToDevice, st));
+  HIPCHK(ctx, launch_copy_block(tmp.as<double>(), rows, dev, ld, rows, cols, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return CSVD_OK;
+}
+
+#define XFER(expr)           \
+  do {                       \
+    const int _rc = (expr);  \
+    if (_rc) return _rc;     \
   } while (0)
 
 double now_ms() {
@@ -137,6 +176,8 @@ double tridiag_max_eig(const std::vector<double> &d, const std::vector<double> &
   return hi;
 }
 
+int pad_L(int L);
+
 int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
   if (!p) return set_err(ctx, CSVD_EINVAL, "params is NULL");
   if (!(std::isfinite(a) && std::isfinite(b)) || !(0.0 <= a && a < b))
@@ -159,6 +200,10 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
   if (p->max_iters < 1) return set_err(ctx, CSVD_EINVAL, "max_iters must be >= 1");
   if (p->window < 0 || p->window > kMaxWindow) return set_err(ctx, CSVD_EINVAL, "window must be 0..64");
   if (!(p->norm_a >= 0.0)) return set_err(ctx, CSVD_EINVAL, "norm_a must be >= 0");
+  if (p->solver != CSVD_SOLVER_AUTO && p->solver != CSVD_SOLVER_BLOCK && p->solver != CSVD_SOLVER_SINGLE)
+    return set_err(ctx, CSVD_EINVAL, "solver must be CSVD_SOLVER_AUTO, CSVD_SOLVER_BLOCK or CSVD_SOLVER_SINGLE");
+  if (p->solver == CSVD_SOLVER_BLOCK && (pad_L(p->L) > kBlockMaxLp || p->precision != CSVD_FP64))
+    return set_err(ctx, CSVD_EINVAL, "the block solver needs L <= 64 and CSVD_FP64");
   return CSVD_OK;
 }
 
@@ -171,6 +216,24 @@ int pad_L(int L) {
   int lp = 1;
   while (lp < L) lp <<= 1;
   return lp;
+}
+
+// the block solver needs the padded width within its LDS-staged kernels
+constexpr int kBlockPoll = 4;  // block steps between convergence polls
+
+// Automatic choice: the block basis only when the matrix has at least
+// kBlockMinRatio columns per basis column.  Below that a few block steps
+// exhaust the whole space, the new blocks are rounding noise that local
+// orthogonalization cannot separate from the old ones, and no deflation
+// threshold suits both well and badly conditioned spectra; the per-column
+// bases degrade gracefully there instead.
+constexpr int kBlockMinRatio = 64;
+
+bool use_block(const csvd_params *p, int64_t n) {
+  if (p->solver == CSVD_SOLVER_SINGLE) return false;
+  const bool fits = pad_L(p->L) <= kBlockMaxLp && p->precision == CSVD_FP64;
+  if (p->solver == CSVD_SOLVER_BLOCK) return fits;
+  return fits && n >= (int64_t)kBlockMinRatio * pad_L(p->L);
 }
 
 }  // namespace
@@ -186,14 +249,74 @@ struct SolveRun {
   DevBuf d_rhs;           // current right-hand side block, column-major
   int64_t rhs_ld = 0;
   DevBuf d_coef;          // S x (M+1) moment coefficients (double2)
-  std::unique_ptr<Job> job;
+  std::unique_ptr<Job> job;        // single-vector solver
+  bool block = false;
+  std::unique_ptr<BlockJob> bjob;  // block solver
+  std::vector<double> pad_cols;    // seeded padding columns of the block (n x (Lp - L), column-major)
+  DevBuf d_Stmp;                   // S_0 of the intermediate rounds (block solver)
   int64_t iters_total = 0;
+  int64_t iters_last = 0;
   bool all_converged = true;
   double max_res_est = 0.0;
   int status = CSVD_OK;
   double t_start = 0, t_solve_end = 0;
   std::vector<double> hist;  // column-0 Lanczos scalars of the first round
 };
+
+// ||A||_2 by power iteration on A^T A (60 products with one column); used to
+// make residuals relative when the caller gives no norm.  Cached per matrix.
+static int estimate_norm(csvd_ctx *ctx, double *out) {
+  if (ctx->norm_est > 0) {
+    *out = ctx->norm_est;
+    return CSVD_OK;
+  }
+  const int64_t n = ctx->n, m = ctx->m;
+  std::vector<double> x(n), y(n);
+  gaussian_block(0x6e6f726dULL, n, x.data());
+  DevBuf dx, du, dy;
+  HIPCHK(ctx, dx.alloc(8 * n));
+  HIPCHK(ctx, du.alloc(8 * m));
+  HIPCHK(ctx, dy.alloc(8 * n));
+  double lam = 0.0;
+  for (int it = 0; it < 60; ++it) {
+    double nx = 0;
+    for (double v : x) nx += v * v;
+    nx = std::sqrt(nx);
+    if (!(nx > 0)) break;
+    for (double &v : x) v /= nx;
+    HIPCHK(ctx, hipMemcpyAsync(dx.p, x.data(), 8 * n, hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(ctx, launch_spmm_rowmajor((int)m, 1, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
+                                     dx.as<double>(), du.as<double>(), ctx->st));
+    HIPCHK(ctx, launch_spmm_rowmajor((int)n, 1, ctx->rpT.as<int>(), ctx->ciT.as<int>(), ctx->vaT.as<double>(),
+                                     du.as<double>(), dy.as<double>(), ctx->st));
+    HIPCHK(ctx, hipMemcpyAsync(y.data(), dy.p, 8 * n, hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+    double r = 0;
+    for (int64_t i = 0; i < n; ++i) r += x[i] * y[i];
+    lam = std::max(lam, r);
+    x.swap(y);
+  }
+  ctx->norm_est = std::sqrt(std::max(lam, 0.0));
+  *out = ctx->norm_est;
+  return CSVD_OK;
+}
+
+// Uploads the padded starting block: columns 0..L-1 from V (column-major,
+// leading dimension ldv, host), padding columns from pad_cols.
+static int upload_vpad(SolveRun &R, const double *V, int64_t ldv) {
+  csvd_ctx *ctx = R.ctx;
+  BlockJob &B = *R.bjob;
+  const int64_t n = ctx->n;
+  const int L = B.h.L, Lp = B.h.Lp;
+  std::vector<double> Vp((size_t)n * Lp);
+  for (int64_t i = 0; i < n; ++i) {
+    for (int l = 0; l < L; ++l) Vp[(size_t)i * Lp + l] = V[(size_t)l * ldv + i];
+    for (int l = L; l < Lp; ++l) Vp[(size_t)i * Lp + l] = R.pad_cols[(size_t)(l - L) * n + i];
+  }
+  HIPCHK(ctx, hipMemcpyAsync(B.h.Vpad, Vp.data(), 8 * Vp.size(), hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
 
 int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params *p, const double *V_host,
               int W, bool mixed) {
@@ -229,6 +352,42 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
   }
   HIPCHK(ctx, R.d_coef.alloc(sizeof(double) * cc.size()));
   HIPCHK(ctx, hipMemcpyAsync(R.d_coef.p, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice, ctx->st));
+  R.block = use_block(p, ctx->n);
+  if (R.block) {
+    const int Lp = R.spec.Lp;
+    const int Kmom = (p->ell == 1) ? M + 1 : 1;
+    const int64_t kc = std::min<int64_t>(p->max_iters, (int64_t)std::ceil(3.5 * (double)n / Lp) + 32);
+    R.bjob.reset(new BlockJob());
+    HIPCHK(ctx, R.bjob->create(ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(), ctx->rpT.as<int>(),
+                               ctx->ciT.as<int>(), ctx->vaT.as<double>(), ctx->m, n, ctx->nnz, L, Lp, S, (int)kc,
+                               M + 1, p->solve_rtol, R.spec.shift_re, R.spec.shift_im, R.spec.c_re, R.spec.c_im,
+                               M + 1, ctx->st));
+    R.bjob->h.Kmom = Kmom;
+    // the deflation test of the basis is relative to ||A^T A||
+    double na = p->norm_a;
+    if (!(na > 0)) {
+      int rc1 = estimate_norm(ctx, &na);
+      if (rc1) return rc1;
+    }
+    R.bjob->h.dscale = na * na;
+    const int64_t npad = round_up(n, kRowPad);
+    HIPCHK(ctx, ctx->d_S.alloc(sizeof(double) * npad * (size_t)(M + 1) * L));
+    if (p->ell > 1) {
+      HIPCHK(ctx, R.d_Stmp.alloc(sizeof(double) * npad * (size_t)L));
+      R.bjob->h.Sout = R.d_Stmp.as<double>();
+    } else {
+      R.bjob->h.Sout = ctx->d_S.as<double>();
+    }
+    R.pad_cols.assign((size_t)n * (Lp - L), 0.0);
+    if (Lp > L) gaussian_block(p->seed ^ 0xA5A5F00DCAFEULL, (int64_t)R.pad_cols.size(), R.pad_cols.data());
+    int rc2 = upload_vpad(R, V.data(), n);
+    if (rc2) return rc2;
+    R.round = 0;
+    R.iters_total = 0;
+    R.all_converged = true;
+    R.max_res_est = 0;
+    return CSVD_OK;
+  }
   R.job.reset(new Job());
   HIPCHK(ctx, R.job->create(ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(), ctx->rpT.as<int>(),
                             ctx->ciT.as<int>(), ctx->vaT.as<double>(), ctx->m, n, ctx->nnz, L, R.spec.Lp, S, W, mixed,
@@ -269,7 +428,48 @@ static int harvest_job(SolveRun &R) {
 
 // Called when the job of the current round has finished.  Returns 1 in *more
 // when another round was started (the caller must re-add the job).
+static int run_after_round_block(SolveRun &R, bool *more) {
+  csvd_ctx *ctx = R.ctx;
+  BlockJob &B = *R.bjob;
+  const int S = B.h.S, Lp = B.h.Lp, L = B.h.L;
+  std::vector<double> res((size_t)S * Lp);
+  HIPCHK(ctx, hipMemcpyAsync(res.data(), B.h.res, sizeof(double) * res.size(), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  double mx = 0;
+  for (int s = 0; s < S; ++s)
+    for (int l = 0; l < L; ++l) mx = std::max(mx, res[(size_t)s * Lp + l]);
+  R.max_res_est = std::max(R.max_res_est, mx);
+  R.iters_total += B.K;
+  R.iters_last = B.K;
+  if (!B.converged) R.all_converged = false;
+  *more = false;
+  const csvd_params &p = R.spec.p;
+  if (R.round + 1 < p.ell) {
+    // eq. iter1: S_0^(nu) becomes the next right-hand side
+    const int64_t n = ctx->n, npad = B.h.npad;
+    std::vector<double> S0((size_t)npad * L);
+    HIPCHK(ctx, hipMemcpyAsync(S0.data(), B.h.Sout, sizeof(double) * S0.size(), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+    int rc = upload_vpad(R, S0.data(), npad);
+    if (rc) return rc;
+    // keep V for the solve check: the last round's right-hand side
+    std::vector<double> Vc((size_t)n * L);
+    for (int l = 0; l < L; ++l)
+      for (int64_t i = 0; i < n; ++i) Vc[(size_t)l * n + i] = S0[(size_t)l * npad + i];
+    HIPCHK(ctx, hipMemcpyAsync(R.d_rhs.p, Vc.data(), 8 * Vc.size(), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+    R.round += 1;
+    if (R.round + 1 == p.ell) {
+      B.h.Kmom = p.M + 1;
+      B.h.Sout = ctx->d_S.as<double>();
+    }
+    *more = true;
+  }
+  return CSVD_OK;
+}
+
 int run_after_round(SolveRun &R, bool *more) {
+  if (R.block) return run_after_round_block(R, more);
   csvd_ctx *ctx = R.ctx;
   int rc = harvest_job(R);
   if (rc) return rc;
@@ -312,7 +512,6 @@ int run_finalize(SolveRun &R) {
   const int L = p.L, M = p.M, S = R.spec.S;
   const int64_t m = ctx->m, n = ctx->n;
   const int64_t npad = round_up(n, kRowPad), mpad = round_up(m, kRowPad);
-  Job &J = *R.job;
   ctx->L = L;
   ctx->M = M;
   ctx->N = p.N;
@@ -321,10 +520,13 @@ int run_finalize(SolveRun &R) {
   ctx->mpad = mpad;
   csvd_info &info = ctx->info;
   std::memset(&info, 0, sizeof(info));
-  // ---- moments S_k, k = 0..M (step 2 and the extra moment of Sec. 3.4.1)
-  HIPCHK(ctx, ctx->d_S.alloc(sizeof(double) * npad * (size_t)(M + 1) * L));
-  HIPCHK(ctx, hipMemsetAsync(ctx->d_S.p, 0, ctx->d_S.bytes, st));
-  HIPCHK(ctx, launch_moments(J.h, R.d_coef.as<double2>(), M + 1, ctx->d_S.as<double>(), st));
+  // ---- moments S_k, k = 0..M (step 2 and the extra moment of Sec. 3.4.1);
+  // the block solver's second pass has already accumulated them
+  if (!R.block) {
+    HIPCHK(ctx, ctx->d_S.alloc(sizeof(double) * npad * (size_t)(M + 1) * L));
+    HIPCHK(ctx, hipMemsetAsync(ctx->d_S.p, 0, ctx->d_S.bytes, st));
+    HIPCHK(ctx, launch_moments(R.job->h, R.d_coef.as<double2>(), M + 1, ctx->d_S.as<double>(), st));
+  }
   HIPCHK(ctx, hipStreamSynchronize(st));
   R.t_solve_end = now_ms();
   double t0 = R.t_solve_end;
@@ -339,9 +541,7 @@ int run_finalize(SolveRun &R) {
   // R (LM x LM upper) to the host, R^T back as a column-major LMe x LMe block
   const int LMe = LM + (LM & 1);
   std::vector<double> Rh((size_t)LM * LM);
-  HIPCHK(ctx, hipMemcpy2DAsync(Rh.data(), sizeof(double) * LM, Xq.p, sizeof(double) * npad, sizeof(double) * LM, LM,
-                               hipMemcpyDeviceToHost, st));
-  HIPCHK(ctx, hipStreamSynchronize(st));
+  XFER(d2h_cols(ctx, Rh.data(), Xq.as<double>(), npad, LM, LM, st));
   std::vector<double> Rt((size_t)LMe * LMe, 0.0), Jm((size_t)LMe * LMe, 0.0);
   for (int c = 0; c < LM; ++c)
     for (int r = 0; r <= c; ++r) Rt[(size_t)r * LMe + c] = Rh[(size_t)c * LM + r];  // Rt[c, r] = R[r, c]
@@ -391,8 +591,7 @@ int run_finalize(SolveRun &R) {
     std::vector<double> Z((size_t)LM * r);
     for (int c = 0; c < r; ++c)
       for (int i = 0; i < LM; ++i) Z[(size_t)c * LM + i] = Jm[(size_t)perm[c] * LMe + i];
-    HIPCHK(ctx, hipMemcpy2DAsync(Vt.p, sizeof(double) * npad, Z.data(), sizeof(double) * LM, sizeof(double) * LM, r,
-                                 hipMemcpyHostToDevice, st));
+    XFER(h2d_cols(ctx, Vt.as<double>(), npad, Z.data(), LM, r, st));
     HIPCHK(ctx, launch_hh_apply(Xq.as<double>(), npad, (int)n, -LM, tau1.as<double>(), Vt.as<double>(), npad, r, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
   }
@@ -415,9 +614,7 @@ int run_finalize(SolveRun &R) {
     for (int j = 0; j + 1 < r; ++j) HIPCHK(ctx, launch_hh_step(Xa.as<double>(), mpad, (int)m, r, j, tau2.as<double>(), st));
     Bh.assign((size_t)r * r, 0.0);
     std::vector<double> Rb((size_t)r * r);
-    HIPCHK(ctx, hipMemcpy2DAsync(Rb.data(), sizeof(double) * r, Xa.p, sizeof(double) * mpad, sizeof(double) * r, r,
-                                 hipMemcpyDeviceToHost, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
+    XFER(d2h_cols(ctx, Rb.data(), Xa.as<double>(), mpad, r, r, st));
     for (int c = 0; c < r; ++c)
       for (int i = 0; i <= c; ++i) Bh[(size_t)c * r + i] = Rb[(size_t)c * r + i];
   }
@@ -468,11 +665,15 @@ int run_finalize(SolveRun &R) {
   HIPCHK(ctx, ctx->d_U.alloc(sizeof(double) * mpad * std::max(t, 1)));
   HIPCHK(ctx, ctx->d_V.alloc(sizeof(double) * npad * std::max(t, 1)));
   double normA = p.norm_a;
-  if (!(normA > 0)) {
+  if (!(normA > 0) && !R.block) {
     std::vector<double> d, e;
     for (size_t k = 0; k + 1 < R.hist.size(); k += 2) d.push_back(R.hist[k]);
     for (size_t k = 0; k + 1 < R.hist.size() && e.size() + 1 < d.size(); k += 2) e.push_back(R.hist[k + 1]);
     normA = std::sqrt(std::max(tridiag_max_eig(d, e), 0.0));
+  }
+  if (!(normA > 0)) {
+    rc = estimate_norm(ctx, &normA);
+    if (rc) return rc;
   }
   info.norm_a = normA;
   if (t > 0) {
@@ -495,8 +696,7 @@ int run_finalize(SolveRun &R) {
     HIPCHK(ctx, launch_gemm((int)npad, t, r, 1.0, Vt.as<double>(), npad, dQs.as<double>(), r, 0.0,
                             ctx->d_V.as<double>(), npad, st));
     HIPCHK(ctx, hipMemsetAsync(ctx->d_U.p, 0, ctx->d_U.bytes, st));
-    HIPCHK(ctx, hipMemcpy2DAsync(ctx->d_U.p, sizeof(double) * mpad, Ps.data(), sizeof(double) * r, sizeof(double) * r,
-                                 t, hipMemcpyHostToDevice, st));
+    XFER(h2d_cols(ctx, ctx->d_U.as<double>(), mpad, Ps.data(), r, t, st));
     HIPCHK(ctx, launch_hh_apply(Xa.as<double>(), mpad, (int)m, -r, tau2.as<double>(), ctx->d_U.as<double>(), mpad, t, st));
     HIPCHK(ctx, launch_sign_fix(ctx->d_U.as<double>(), mpad, (int)m, ctx->d_V.as<double>(), npad, (int)n, t, st));
     // residuals: ||A v - s u|| and ||A^T u - s v||
@@ -527,7 +727,7 @@ int run_finalize(SolveRun &R) {
     }
   }
   double t3 = now_ms();
-  info.iterations = J.iters;
+  info.iterations = R.block ? R.iters_last : R.job->iters;
   info.iterations_total = R.iters_total;
   info.t_hat = t;
   info.converged = R.all_converged ? 1 : 0;
@@ -538,13 +738,24 @@ int run_finalize(SolveRun &R) {
   info.t_qr_ms = t2 - t1;
   info.t_extract_ms = t3 - t2;
   info.t_total_ms = t3 - R.t_start;
-  info.window = J.h.W;
-  info.L_padded = J.h.Lp;
-  const double Lp = J.h.Lp;
+  info.window = R.block ? 0 : R.job->h.W;
+  info.L_padded = R.spec.Lp;
+  info.solver = R.block ? CSVD_SOLVER_BLOCK : CSVD_SOLVER_SINGLE;
+  const double Lp = R.spec.Lp;
   int64_t nnz = ctx->nnz;
-  info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
-  info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + 4.0 * n);
-  info.window_bytes = 8.0 * J.h.W * L * n + 64.0 * S * L * n;
+  if (R.block) {
+    // one A product: A, x gather (n x Lp), y write (m x Lp); one A^T product:
+    // A^T, u gather (m x Lp), w write (n x Lp)
+    info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
+    info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + n);
+    int fl = 0;
+    HIPCHK(ctx, hipMemcpy(&fl, R.bjob->h.flags, sizeof(int), hipMemcpyDeviceToHost));
+    info.deflated = fl;
+  } else {
+    info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
+    info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + 4.0 * n);
+    info.window_bytes = 8.0 * R.job->h.W * L * n + 64.0 * S * L * n;
+  }
   ctx->solved = true;
   return CSVD_OK;
 }
@@ -554,6 +765,7 @@ int run_finalize(SolveRun &R) {
 int check_solves(SolveRun &R) {
   csvd_ctx *ctx = R.ctx;
   hipStream_t st = ctx->st;
+  if (R.block) return CSVD_OK;  // the block solver keeps no per-shift solution vectors
   Job &J = *R.job;
   const int L = J.h.L, S = J.h.S;
   const int64_t n = ctx->n, m = ctx->m;
@@ -564,8 +776,7 @@ int check_solves(SolveRun &R) {
   HIPCHK(ctx, ub.alloc(sizeof(double) * m * 2 * L));
   HIPCHK(ctx, gb.alloc(sizeof(double) * n * 2 * L));
   std::vector<double> V((size_t)n * L), G((size_t)n * 2 * L), Yr((size_t)n * L), Yi((size_t)n * L);
-  HIPCHK(ctx, hipMemcpy2DAsync(V.data(), sizeof(double) * n, R.d_rhs.p, sizeof(double) * R.rhs_ld, sizeof(double) * n,
-                               L, hipMemcpyDeviceToHost, st));
+  XFER(d2h_cols(ctx, V.data(), R.d_rhs.as<double>(), R.rhs_ld, n, L, st));
   double worst = 0;
   for (int s = 0; s < S; ++s) {
     HIPCHK(ctx, launch_get_solution(J.h, s, re.as<double>(), im.as<double>(), st));
@@ -629,6 +840,7 @@ int csvd_params_default(csvd_params *p) {
   p->norm_a = 0.0;
   p->window = 0;
   p->check_solves = 0;
+  p->solver = CSVD_SOLVER_AUTO;
   return CSVD_OK;
 }
 
@@ -702,23 +914,45 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   const int W = p ? pick_window(p) : 32;
   int rc = run_begin(*R, ctx, a, b, p, V_in, W, mixed);
   if (rc) return rc;
-  Engine eng(ctx->st, W, mixed);
-  HIPCHK(ctx, eng.init());
   KernelTimer timer;
-  HIPCHK(ctx, eng.add(R->job.get()));
-  while (true) {
-    HIPCHK(ctx, eng.run_window(&timer, 64));
-    std::vector<Job *> fin;
-    HIPCHK(ctx, eng.collect(&fin));
-    if (!fin.empty()) {
-      bool more = false;
-      rc = run_after_round(*R, &more);
-      if (rc) return rc;
-      if (more) {
-        HIPCHK(ctx, eng.add(R->job.get()));
-        continue;
+  if (R->block) {
+    BEngine eng(ctx->st);
+    HIPCHK(ctx, eng.init());
+    HIPCHK(ctx, eng.start(R->bjob.get()));
+    int64_t step = 0;
+    while (true) {
+      for (int q = 0; q < kBlockPoll; ++q, ++step) HIPCHK(ctx, eng.step(&timer, (step % 8) == 3));
+      std::vector<BlockJob *> fin;
+      HIPCHK(ctx, eng.poll(&fin));
+      if (!fin.empty()) {
+        bool more = false;
+        rc = run_after_round(*R, &more);
+        if (rc) return rc;
+        if (more) {
+          HIPCHK(ctx, eng.start(R->bjob.get()));
+          continue;
+        }
+        break;
       }
-      break;
+    }
+  } else {
+    Engine eng(ctx->st, W, mixed);
+    HIPCHK(ctx, eng.init());
+    HIPCHK(ctx, eng.add(R->job.get()));
+    while (true) {
+      HIPCHK(ctx, eng.run_window(&timer, 64));
+      std::vector<Job *> fin;
+      HIPCHK(ctx, eng.collect(&fin));
+      if (!fin.empty()) {
+        bool more = false;
+        rc = run_after_round(*R, &more);
+        if (rc) return rc;
+        if (more) {
+          HIPCHK(ctx, eng.add(R->job.get()));
+          continue;
+        }
+        break;
+      }
     }
   }
   rc = run_finalize(*R);
@@ -733,7 +967,8 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   timer.summarize(avg, cnt);
   ctx->info.spmm_a_ms = avg[0];
   ctx->info.spmm_at_ms = avg[1];
-  ctx->info.window_ms = avg[2];
+  if (R->block) ctx->info.rest_ms = avg[2];
+  else ctx->info.window_ms = avg[2];
   ctx->info.spmm_samples = cnt[0];
   ctx->job = std::move(R->job);
   ctx->spec = R->spec;
@@ -752,12 +987,8 @@ int csvd_get_triplets(csvd_ctx *ctx, int64_t *t_hat, int64_t capacity, double *s
   if (capacity < t) return set_err(ctx, CSVD_EINVAL, "capacity smaller than t_hat");
   if (sigma) std::memcpy(sigma, ctx->sigma.data(), sizeof(double) * t);
   if (resid) std::memcpy(resid, ctx->resid.data(), sizeof(double) * t);
-  if (t > 0 && U)
-    HIPCHK(ctx, hipMemcpy2DAsync(U, sizeof(double) * ctx->m, ctx->d_U.p, sizeof(double) * ctx->mpad,
-                                 sizeof(double) * ctx->m, t, hipMemcpyDeviceToHost, ctx->st));
-  if (t > 0 && V)
-    HIPCHK(ctx, hipMemcpy2DAsync(V, sizeof(double) * ctx->n, ctx->d_V.p, sizeof(double) * ctx->npad,
-                                 sizeof(double) * ctx->n, t, hipMemcpyDeviceToHost, ctx->st));
+  if (t > 0 && U) XFER(d2h_cols(ctx, U, ctx->d_U.as<double>(), ctx->mpad, ctx->m, t, ctx->st));
+  if (t > 0 && V) XFER(d2h_cols(ctx, V, ctx->d_V.as<double>(), ctx->npad, ctx->n, t, ctx->st));
   HIPCHK(ctx, hipStreamSynchronize(ctx->st));
   return CSVD_OK;
 }
@@ -774,8 +1005,7 @@ int csvd_get_moment(csvd_ctx *ctx, int32_t k, double *S_k) {
   if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
   if (k < 0 || k > ctx->M) return set_err(ctx, CSVD_EINVAL, "moment index out of range");
   const double *src = ctx->d_S.as<double>() + (size_t)k * ctx->L * ctx->npad;
-  HIPCHK(ctx, hipMemcpy2DAsync(S_k, sizeof(double) * ctx->n, src, sizeof(double) * ctx->npad, sizeof(double) * ctx->n,
-                               ctx->L, hipMemcpyDeviceToHost, ctx->st));
+  XFER(d2h_cols(ctx, S_k, src, ctx->npad, ctx->n, ctx->L, ctx->st));
   HIPCHK(ctx, hipStreamSynchronize(ctx->st));
   return CSVD_OK;
 }
@@ -876,6 +1106,61 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
   hipStream_t st = ctxs[0]->st;
   const int W = pick_window(&params[0]);
   const bool mixed = params[0].precision == CSVD_MIXED;
+  if (use_block(&params[0], ctxs[0]->n)) {
+    std::vector<std::unique_ptr<SolveRun>> runs(count);
+    std::map<BlockJob *, int> owner;
+    BEngine eng(st);
+    if (eng.init() != hipSuccess) return CSVD_EDEVICE;
+    for (int i = 0; i < count; ++i) {
+      status[i] = CSVD_OK;
+      ctxs[i]->err.clear();
+      ctxs[i]->solved = false;
+      if (ctxs[i]->st != st || !use_block(&params[i], ctxs[i]->n)) {
+        status[i] = set_err(ctxs[i], CSVD_EINVAL, "batched problems must share the stream and the solver");
+        continue;
+      }
+      runs[i].reset(new SolveRun());
+      int rc = run_begin(*runs[i], ctxs[i], a[i], b[i], &params[i], V_in ? V_in[i] : nullptr, W, false);
+      if (rc) {
+        status[i] = rc;
+        runs[i].reset();
+        continue;
+      }
+      owner[runs[i]->bjob.get()] = i;
+      if (eng.start(runs[i]->bjob.get()) != hipSuccess) return CSVD_EDEVICE;
+    }
+    while (eng.active() > 0) {
+      for (int q = 0; q < kBlockPoll; ++q)
+        if (eng.step(nullptr, false) != hipSuccess) return CSVD_EDEVICE;
+      std::vector<BlockJob *> fin;
+      if (eng.poll(&fin) != hipSuccess) return CSVD_EDEVICE;
+      for (BlockJob *j : fin) {
+        const int i = owner[j];
+        SolveRun &R = *runs[i];
+        bool more = false;
+        int rc = run_after_round(R, &more);
+        if (rc) {
+          status[i] = rc;
+          continue;
+        }
+        if (more) {
+          if (eng.start(j) != hipSuccess) return CSVD_EDEVICE;
+          continue;
+        }
+        rc = run_finalize(R);
+        if (rc) {
+          status[i] = rc;
+          continue;
+        }
+        csvd_ctx *ctx = ctxs[i];
+        ctx->spec = R.spec;
+        ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
+        status[i] = ctx->last_status;
+        R.bjob.reset();  // free the basis histories early
+      }
+    }
+    return CSVD_OK;
+  }
   std::vector<std::unique_ptr<SolveRun>> runs(count);
   std::map<Job *, int> owner;
   Engine eng(st, W, mixed);
@@ -939,7 +1224,9 @@ struct csvd_server {
   int32_t max_batch = 0;
   int64_t used = 0;
   std::string err;
-  std::unique_ptr<Engine> eng[2];  // FP64, MIXED
+  std::unique_ptr<Engine> eng[2];  // single-vector solver: FP64, MIXED
+  std::unique_ptr<BEngine> beng;   // block solver
+  std::map<BlockJob *, int64_t> bowner;
   struct Req {
     csvd_ctx *ctx = nullptr;
     double a = 0, b = 0;
@@ -961,7 +1248,13 @@ static int64_t request_bytes(const csvd_ctx *ctx, const csvd_params *p) {
   const int Lp = pad_L(p->L), S = p->N / 2, W = pick_window(p);
   const int64_t npad = round_up(ctx->n, kRowPad), mpad = round_up(ctx->m, kRowPad);
   const int64_t LM = (int64_t)p->L * p->M;
-  int64_t b = (int64_t)Job::bytes_needed(ctx->m, ctx->n, ctx->nnz, Lp, S, W, p->precision == CSVD_MIXED);
+  int64_t b;
+  if (use_block(p, ctx->n)) {
+    const int64_t kc = std::min<int64_t>(p->max_iters, (int64_t)std::ceil(3.5 * (double)ctx->n / Lp) + 32);
+    b = (int64_t)BlockJob::bytes_needed(ctx->m, ctx->n, ctx->nnz, Lp, S, (int)kc, p->L, p->M + 1);
+  } else {
+    b = (int64_t)Job::bytes_needed(ctx->m, ctx->n, ctx->nnz, Lp, S, W, p->precision == CSVD_MIXED);
+  }
   // moments + QR copy + V~ + A V~ (row and column) + triplet vectors
   b += 8 * npad * (p->M + 1) * (int64_t)p->L + 8 * npad * LM * 2 + 8 * (mpad + ctx->m) * LM + 8 * ctx->n * LM;
   b += 8 * (mpad + npad) * LM;
@@ -994,8 +1287,13 @@ static int srv_admit(csvd_server *s) {
     }
     s->used += R.bytes;
     R.state = 1;
-    s->owner[R.run->job.get()] = id;
-    if (e->add(R.run->job.get()) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "engine add failed");
+    if (R.run->block) {
+      s->bowner[R.run->bjob.get()] = id;
+      if (s->beng->start(R.run->bjob.get()) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "engine start failed");
+    } else {
+      s->owner[R.run->job.get()] = id;
+      if (e->add(R.run->job.get()) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "engine add failed");
+    }
     ++running;
   }
   return CSVD_OK;
@@ -1007,6 +1305,26 @@ static void srv_release(csvd_server *s, csvd_server::Req &R) {
     if (R.run && it->first == R.run->job.get()) it = s->owner.erase(it);
     else ++it;
   }
+  for (auto it = s->bowner.begin(); it != s->bowner.end();) {
+    if (R.run && it->first == R.run->bjob.get()) it = s->bowner.erase(it);
+    else ++it;
+  }
+}
+
+// finishes a request whose solves are done: dense steps and bookkeeping
+static void srv_finish(csvd_server *s, csvd_server::Req &R) {
+  int r2 = run_finalize(*R.run);
+  if (!r2 && R.p.check_solves) r2 = check_solves(*R.run);
+  if (!r2) {
+    if (R.run->job) R.ctx->job = std::move(R.run->job);
+    R.ctx->spec = R.run->spec;
+    R.ctx->last_status = R.ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
+    r2 = R.ctx->last_status;
+  }
+  R.status = r2;
+  R.state = 2;
+  srv_release(s, R);
+  R.run.reset();
 }
 
 extern "C" {
@@ -1021,6 +1339,8 @@ int csvd_server_create(csvd_server **srv, int64_t budget_bytes, int32_t max_batc
     s->eng[i].reset(new Engine(s->st, 32, i == 1));
     if (s->eng[i]->init() != hipSuccess) return CSVD_EDEVICE;
   }
+  s->beng.reset(new BEngine(s->st));
+  if (s->beng->init() != hipSuccess) return CSVD_EDEVICE;
   *srv = s.release();
   return CSVD_OK;
 }
@@ -1057,6 +1377,34 @@ int csvd_server_step(csvd_server *s, int32_t steps, int32_t *n_active) {
   int done_steps = 0;
   do {
     bool any = false;
+    if (s->beng->active() > 0) {
+      any = true;
+      for (int q = 0; q < kBlockPoll; ++q)
+        if (s->beng->step(nullptr, false) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "block step failed");
+      std::vector<BlockJob *> fin;
+      if (s->beng->poll(&fin) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "block poll failed");
+      for (BlockJob *j : fin) {
+        auto it = s->bowner.find(j);
+        if (it == s->bowner.end()) continue;
+        const int64_t rid = it->second;
+        auto &R = s->reqs[rid];
+        bool more = false;
+        int r2 = run_after_round(*R.run, &more);
+        if (!r2 && more) {
+          if (s->beng->start(j) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "block start failed");
+          continue;
+        }
+        s->bowner.erase(it);
+        if (r2) {
+          R.status = r2;
+          R.state = 2;
+          srv_release(s, R);
+          R.run.reset();
+          continue;
+        }
+        srv_finish(s, R);
+      }
+    }
     for (int ei = 0; ei < 2; ++ei) {
       Engine &e = *s->eng[ei];
       if (e.active() == 0) continue;
@@ -1122,7 +1470,9 @@ int csvd_server_cancel(csvd_server *s, int64_t req) {
   if (R.state == 0) {
     s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), req), s->queue.end());
   } else if (R.state == 1) {
-    for (int ei = 0; ei < 2; ++ei) s->eng[ei]->remove(R.run->job.get());
+    if (R.run->block) s->beng->remove(R.run->bjob.get());
+    else
+      for (int ei = 0; ei < 2; ++ei) s->eng[ei]->remove(R.run->job.get());
     srv_release(s, R);
     R.run.reset();
   } else {

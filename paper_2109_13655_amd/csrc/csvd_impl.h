@@ -86,6 +86,79 @@ struct JobDesc {
 
 constexpr int kHist = 128;
 
+// ----------------------------------------------------------------------------
+// A device block-Lanczos job.  One real block Lanczos process on A^T A of
+// width Lp (the L right-hand sides plus seeded padding columns) serves every
+// shift; the per-shift block LU of (z I - T_k) monitors convergence, and a
+// second pass regenerates the basis to accumulate the moments.
+struct BJobDesc {
+  const int *rp, *ci;
+  const double *va;
+  const int *rpT, *ciT;
+  const double *vaT;
+  int m, n, Lp, lgLp, L, S, npad;
+  int G1, lgG1, E1, rpt1, tiles1;  // tiling of the A product (m rows)
+  int G2, lgG2, E2, rpt2, tiles2;  // tiling of the A^T product (n rows)
+  int rchunks;                     // row chunks of the tall-skinny kernels
+  int Kcap;                        // capacity of the per-step histories
+  int Kstop;                       // steps of the current pass that do work (later steps are no-ops)
+  int start_clock;                 // engine clock of step 0 of the current pass
+  int Kmom;                        // moments accumulated in pass 2
+  int cstride;                     // row stride of cmom (M + 1)
+  double tol;
+  double dscale;                   // ||A||^2 estimate: scale of the deflation test
+  double *U;                       // m x Lp
+  double *Q;                       // 3 x (n x Lp): slot (k mod 3) holds Q_k
+  double *W, *W2;                  // n x Lp work blocks
+  double *Vpad;                    // n x Lp: the padded starting block
+  double *gpart;                   // rchunks x Lp x Lp partial Gram matrices
+  double *G;                       // Lp x Lp reduced Gram (scratch)
+  double *R1, *R1inv;              // Lp x Lp scratch of CholeskyQR2
+  double *Ah, *Ch, *Bh, *Mh;       // (Kcap + 1) x Lp x Lp step histories
+  double2 *Hinv, *Zh;              // S x (Kcap + 1) x Lp x Lp
+  double2 *ctmp;                   // S x 2 x Lp x Lp complex scratch
+  double *res;                     // S x Lp residual estimates
+  int *active;                     // unconverged (shift, column) pairs after the last step
+  int *flags;                      // [0] deflated columns of the newest basis block
+  const double2 *shift;            // S shifts
+  const double2 *cmom;             // S x Kmom moment coefficients
+  double *beta0;                   // Lp column norms of Vpad
+  double *F;                       // Kcap x (Kmom L) x Lp moment coefficients (column-major per step)
+  double *Sout;                    // npad x (Kmom L) column-major moments
+};
+
+struct BBatch {
+  const BJobDesc *jobs;
+  int njob;
+  const int *toff1, *toff2, *toffr, *toffs;  // tiles of A, A^T, row chunks, shifts
+  int total1, total2, totalr, totals;
+  const int64_t *clock;
+};
+
+constexpr int kChunk = 256;      // rows per block of the tall-skinny kernels
+constexpr int kBlockMaxLp = 64;  // widest block of the block Lanczos engine
+constexpr double kDeflTol = 1e-7;  // relative size below which a new basis direction is deflated
+
+// buffer codes of the tall-skinny kernels
+enum BBuf { BQ_PREV = 0, BQ_CUR = 1, BQ_NEXT = 2, BW = 3, BW2 = 4, BVPAD = 5, BNONE = 6 };
+// small-matrix codes
+enum BMat { BM_BK_T = 0, BM_AK = 1, BM_AK_CK = 2, BM_R1INV = 3, BM_MK = 4, BM_MINIT = 5 };
+
+hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);
+hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st);
+// Y = Z - X S  (Z = BNONE: Y = X S); S chosen by code for the step
+hipError_t launch_b_rowmm(const BBatch &b, int X, int Z, int Y, int smat, hipStream_t st);
+// partial Gram X^T Y over row chunks, then reduction into dest (0: A_k sym,
+// 1: C_k, 2: G scratch)
+hipError_t launch_b_gram(const BBatch &b, int X, int Y, int dest, hipStream_t st);
+// Cholesky of G: mode 1 -> R1, R1inv; mode 2 -> M_k = R1inv R2inv, B_{k+1} =
+// R2 R1 (init = 1: M_init and B_0 instead)
+hipError_t launch_b_chol(const BBatch &b, int mode, int init, hipStream_t st);
+hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st);
+hipError_t launch_b_backsolve(const BJobDesc &hj, int K, hipStream_t st);
+hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st);
+hipError_t launch_b_tick(int64_t *clock, hipStream_t st);
+
 struct Ctx;  // defined in csvd.cpp
 
 // ----------------------------------------------------------------------------
@@ -139,8 +212,13 @@ hipError_t launch_hh_apply(const double *Xr, int64_t ldr, int rows, int j, const
 hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, double *V, int64_t ldv,
                               int vrows, int step, double tol, int *counter, hipStream_t st);
 hipError_t launch_col_norms(const double *A, int64_t lda, int rows, int cols, double *out, hipStream_t st);
+hipError_t launch_copy_block(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows, int cols,
+                             hipStream_t st);
 hipError_t launch_gemm(int R, int N, int K, double alpha, const double *A, int64_t lda, const double *B,
                        int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t st);
+// same with A stored transposed (element (r, k) at A[r * lda + k])
+hipError_t launch_gemm_ta(int R, int N, int K, double alpha, const double *A, int64_t lda, const double *B,
+                          int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t st);
 hipError_t launch_scale_cols(double *A, int64_t lda, int rows, int cols, const double *s, hipStream_t st);
 hipError_t launch_sign_fix(double *U, int64_t ldu, int urows, double *V, int64_t ldv, int vrows, int cols,
                            hipStream_t st);

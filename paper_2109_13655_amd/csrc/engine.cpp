@@ -13,29 +13,6 @@ static int ilog2(int x) {
   return l;
 }
 
-// Sparse-product tiling of one job side (rows of A or of A^T): G lane
-// groups split each row's nonzeros (about 16 nonzeros per lane group), E
-// thread slots per thread, rpt = 256 E / (Lp G) rows per tile; E shrinks
-// until there are enough tiles to fill the chip.
-struct Tiling {
-  int G, lgG, E, rpt, tiles;
-};
-
-static Tiling tiling_for(int64_t rows, int64_t nnz, int Lp) {
-  Tiling t{};
-  const double avg = rows > 0 ? (double)nnz / rows : 0.0;
-  t.G = 1;
-  while (t.G * Lp < kThreads && avg / t.G > 16.0) t.G *= 2;
-  t.lgG = ilog2(t.G);
-  t.E = 8;
-  while (t.E > 1 && rows * Lp * t.G / (kThreads * t.E) < 2048) t.E /= 2;
-  t.rpt = kThreads * t.E / (Lp * t.G);
-  t.tiles = (int)((rows + t.rpt - 1) / t.rpt);
-  return t;
-}
-
-
-
 size_t Job::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int W, bool mixed) {
   const int64_t npad = round_up(n, kRowPad);
   const int64_t nL = n * Lp;

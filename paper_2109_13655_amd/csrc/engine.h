@@ -3,6 +3,8 @@
 // context / server objects behind the C ABI.
 #pragma once
 
+#include <cstdlib>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -31,7 +33,17 @@ struct DevBuf {
       return e;
     }
     bytes = b;
+    if (poison_allocs()) return hipMemset(p, 0xFF, b);  // all-ones bytes: NaN doubles
     return hipSuccess;
+  }
+  // CSVD_POISON_ALLOC=1 fills every new buffer with NaN bytes so that a read
+  // of memory no kernel has written shows up in the results (debug aid)
+  static bool poison_allocs() {
+    static const bool on = [] {
+      const char *v = std::getenv("CSVD_POISON_ALLOC");
+      return v && v[0] == '1';
+    }();
+    return on;
   }
   void release() {
     if (p) (void)hipFree(p);
@@ -43,6 +55,35 @@ struct DevBuf {
     return static_cast<T *>(p);
   }
 };
+
+inline int ilog2i(int x) {
+  int l = 0;
+  while ((1 << l) < x) ++l;
+  return l;
+}
+
+// Sparse-product tiling of one job side (rows of A or of A^T): G lane
+// groups split each row's nonzeros (about 16 nonzeros per lane group), E
+// thread slots per thread, rpt = 256 E / (Lp G) rows per tile; E shrinks
+// until there are enough tiles to fill the chip.
+struct Tiling {
+  int G, lgG, E, rpt, tiles;
+};
+
+inline Tiling tiling_for(int64_t rows, int64_t nnz, int Lp) {
+  Tiling t{};
+  const double avg = rows > 0 ? (double)nnz / rows : 0.0;
+  t.G = 1;
+  while (t.G * Lp < kThreads && avg / t.G > 16.0) t.G *= 2;
+  t.lgG = ilog2i(t.G);
+  t.E = 8;
+  while (t.E > 1 && rows * Lp * t.G / (kThreads * t.E) < 2048) t.E /= 2;
+  t.rpt = kThreads * t.E / (Lp * t.G);
+  t.tiles = (int)((rows + t.rpt - 1) / t.rpt);
+  return t;
+}
+
+
 
 struct SolveSpec {
   double a = 0, b = 0;
@@ -132,7 +173,8 @@ struct csvd_ctx {
   csvd::DevBuf d_U, d_V;             // triplet vectors, mpad x t / npad x t
   std::vector<double> sigma, resid;  // t_hat
   csvd_info info{};
-  std::unique_ptr<csvd::Job> job;    // last round's job (solutions)
+  std::unique_ptr<csvd::Job> job;    // last round's job (solutions), single-vector solver
+  double norm_est = 0.0;             // cached ||A||_2 estimate
   csvd::SolveSpec spec;
 };
 

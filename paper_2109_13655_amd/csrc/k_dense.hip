@@ -11,6 +11,8 @@
 //   * FP64 MFMA GEMM (v_mfma_f64_16x16x4f64) for V-hat = V~ Q_sel.
 //   * Column norms, column scaling, sign normalisation and residual norms.
 // All reductions are fixed-order block trees, so results are reproducible.
+#include <algorithm>
+
 #include "csvd_impl.h"
 
 namespace csvd {
@@ -187,6 +189,25 @@ hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, d
 }
 
 // ------------------------------------------------------------ small helpers
+// dst[c * ldd + r] = src[c * lds + r] for r < rows, c < cols (column-major
+// blocks with different leading dimensions; replaces strided 2-D copies)
+__global__ __launch_bounds__(kThreads) void k_copy_block(const double *__restrict__ src, int64_t lds,
+                                                         double *__restrict__ dst, int64_t ldd, int64_t rows) {
+  const int c = blockIdx.y;
+  const GLB double *s = gp(src) + (int64_t)c * lds;
+  GLB double *d = gp(dst) + (int64_t)c * ldd;
+  for (int64_t r = (int64_t)blockIdx.x * kThreads + threadIdx.x; r < rows; r += (int64_t)gridDim.x * kThreads)
+    d[r] = s[r];
+}
+
+hipError_t launch_copy_block(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows, int cols,
+                             hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return hipSuccess;
+  const int gx = (int)std::min<int64_t>((rows + kThreads - 1) / kThreads, 1024);
+  hipLaunchKernelGGL(k_copy_block, dim3(gx, cols), dim3(kThreads), 0, st, src, lds, dst, ldd, rows);
+  return hipGetLastError();
+}
+
 __global__ __launch_bounds__(kThreads) void k_col_norms(const double *A, int64_t lda, int rows, double *out) {
   __shared__ double red[kThreads];
   const double *a = A + (int64_t)blockIdx.x * lda;
@@ -292,6 +313,8 @@ hipError_t launch_resid_cols(const double *X, const double *Y, int64_t ldy, cons
 // on the device with unit and random operands).
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// TA: A is given transposed in memory (element (r, k) at A[r * lda + k]).
+template <bool TA>
 __global__ __launch_bounds__(256) void k_gemm_mfma(int R, int N, int K, double alpha, const double *__restrict__ A,
                                                    int64_t lda, const double *__restrict__ B, int64_t ldb,
                                                    double beta, double *__restrict__ C, int64_t ldc) {
@@ -306,9 +329,15 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(int R, int N, int K, double a
     for (int b = 0; b < 2; ++b) acc[a][b] = (d4){0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += 16) {
     for (int e = t; e < 1024; e += 256) {
-      const int i = e & 63, kk = e >> 6;
-      const int gr = row0 + i, gk = k0 + kk;
-      As[kk][i] = (gr < R && gk < K) ? A[(int64_t)gk * lda + gr] : 0.0;
+      if (TA) {
+        const int kk = e & 15, i = e >> 4;
+        const int gr = row0 + i, gk = k0 + kk;
+        As[kk][i] = (gr < R && gk < K) ? A[(int64_t)gr * lda + gk] : 0.0;
+      } else {
+        const int i = e & 63, kk = e >> 6;
+        const int gr = row0 + i, gk = k0 + kk;
+        As[kk][i] = (gr < R && gk < K) ? A[(int64_t)gk * lda + gr] : 0.0;
+      }
       const int kb = e & 15, jb = e >> 4;
       const int gc = col0 + jb, gk2 = k0 + kb;
       Bs[kb][jb] = (gc < N && gk2 < K) ? B[(int64_t)gc * ldb + gk2] : 0.0;
@@ -345,7 +374,15 @@ hipError_t launch_gemm(int R, int N, int K, double alpha, const double *A, int64
                        double beta, double *C, int64_t ldc, hipStream_t st) {
   if (R <= 0 || N <= 0) return hipSuccess;
   dim3 g((R + 63) / 64, (N + 63) / 64);
-  hipLaunchKernelGGL(k_gemm_mfma, g, dim3(256), 0, st, R, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  hipLaunchKernelGGL(k_gemm_mfma<false>, g, dim3(256), 0, st, R, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_ta(int R, int N, int K, double alpha, const double *A, int64_t lda, const double *B,
+                          int64_t ldb, double beta, double *C, int64_t ldc, hipStream_t st) {
+  if (R <= 0 || N <= 0) return hipSuccess;
+  dim3 g((R + 63) / 64, (N + 63) / 64);
+  hipLaunchKernelGGL(k_gemm_mfma<true>, g, dim3(256), 0, st, R, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
   return hipGetLastError();
 }
 

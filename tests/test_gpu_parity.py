@@ -77,7 +77,8 @@ def test_solutions_and_moments_match_oracle(transform):
     say("solve small", I.m, I.n, "transform", transform)
     ctx = make_ctx(I)
     try:
-        p = cs.csvd_params_default(L=L, M=M, N=N, transform=transform, solve_rtol=1e-12, check_solves=1)
+        p = cs.csvd_params_default(L=L, M=M, N=N, transform=transform, solve_rtol=1e-12, check_solves=1,
+                                   solver=cs.CSVD_SOLVER_SINGLE)
         st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
         assert st == cs.CSVD_OK
         info = cs.csvd_get_info(ctx)
@@ -93,6 +94,55 @@ def test_solutions_and_moments_match_oracle(transform):
             Sk = cs.csvd_get_moment(ctx, k, I.n, L)
             scale = 2 * np.abs(c[:, k]).sum() * ymax
             assert np.linalg.norm(Sk - S_o[k]) <= 1e-9 * scale, (k, np.linalg.norm(Sk - S_o[k]), scale)
+    finally:
+        cs.csvd_destroy(ctx)
+
+
+@pytest.mark.parametrize("transform", [cs.CSVD_PLAIN, cs.CSVD_EXP])
+@pytest.mark.parametrize("L", [8, 5])
+def test_block_moments_match_oracle(transform, L):
+    """Block solver (one block Lanczos basis for all shifts, two passes):
+    moments S_0..S_M against the oracle's direct solves; L = 5 exercises the
+    seeded padding columns of the block."""
+    I = _small_problem()
+    M, N = 4, 16
+    V = synth.v_in(I.n, L, 3)
+    say("block moments", transform, L)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=L, M=M, N=N, transform=transform, solve_rtol=1e-12,
+                                   solver=cs.CSVD_SOLVER_BLOCK)
+        st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+        info = cs.csvd_get_info(ctx)
+        say("block steps", info.iterations, "Lp", info.L_padded, "deflated", info.deflated)
+        assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK
+        S_o, Y_o, shifts, c = method.filtered_moments(I, I.a, I.b, V, M, N, transform=transform)
+        ymax = max(np.linalg.norm(Y_o[j]) for j in range(N // 2))
+        for k in range(M + 1):
+            Sk = cs.csvd_get_moment(ctx, k, I.n, L)
+            scale = 2 * np.abs(c[:, k]).sum() * ymax
+            assert np.linalg.norm(Sk - S_o[k]) <= 1e-9 * scale, (k, np.linalg.norm(Sk - S_o[k]), scale)
+    finally:
+        cs.csvd_destroy(ctx)
+
+
+def test_block_and_single_solvers_agree():
+    """Both solvers give the same triplets on the same problem."""
+    I = _small_problem()
+    V = synth.v_in(I.n, 8, 12)
+    ctx = make_ctx(I)
+    try:
+        out = []
+        for solver in (cs.CSVD_SOLVER_BLOCK, cs.CSVD_SOLVER_SINGLE):
+            p = cs.csvd_params_default(L=8, M=4, N=16, ell=2, norm_a=1.0, solver=solver)
+            cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+            out.append(cs.csvd_get_triplets(ctx, I.m, I.n))
+        (s1, U1, V1, r1), (s2, U2, V2, r2) = out
+        assert s1.size == s2.size > 0
+        np.testing.assert_allclose(s1, s2, rtol=1e-10)
+        assert r1.max() <= 1e-8 and r2.max() <= 1e-8
+        for i in range(s1.size):
+            assert abs(abs(V1[:, i] @ V2[:, i]) - 1.0) < 1e-8
     finally:
         cs.csvd_destroy(ctx)
 
@@ -223,6 +273,37 @@ def test_random_sparse_vs_dense_truth(L, M):
         cs.csvd_destroy(ctx)
 
 
+@pytest.mark.parametrize("L", [12, 16])
+def test_block_random_sparse_vs_dense_truth(L):
+    """The automatic choice takes the block basis once n >= 64 x padded L:
+    random sparse 4000 x 2048, interval of about 10 values mid-spectrum."""
+    I = synth.random_sparse(4000, 2048, 7, config=84)
+    A = I.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    a, b = synth.interval_by_count(ev, 1024, 10)
+    s_o, U_o, V_o, sall = truth.dense_truth(I, a, b)
+    V = synth.v_in(I.n, L, 6)
+    say("block random sparse L", L)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=L, M=4, N=32, solve_rtol=1e-12)
+        st = cs.csvd_solve_interval(ctx, a, b, p, V)
+        info = cs.csvd_get_info(ctx)
+        say("block steps", info.iterations, "deflated", info.deflated)
+        assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+        o = method.ss_svd(I, a, b, V, L, 4, 32)
+        assert sig.size == o["sigma"].size
+        np.testing.assert_allclose(sig, o["sigma"], rtol=1e-9)
+        assert o["sigma"].size == s_o.size
+        np.testing.assert_allclose(sig, s_o, rtol=1e-9)
+        r_host = truth.triplet_residuals(I, sig, U, Vv, normA=sall[0])
+        assert r_host.max() <= 1e-8
+        assert truth.subspace_gap(Vv, V_o) <= 1e-6
+    finally:
+        cs.csvd_destroy(ctx)
+
+
 def test_empty_interval_and_determinism():
     I = _small_problem()
     V = synth.v_in(I.n, 4, 6)
@@ -308,9 +389,11 @@ def _three_problems():
     return out
 
 
-def test_batch_equals_solo_bitwise():
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_SINGLE, cs.CSVD_SOLVER_BLOCK])
+def test_batch_equals_solo_bitwise(solver):
     probs = _three_problems()
-    p = cs.csvd_params_default(L=8, M=2, N=16)
+    p = cs.csvd_params_default(L=8, M=2, N=16, solver=solver)
+    say("batch solver", solver)
     solo = []
     ctxs = [make_ctx(I) for I, _, _ in probs]
     try:
@@ -330,9 +413,11 @@ def test_batch_equals_solo_bitwise():
             cs.csvd_destroy(c)
 
 
-def test_server_results_match_solo_and_cancel():
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_SINGLE, cs.CSVD_SOLVER_BLOCK])
+def test_server_results_match_solo_and_cancel(solver):
     probs = _three_problems()
-    p = cs.csvd_params_default(L=8, M=2, N=16)
+    p = cs.csvd_params_default(L=8, M=2, N=16, solver=solver)
+    say("server solver", solver)
     ctxs = [make_ctx(I) for I, _, _ in probs]
     solo_ctx = [make_ctx(I) for I, _, _ in probs]
     srv = cs.csvd_server_create(8 << 30, 2)
