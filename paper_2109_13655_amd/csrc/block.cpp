@@ -10,13 +10,13 @@ namespace csvd {
 size_t BlockJob::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int Kcap, int L, int Kmom) {
   (void)nnz;
   const int64_t L2 = (int64_t)Lp * Lp;
-  const int64_t rchunks = (n + kChunk - 1) / kChunk;
+  const int64_t nvb = std::min<int64_t>((n + kBlockPanel - 1) / kBlockPanel, kBlockMaxVB);
   size_t b = 0;
   b += 8 * (size_t)(m * Lp);                       // U
-  b += 8 * (size_t)(6 * n * Lp);                   // Q ring, W, W2, Vpad
-  b += 8 * (size_t)(rchunks * L2);                 // partial Gram matrices
-  b += 8 * (size_t)(3 * L2);                       // G, R1, R1inv
-  b += 8 * (size_t)(4 * (Kcap + 1) * L2);          // A, C, B, M histories
+  b += 8 * (size_t)(5 * n * Lp);                   // Q ring, W, Vpad
+  b += 8 * (size_t)(nvb * 2 * L2);                 // partial Gram matrices
+  b += 8 * (size_t)(7 * L2);                       // reduced Gram matrices, R1, R1^-1, T
+  b += 8 * (size_t)(4 * (Kcap + 1) * L2);          // A, B, M, N histories
   b += 16 * (size_t)(2 * S * (Kcap + 1) * L2);     // Hinv, Z histories
   b += 16 * (size_t)(2 * S * L2);                  // complex scratch
   b += 8 * (size_t)(S * Lp) + 8 * Lp + 16 * 4;     // res, beta0, counters
@@ -50,7 +50,8 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   const Tiling t1 = tiling_for(m, nnz, Lp), t2 = tiling_for(n, nnz, Lp);
   J.G1 = t1.G; J.lgG1 = t1.lgG; J.E1 = t1.E; J.rpt1 = t1.rpt; J.tiles1 = t1.tiles;
   J.G2 = t2.G; J.lgG2 = t2.lgG; J.E2 = t2.E; J.rpt2 = t2.rpt; J.tiles2 = t2.tiles;
-  J.rchunks = (int)((n + kChunk - 1) / kChunk);
+  J.nchunk = (int)((n + kBlockPanel - 1) / kBlockPanel);
+  J.nvb = std::min(J.nchunk, kBlockMaxVB);
   J.Kcap = Kcap;
   J.Kmom = Kmom;
   J.cstride = cstride;
@@ -58,16 +59,14 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.U = (double *)take(8 * (size_t)(m * Lp));
   J.Q = (double *)take(8 * (size_t)(3 * n * Lp));
   J.W = (double *)take(8 * (size_t)(n * Lp));
-  J.W2 = (double *)take(8 * (size_t)(n * Lp));
   J.Vpad = (double *)take(8 * (size_t)(n * Lp));
-  J.gpart = (double *)take(8 * (size_t)(J.rchunks * L2));
-  J.G = (double *)take(8 * L2);
-  J.R1 = (double *)take(8 * L2);
-  J.R1inv = (double *)take(8 * L2);
+  J.gpart = (double *)take(8 * (size_t)(J.nvb * 2 * L2));
+  J.red = (double *)take(8 * 4 * L2);
+  J.scr = (double *)take(8 * 3 * L2);
   J.Ah = (double *)take(8 * (size_t)((Kcap + 1) * L2));
-  J.Ch = (double *)take(8 * (size_t)((Kcap + 1) * L2));
   J.Bh = (double *)take(8 * (size_t)((Kcap + 1) * L2));
   J.Mh = (double *)take(8 * (size_t)((Kcap + 1) * L2));
+  J.Nh = (double *)take(8 * (size_t)((Kcap + 1) * L2));
   J.Hinv = (double2 *)take(16 * (size_t)(S * (Kcap + 1) * L2));
   J.Zh = (double2 *)take(16 * (size_t)(S * (Kcap + 1) * L2));
   J.ctmp = (double2 *)take(16 * (size_t)(2 * S * L2));
@@ -104,7 +103,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   if (e != hipSuccess) return e;
   e = d_toff.alloc(sizeof(int) * 8);
   if (e != hipSuccess) return e;
-  const int toff[8] = {0, J.tiles1, 0, J.tiles2, 0, J.rchunks, 0, S};
+  const int toff[8] = {0, J.tiles1, 0, J.tiles2, 0, J.nvb, 0, S};
   e = hipMemcpyAsync(d_toff.p, toff, sizeof(toff), hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   int *dt = d_toff.as<int>();
@@ -116,7 +115,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   solo.toffs = dt + 6;
   solo.total1 = J.tiles1;
   solo.total2 = J.tiles2;
-  solo.totalr = J.rchunks;
+  solo.totalr = J.nvb;
   solo.totals = S;
   return hipStreamSynchronize(st);  // host vectors are temporaries
 }
@@ -131,7 +130,31 @@ hipError_t BlockJob::sync_desc(hipStream_t st) {
 hipError_t BEngine::init() {
   hipError_t e = d_clock_.alloc(sizeof(int64_t));
   if (e != hipSuccess) return e;
-  return hipMemsetAsync(d_clock_.p, 0, sizeof(int64_t), st_);
+  if ((e = d_sclock_.alloc(sizeof(int64_t))) != hipSuccess) return e;
+  if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&ev_, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(d_clock_.p, 0, sizeof(int64_t), st_)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(d_sclock_.p, 0, sizeof(int64_t), st_)) != hipSuccess) return e;
+  return hipStreamSynchronize(st_);
+}
+
+BEngine::~BEngine() {
+  if (side_) {
+    (void)hipStreamSynchronize(side_);
+    (void)hipStreamDestroy(side_);
+  }
+  if (ev_) (void)hipEventDestroy(ev_);
+}
+
+// the shift recurrences of the current step on the side stream, after the
+// main stream has produced B_{k+1} (init: the starting Z_0 = B_0)
+hipError_t BEngine::launch_shift(const BBatch &b, int init) {
+  hipError_t e = hipEventRecord(ev_, st_);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(side_, ev_, 0)) != hipSuccess) return e;
+  BBatch bs = b;
+  bs.clock = d_sclock_.as<int64_t>();
+  return launch_b_shift(bs, init, side_);
 }
 
 // CholeskyQR2 of Vpad gives Q_0 and R_0 = B_0; Z_0 = R_0 for every shift.
@@ -150,13 +173,14 @@ hipError_t BEngine::start(BlockJob *j) {
   if (e != hipSuccess) return e;
   BBatch b = j->solo;
   b.clock = d_clock_.as<int64_t>();
-  if ((e = launch_b_gram(b, BVPAD, BVPAD, 2, st_)) != hipSuccess) return e;
-  if ((e = launch_b_chol(b, 1, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_b_rowmm(b, BVPAD, BNONE, BW, BM_R1INV, st_)) != hipSuccess) return e;
-  if ((e = launch_b_gram(b, BW, BW, 2, st_)) != hipSuccess) return e;
-  if ((e = launch_b_chol(b, 2, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_b_rowmm(b, BVPAD, BNONE, BQ_CUR, BM_MINIT, st_)) != hipSuccess) return e;
-  if ((e = launch_b_shift(b, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_tall(b, 1, 1, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_reduce(b, 0, 2, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_small1(b, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_tall(b, 2, 1, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_reduce(b, 1, 1, 3, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_small2(b, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_gamma(b, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_shift(b, 1)) != hipSuccess) return e;
   p1_.push_back(j);
   dirty1_ = true;
   return hipSuccess;
@@ -175,13 +199,16 @@ hipError_t BEngine::enter_pass2(BlockJob *j) {
   if ((e = j->sync_desc(st_)) != hipSuccess) return e;
   BBatch b = j->solo;
   b.clock = d_clock_.as<int64_t>();
-  if ((e = launch_b_rowmm(b, BVPAD, BNONE, BQ_CUR, BM_MINIT, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_gamma(b, 1, st_)) != hipSuccess) return e;
   p2_.push_back(j);
   dirty2_ = true;
   return hipSuccess;
 }
 
 hipError_t BEngine::rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &dt, BBatch &b) {
+  // the side stream may still read the old tables
+  hipError_t es = hipStreamSynchronize(side_);
+  if (es != hipSuccess) return es;
   const int nj = (int)jobs.size();
   std::vector<BJobDesc> descs(nj);
   std::vector<int> toff(4 * (nj + 1), 0);
@@ -190,7 +217,7 @@ hipError_t BEngine::rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &d
     descs[i] = jobs[i]->h;
     t1[i + 1] = t1[i] + descs[i].tiles1;
     t2[i + 1] = t2[i] + descs[i].tiles2;
-    tr[i + 1] = tr[i] + descs[i].rchunks;
+    tr[i + 1] = tr[i] + descs[i].nvb;
     ts[i + 1] = ts[i] + descs[i].S;
   }
   if (dj.bytes < sizeof(BJobDesc) * std::max(nj, 1)) {
@@ -237,18 +264,16 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
     if (timer && sample) timer->end(st_);
     if (timer && sample) timer->begin(2, st_);
-    if ((e = launch_b_rowmm(b, BQ_PREV, BW, BW, BM_BK_T, st_)) != hipSuccess) return e;
-    if ((e = launch_b_gram(b, BQ_CUR, BW, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_b_rowmm(b, BQ_CUR, BW, BW2, BM_AK, st_)) != hipSuccess) return e;
-    if ((e = launch_b_gram(b, BQ_CUR, BW2, 1, st_)) != hipSuccess) return e;
-    if ((e = launch_b_rowmm(b, BQ_CUR, BW, BW2, BM_AK_CK, st_)) != hipSuccess) return e;
-    if ((e = launch_b_gram(b, BW2, BW2, 2, st_)) != hipSuccess) return e;
-    if ((e = launch_b_chol(b, 1, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_b_rowmm(b, BW2, BNONE, BW, BM_R1INV, st_)) != hipSuccess) return e;
-    if ((e = launch_b_gram(b, BW, BW, 2, st_)) != hipSuccess) return e;
-    if ((e = launch_b_chol(b, 2, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_b_rowmm(b, BW2, BNONE, BQ_NEXT, BM_MK, st_)) != hipSuccess) return e;
-    if ((e = launch_b_shift(b, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_tall(b, 0, 1, 0, st_)) != hipSuccess) return e;   // W', P
+    if ((e = launch_bs_reduce(b, 0, 1, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_tall(b, 1, 1, 0, st_)) != hipSuccess) return e;   // C, G2
+    if ((e = launch_bs_reduce(b, 0, 2, 1, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_small1(b, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_tall(b, 2, 1, 0, st_)) != hipSuccess) return e;   // G3
+    if ((e = launch_bs_reduce(b, 1, 1, 3, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_small2(b, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_gamma(b, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_shift(b, 0)) != hipSuccess) return e;
     if (timer && sample) timer->end(st_);
   }
   if (!p2_.empty()) {
@@ -270,12 +295,12 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     }
     if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
-    if ((e = launch_b_rowmm(b, BQ_PREV, BW, BW, BM_BK_T, st_)) != hipSuccess) return e;
-    if ((e = launch_b_rowmm(b, BQ_CUR, BW, BW2, BM_AK_CK, st_)) != hipSuccess) return e;
-    if ((e = launch_b_rowmm(b, BW2, BNONE, BQ_NEXT, BM_MK, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_tall(b, 0, 0, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_gamma(b, 0, st_)) != hipSuccess) return e;
   }
   if (p1_.empty() && p2_.empty()) return hipSuccess;
   if ((e = launch_b_tick(d_clock_.as<int64_t>(), st_)) != hipSuccess) return e;
+  if ((e = launch_b_tick(d_sclock_.as<int64_t>(), side_)) != hipSuccess) return e;
   ++clock_;
   for (BlockJob *j : p1_) j->steps_total++;
   for (BlockJob *j : p2_) j->steps_total++;
@@ -287,9 +312,12 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
   // pass-1 jobs: unconverged pairs after their last step
   const int n1 = (int)p1_.size();
   std::vector<int> act(n1, 1);
+  // the active counts are written on the side stream
+  if ((e = hipStreamSynchronize(side_)) != hipSuccess) return e;
   for (int i = 0; i < n1; ++i) {
     const BJobDesc &J = p1_[i]->h;
-    const int klast = (int)(clock_ - 1 - J.start_clock);
+    // the newest step whose recurrences ran (none run past Kstop)
+    const int klast = std::min((int)(clock_ - 1 - J.start_clock), J.Kstop - 1);
     if (klast < 0) continue;
     e = hipMemcpyAsync(&act[i], J.active + (klast & 1), sizeof(int), hipMemcpyDeviceToHost, st_);
     if (e != hipSuccess) return e;
@@ -326,6 +354,9 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
 }
 
 void BEngine::remove(BlockJob *j) {
+  // the caller frees the job next: no launch may still use it
+  (void)hipStreamSynchronize(side_);
+  (void)hipStreamSynchronize(st_);
   auto r = [&](std::vector<BlockJob *> &v, bool &dirty) {
     auto it = std::find(v.begin(), v.end(), j);
     if (it != v.end()) {

@@ -30,9 +30,15 @@ struct BlockJob {
   hipError_t sync_desc(hipStream_t st);
 };
 
+// The per-shift recurrences (b_shift) of step k depend only on A_k, B_k and
+// B_{k+1}, so they run on a second stream and overlap the next steps; that
+// stream has its own copy of the step clock.
 class BEngine {
  public:
   explicit BEngine(hipStream_t st) : st_(st) {}
+  ~BEngine();
+  BEngine(const BEngine &) = delete;
+  BEngine &operator=(const BEngine &) = delete;
   hipError_t init();
   // starts pass 1 of a job whose Vpad and Sout are ready (runs its set-up)
   hipError_t start(BlockJob *j);
@@ -48,9 +54,12 @@ class BEngine {
  private:
   hipError_t rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &dt, BBatch &b);
   hipError_t enter_pass2(BlockJob *j);
+  hipError_t launch_shift(const BBatch &b, int init);
   hipStream_t st_;
+  hipStream_t side_ = nullptr;
+  hipEvent_t ev_ = nullptr;
   int64_t clock_ = 0;
-  DevBuf d_clock_;
+  DevBuf d_clock_, d_sclock_;
   std::vector<BlockJob *> p1_, p2_;
   DevBuf dj1_, dt1_, dj2_, dt2_;
   BBatch b1_{}, b2_{};

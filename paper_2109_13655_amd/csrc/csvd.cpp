@@ -229,11 +229,14 @@ constexpr int kBlockPoll = 4;  // block steps between convergence polls
 // bases degrade gracefully there instead.
 constexpr int kBlockMinRatio = 64;
 
+// the block basis is at least one MFMA tile wide
+int block_Lp(int L) { return std::max(kBlockMinLp, pad_L(L)); }
+
 bool use_block(const csvd_params *p, int64_t n) {
   if (p->solver == CSVD_SOLVER_SINGLE) return false;
   const bool fits = pad_L(p->L) <= kBlockMaxLp && p->precision == CSVD_FP64;
   if (p->solver == CSVD_SOLVER_BLOCK) return fits;
-  return fits && n >= (int64_t)kBlockMinRatio * pad_L(p->L);
+  return fits && n >= (int64_t)kBlockMinRatio * block_Lp(p->L);
 }
 
 }  // namespace
@@ -329,7 +332,7 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
   R.spec.b = b;
   R.spec.p = *p;
   quadrature(a, b, p->N, p->M, p->alpha, p->transform, &R.spec);
-  R.spec.Lp = pad_L(p->L);
+  R.spec.Lp = use_block(p, ctx->n) ? block_Lp(p->L) : pad_L(p->L);
   R.spec.W = W;
   const int S = R.spec.S, M = p->M, L = p->L;
   const int64_t n = ctx->n;
@@ -1250,8 +1253,9 @@ static int64_t request_bytes(const csvd_ctx *ctx, const csvd_params *p) {
   const int64_t LM = (int64_t)p->L * p->M;
   int64_t b;
   if (use_block(p, ctx->n)) {
-    const int64_t kc = std::min<int64_t>(p->max_iters, (int64_t)std::ceil(3.5 * (double)ctx->n / Lp) + 32);
-    b = (int64_t)BlockJob::bytes_needed(ctx->m, ctx->n, ctx->nnz, Lp, S, (int)kc, p->L, p->M + 1);
+    const int bLp = block_Lp(p->L);
+    const int64_t kc = std::min<int64_t>(p->max_iters, (int64_t)std::ceil(3.5 * (double)ctx->n / bLp) + 32);
+    b = (int64_t)BlockJob::bytes_needed(ctx->m, ctx->n, ctx->nnz, bLp, S, (int)kc, p->L, p->M + 1);
   } else {
     b = (int64_t)Job::bytes_needed(ctx->m, ctx->n, ctx->nnz, Lp, S, W, p->precision == CSVD_MIXED);
   }

@@ -99,7 +99,8 @@ struct BJobDesc {
   int m, n, Lp, lgLp, L, S, npad;
   int G1, lgG1, E1, rpt1, tiles1;  // tiling of the A product (m rows)
   int G2, lgG2, E2, rpt2, tiles2;  // tiling of the A^T product (n rows)
-  int rchunks;                     // row chunks of the tall-skinny kernels
+  int nchunk;                      // 64-row chunks of the tall kernels
+  int nvb;                         // workgroups per tall kernel (each walks chunks vb, vb + nvb, ...)
   int Kcap;                        // capacity of the per-step histories
   int Kstop;                       // steps of the current pass that do work (later steps are no-ops)
   int start_clock;                 // engine clock of step 0 of the current pass
@@ -109,12 +110,12 @@ struct BJobDesc {
   double dscale;                   // ||A||^2 estimate: scale of the deflation test
   double *U;                       // m x Lp
   double *Q;                       // 3 x (n x Lp): slot (k mod 3) holds Q_k
-  double *W, *W2;                  // n x Lp work blocks
+  double *W;                       // n x Lp work block
   double *Vpad;                    // n x Lp: the padded starting block
-  double *gpart;                   // rchunks x Lp x Lp partial Gram matrices
-  double *G;                       // Lp x Lp reduced Gram (scratch)
-  double *R1, *R1inv;              // Lp x Lp scratch of CholeskyQR2
-  double *Ah, *Ch, *Bh, *Mh;       // (Kcap + 1) x Lp x Lp step histories
+  double *gpart;                   // nvb x 2 x Lp x Lp partial Gram matrices
+  double *red;                     // 4 x Lp x Lp reduced Gram matrices (P, C, G2, G3)
+  double *scr;                     // 3 x Lp x Lp: R1, R1^-1, T of the current step
+  double *Ah, *Bh, *Mh, *Nh;       // (Kcap + 1) x Lp x Lp step histories
   double2 *Hinv, *Zh;              // S x (Kcap + 1) x Lp x Lp
   double2 *ctmp;                   // S x 2 x Lp x Lp complex scratch
   double *res;                     // S x Lp residual estimates
@@ -135,25 +136,27 @@ struct BBatch {
   const int64_t *clock;
 };
 
-constexpr int kChunk = 256;      // rows per block of the tall-skinny kernels
-constexpr int kBlockMaxLp = 64;  // widest block of the block Lanczos engine
-constexpr double kDeflTol = 1e-7;  // relative size below which a new basis direction is deflated
-
-// buffer codes of the tall-skinny kernels
-enum BBuf { BQ_PREV = 0, BQ_CUR = 1, BQ_NEXT = 2, BW = 3, BW2 = 4, BVPAD = 5, BNONE = 6 };
-// small-matrix codes
-enum BMat { BM_BK_T = 0, BM_AK = 1, BM_AK_CK = 2, BM_R1INV = 3, BM_MK = 4, BM_MINIT = 5 };
+constexpr int kBlockMaxLp = 64;   // widest block of the block Lanczos engine
+constexpr int kBlockMinLp = 16;   // narrowest (MFMA tile width)
+constexpr int kBlockPanel = 64;   // rows per chunk of the tall kernels
+constexpr int kBlockMaxVB = 256;  // workgroups per job in the tall kernels
+constexpr double kDeflTol = 1e-10;  // relative size below which a new basis direction is deflated
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);
 hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st);
-// Y = Z - X S  (Z = BNONE: Y = X S); S chosen by code for the step
-hipError_t launch_b_rowmm(const BBatch &b, int X, int Z, int Y, int smat, hipStream_t st);
-// partial Gram X^T Y over row chunks, then reduction into dest (0: A_k sym,
-// 1: C_k, 2: G scratch)
-hipError_t launch_b_gram(const BBatch &b, int X, int Y, int dest, hipStream_t st);
-// Cholesky of G: mode 1 -> R1, R1inv; mode 2 -> M_k = R1inv R2inv, B_{k+1} =
-// R2 R1 (init = 1: M_init and B_0 instead)
-hipError_t launch_b_chol(const BBatch &b, int mode, int init, hipStream_t st);
+// Tall kernels of one block step (see k_bstep.hip).  mode 0 (alpha): W' =
+// W - Q_{k-1} B_k^T and (grams = 1) the partial Gram matrix Q_k^T W'; mode 1
+// (beta): partial Gram matrices of W2 = W' - Q_k P; mode 2 (gamma0): partial
+// Gram matrix of Y = W' R1^-1 - Q_k T; init = 1 takes Vpad for W' and no Q_k.
+// gamma: Q_{k+1} = W' M_k - Q_k N_k (init = 1: Q_0 = Vpad M_init).
+hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st);
+hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st);
+// reduction of nm partial Gram matrices from slot m0 into red slots d0.. (fixed order)
+hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, hipStream_t st);
+// small1: A_k, first Cholesky, R1^-1, T.  small2: second Cholesky, M_k, N_k,
+// B_{k+1} (init = 1: M_init and B_0)
+hipError_t launch_bs_small1(const BBatch &b, int init, hipStream_t st);
+hipError_t launch_bs_small2(const BBatch &b, int init, hipStream_t st);
 hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st);
 hipError_t launch_b_backsolve(const BJobDesc &hj, int K, hipStream_t st);
 hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st);

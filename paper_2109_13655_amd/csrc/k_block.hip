@@ -1,12 +1,12 @@
-// Block Lanczos kernels for gfx950 (Algorithm 1/2, steps 1-2).
+// Block Lanczos kernels for gfx950 (Algorithm 1/2, steps 1-2): the sparse
+// products, the per-shift recurrences and the moment coefficients.  The
+// orthogonalisation of each new block lives in k_bstep.hip.
 //
 // One real block Lanczos process on G = A^T A of width Lp (the L right-hand
 // sides plus seeded padding columns) spans the block Krylov space of every
 // shifted system (z I - G) Y = V, since G and V are real.  Step k:
-//   W   = A^T (A Q_k) - Q_{k-1} B_k^T
-//   A_k = sym(Q_k^T W),  C_k = Q_k^T (W - Q_k A_k)       (CGS2 against Q_k)
-//   W2  = W - Q_k (A_k + C_k)
-//   W2  = Q_{k+1} B_{k+1}                                 (CholeskyQR2)
+//   W = A^T (A Q_k) - Q_{k-1} B_k^T,  A_k = sym(Q_k^T W),
+//   W - Q_k A_k (after reorthogonalisation) = Q_{k+1} B_{k+1}
 // and for every shift z the block LU of (z I - T_k) without pivoting
 //   H_k = z I - A_k - B_k H_{k-1}^{-1} B_k^T,  Z_{k+1} = B_{k+1} H_k^{-1} Z_k
 // (Im H_k is positive definite, so every H_k is invertible) gives the
@@ -115,287 +115,6 @@ hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st) {
 hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(b_spmm_at, dim3(bgrid(b.total2, 4096)), dim3(kThreads), 0, st, b.jobs, b.njob, b.toff2, b.total2,
                      b.clock);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------ buffer selection
-__device__ __forceinline__ GLB double *bbuf(const BJobDesc &J, int code, int k) {
-  const int64_t nL = (int64_t)J.n * J.Lp;
-  switch (code) {
-    case BQ_PREV: return gp(J.Q) + (int64_t)((k + 2) % 3) * nL;
-    case BQ_CUR: return gp(J.Q) + (int64_t)(k % 3) * nL;
-    case BQ_NEXT: return gp(J.Q) + (int64_t)((k + 1) % 3) * nL;
-    case BW: return gp(J.W);
-    case BW2: return gp(J.W2);
-    case BVPAD: return gp(J.Vpad);
-    default: return nullptr;
-  }
-}
-
-// S(c, col) staged row-major in LDS (stride Lp)
-__device__ void stage_small(const BJobDesc &J, int code, int k, double *Ssh) {
-  const int Lp = J.Lp, L2 = Lp * Lp;
-  const int64_t hk = (int64_t)k * L2;
-  for (int e = threadIdx.x; e < L2; e += kThreads) {
-    const int c = e / Lp, col = e - c * Lp;
-    double v;
-    switch (code) {
-      case BM_BK_T: v = gp(J.Bh)[hk + (int64_t)col * Lp + c]; break;
-      case BM_AK: v = gp(J.Ah)[hk + e]; break;
-      case BM_AK_CK: v = gp(J.Ah)[hk + e] + gp(J.Ch)[hk + e]; break;
-      case BM_R1INV: v = gp(J.R1inv)[e]; break;
-      case BM_MK: v = gp(J.Mh)[hk + e]; break;
-      default: v = gp(J.Mh)[(int64_t)J.Kcap * L2 + e]; break;  // BM_MINIT
-    }
-    Ssh[e] = v;
-  }
-}
-
-// ------------------------------------------------------------ row products
-// Y = Z - X S (or Y = X S), rows of one chunk; thread = (row of the group, col).
-__global__ __launch_bounds__(kThreads) void b_rowmm(const BJobDesc *__restrict__ jobs, int njob,
-                                                    const int *__restrict__ toff, const int64_t *__restrict__ clock,
-                                                    int Xc, int Zc, int Yc, int smat) {
-  __shared__ double Ssh[kBlockMaxLp * kBlockMaxLp];
-  __shared__ double Xs[kThreads];
-  const int g = blockIdx.x;
-  const int j = bfind(toff, njob, g);
-  const BJobDesc &J = jobs[j];
-  const int k = (int)(*clock - J.start_clock);
-  if (k >= J.Kstop) return;
-  const int chunk = g - toff[j];
-  const int Lp = J.Lp, lg = J.lgLp;
-  stage_small(J, smat, k, Ssh);
-  // Z may alias Y (in-place update): each thread reads Z[e] before writing Y[e]
-  const GLB double *__restrict__ X = bbuf(J, Xc, k);
-  const GLB double *Z = bbuf(J, Zc, k);
-  GLB double *Y = bbuf(J, Yc, k);
-  const int t = threadIdx.x;
-  const int col = t & (Lp - 1);
-  const int rl = t >> lg;              // row inside the group
-  const int rpg = kThreads >> lg;      // rows per group
-  const int64_t r0 = (int64_t)chunk * kChunk;
-  int64_t r1 = r0 + kChunk;
-  if (r1 > J.n) r1 = J.n;
-  __syncthreads();
-  for (int64_t rb = r0; rb < r1; rb += rpg) {
-    const int64_t row = rb + rl;
-    Xs[t] = (row < r1) ? X[(row << lg) + col] : 0.0;
-    __syncthreads();
-    if (row < r1) {
-      double acc = 0.0;
-      const double *xr = Xs + (rl << lg);
-      for (int c = 0; c < Lp; ++c) acc = fma(xr[c], Ssh[(c << lg) + col], acc);
-      const int64_t e = (row << lg) + col;
-      Y[e] = (Z ? Z[e] : 0.0) - (Z ? acc : -acc);
-    }
-    __syncthreads();
-  }
-}
-
-hipError_t launch_b_rowmm(const BBatch &b, int X, int Z, int Y, int smat, hipStream_t st) {
-  hipLaunchKernelGGL(b_rowmm, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, X, Z, Y, smat);
-  return hipGetLastError();
-}
-
-// ------------------------------------------------------------ Gram matrices
-// partial P = X^T Y over one chunk of rows.  Thread t owns the outputs
-// e = t + 256 i: fixed column c2 = t mod Lp and rows c1 = t / Lp + i (256/Lp).
-__global__ __launch_bounds__(kThreads) void b_gram_part(const BJobDesc *__restrict__ jobs, int njob,
-                                                        const int *__restrict__ toff,
-                                                        const int64_t *__restrict__ clock, int Xc, int Yc) {
-  constexpr int RB = 16;  // rows staged per batch
-  constexpr int MO = kBlockMaxLp * kBlockMaxLp / kThreads;
-  __shared__ double Xs[RB * kBlockMaxLp], Ys[RB * kBlockMaxLp];
-  const int g = blockIdx.x;
-  const int j = bfind(toff, njob, g);
-  const BJobDesc &J = jobs[j];
-  const int k = (int)(*clock - J.start_clock);
-  if (k >= J.Kstop) return;
-  const int chunk = g - toff[j];
-  const int Lp = J.Lp, lg = J.lgLp, L2 = Lp * Lp;
-  const GLB double *__restrict__ X = bbuf(J, Xc, k);
-  const GLB double *__restrict__ Y = bbuf(J, Yc, k);
-  const int t = threadIdx.x;
-  const int c2 = t & (Lp - 1);
-  const int c1base = t >> lg;
-  const int c1step = kThreads >> lg;
-  const int nout = (L2 + kThreads - 1) / kThreads;
-  const int64_t r0 = (int64_t)chunk * kChunk;
-  int64_t r1 = r0 + kChunk;
-  if (r1 > J.n) r1 = J.n;
-  double acc[MO];
-#pragma unroll
-  for (int i = 0; i < MO; ++i) acc[i] = 0.0;
-  for (int64_t rb = r0; rb < r1; rb += RB) {
-    for (int e = t; e < RB * Lp; e += kThreads) {
-      const int64_t row = rb + (e >> lg);
-      const int cc = e & (Lp - 1);
-      Xs[e] = (row < r1) ? X[(row << lg) + cc] : 0.0;
-      Ys[e] = (row < r1) ? Y[(row << lg) + cc] : 0.0;
-    }
-    __syncthreads();
-    if (t < L2) {
-      for (int rr = 0; rr < RB; ++rr) {
-        const double y = Ys[(rr << lg) + c2];
-        const double *xr = Xs + (rr << lg) + c1base;
-#pragma unroll
-        for (int i = 0; i < MO; ++i)
-          if (i < nout) acc[i] = fma(xr[i * c1step], y, acc[i]);
-      }
-    }
-    __syncthreads();
-  }
-  GLB double *__restrict__ P = gp(J.gpart) + (int64_t)chunk * L2;
-#pragma unroll
-  for (int i = 0; i < MO; ++i) {
-    const int e = t + i * kThreads;
-    if (i < nout && e < L2) P[e] = acc[i];
-  }
-}
-
-// dest 0: A_k = sym(sum), 1: C_k = sum, 2: G = sum.  Grid (njob, 64).
-__global__ __launch_bounds__(kThreads) void b_gram_reduce(const BJobDesc *__restrict__ jobs,
-                                                          const int64_t *__restrict__ clock, int dest) {
-  const BJobDesc &J = jobs[blockIdx.x];
-  const int Lp = J.Lp, L2 = Lp * Lp;
-  const int e = blockIdx.y * kThreads + threadIdx.x;
-  if (e >= L2) return;
-  const int k = (int)(*clock - J.start_clock);
-  if (k >= J.Kstop) return;
-  const GLB double *__restrict__ P = gp(J.gpart);
-  double s = 0.0;
-  for (int c = 0; c < J.rchunks; ++c) s += P[(int64_t)c * L2 + e];
-  if (dest == 0) {
-    const int et = (e & (Lp - 1)) * Lp + (e / Lp);
-    double s2 = 0.0;
-    for (int c = 0; c < J.rchunks; ++c) s2 += P[(int64_t)c * L2 + et];
-    gp(J.Ah)[(int64_t)k * L2 + e] = 0.5 * (s + s2);
-  } else if (dest == 1) {
-    gp(J.Ch)[(int64_t)k * L2 + e] = s;
-  } else {
-    gp(J.G)[e] = s;
-  }
-}
-
-hipError_t launch_b_gram(const BBatch &b, int X, int Y, int dest, hipStream_t st) {
-  hipLaunchKernelGGL(b_gram_part, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, X, Y);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(b_gram_reduce, dim3(b.njob, kBlockMaxLp * kBlockMaxLp / kThreads), dim3(kThreads), 0, st,
-                     b.jobs, b.clock, dest);
-  return hipGetLastError();
-}
-
-// ----------------------------------------------------------- Cholesky step
-// R = chol(G) (upper, G = R^T R); a non-positive pivot restarts once from
-// G + s I with s = 1e-14 trace(G) (shifted CholeskyQR).  Rinv by back
-// substitution, one column per thread.
-__global__ __launch_bounds__(kThreads) void b_chol(const BJobDesc *__restrict__ jobs,
-                                                   const int64_t *__restrict__ clock, int mode, int init) {
-  __shared__ double A[kBlockMaxLp][kBlockMaxLp + 1];
-  __shared__ double Ri[kBlockMaxLp][kBlockMaxLp + 1];
-  __shared__ int dead[kBlockMaxLp];
-  __shared__ double thr;
-  const BJobDesc &J = jobs[blockIdx.x];
-  const int Lp = J.Lp, L2 = Lp * Lp;
-  const int k = (int)(*clock - J.start_clock);
-  if (k >= J.Kstop) return;
-  const int t = threadIdx.x;
-  const GLB double *__restrict__ G = gp(J.G);
-  // Deflation threshold on the pivots.  First pass: a column whose part
-  // outside the span of the earlier columns is below kDeflTol * ||A^T A||
-  // (or, for the starting block, kDeflTol * its largest column norm) is
-  // dropped.  Second pass: the block is already near orthonormal, so the
-  // threshold is kDeflTol on unit columns.
-  if (t == 0) {
-    double sc;
-    if (mode == 2) {
-      sc = 1.0;
-    } else if (init) {
-      double mx = 0.0;
-      for (int i = 0; i < Lp; ++i) mx = fmax(mx, G[i * Lp + i]);
-      sc = sqrt(mx);
-    } else {
-      sc = J.dscale;
-    }
-    thr = (kDeflTol * sc) * (kDeflTol * sc);
-  }
-  for (int e = t; e < L2; e += kThreads) {
-    const int i = e / Lp, jj = e - i * Lp;
-    A[i][jj] = G[e];
-  }
-  __syncthreads();
-  // right-looking Cholesky; a deflated column gets a zero row in R
-  for (int c = 0; c < Lp; ++c) {
-    if (t == 0) {
-      const double d = A[c][c];
-      const int dd = !(d > thr);
-      dead[c] = dd;
-      A[c][c] = dd ? 0.0 : sqrt(d);
-    }
-    __syncthreads();
-    const int dd = dead[c];
-    for (int jj = c + 1 + t; jj < Lp; jj += kThreads) A[c][jj] = dd ? 0.0 : A[c][jj] / A[c][c];
-    __syncthreads();
-    if (!dd) {
-      const int rem = Lp - c - 1;
-      for (int e = t; e < rem * rem; e += kThreads) {
-        const int i = c + 1 + e / rem, jj = c + 1 + e % rem;
-        if (jj >= i) A[i][jj] -= A[c][i] * A[c][jj];
-      }
-    }
-    __syncthreads();
-  }
-  if (mode == 2 && t == 0) {
-    int nd = 0;
-    for (int c = 0; c < Lp; ++c) nd += dead[c];
-    gp(J.flags)[0] = nd;
-  }
-  // upper R: A[i][j], j >= i, zero rows at deflated columns.  Its
-  // pseudo-inverse on the kept columns, column by column (deflated rows and
-  // columns of Ri are zero).
-  if (t < Lp) {
-    const int c = t;
-    for (int i = Lp - 1; i >= 0; --i) {
-      double v = 0.0;
-      if (i <= c && !dead[i] && !dead[c]) {
-        v = (i == c) ? 1.0 : 0.0;
-        for (int l2 = i + 1; l2 <= c; ++l2) v -= A[i][l2] * Ri[l2][c];
-        v /= A[i][i];
-      }
-      Ri[i][c] = v;
-    }
-  }
-  __syncthreads();
-  if (mode == 1) {
-    for (int e = t; e < L2; e += kThreads) {
-      const int i = e / Lp, jj = e - i * Lp;
-      gp(J.R1)[e] = (jj >= i) ? A[i][jj] : 0.0;
-      gp(J.R1inv)[e] = Ri[i][jj];
-    }
-    if (init && t < Lp) gp(J.beta0)[t] = sqrt(G[t * Lp + t]);
-  } else {
-    // M = R1inv R2inv (upper x upper), B = R2 R1
-    const GLB double *__restrict__ R1 = gp(J.R1);
-    const GLB double *__restrict__ R1i = gp(J.R1inv);
-    const int64_t mdst = (int64_t)(init ? J.Kcap : k) * L2;
-    const int64_t bdst = (int64_t)(init ? 0 : k + 1) * L2;
-    for (int e = t; e < L2; e += kThreads) {
-      const int i = e / Lp, jj = e - i * Lp;
-      double m = 0.0, bb = 0.0;
-      for (int l2 = i; l2 <= jj; ++l2) {
-        m += R1i[i * Lp + l2] * Ri[l2][jj];
-        bb += ((l2 >= i) ? A[i][l2] : 0.0) * R1[l2 * Lp + jj];
-      }
-      gp(J.Mh)[mdst + e] = (jj >= i) ? m : 0.0;
-      gp(J.Bh)[bdst + e] = (jj >= i) ? bb : 0.0;
-    }
-  }
-}
-
-hipError_t launch_b_chol(const BBatch &b, int mode, int init, hipStream_t st) {
-  hipLaunchKernelGGL(b_chol, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, mode, init);
   return hipGetLastError();
 }
 
@@ -529,56 +248,58 @@ hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st) {
 }
 
 // ------------------------------------------------------ backward solution
-// One block per shift of one job: Y_k overwrites Z_k (columns < L).
+// Y_k = H_k^{-1} (Z_k + B_{k+1}^T Y_{k+1}), k = K-1 .. 0; Y_k overwrites Z_k
+// (columns < L).  The columns are independent: one workgroup per (shift,
+// group of 16 columns), H_k^{-1} staged in LDS for each step.
+constexpr int kBsCols = 16;
+
 __global__ __launch_bounds__(kThreads) void b_backsolve(BJobDesc J, int K) {
-  const int s = blockIdx.x;
+  __shared__ double2 Hs[kBlockMaxLp * kBlockMaxLp];
+  __shared__ double2 Ts[kBlockMaxLp * kBsCols], Yn[kBlockMaxLp * kBsCols];
+  const int ng = (J.L + kBsCols - 1) / kBsCols;
+  const int s = blockIdx.x / ng, cg = blockIdx.x - s * ng;
   const int Lp = J.Lp, L2 = Lp * Lp, L = J.L;
   const int t = threadIdx.x;
+  const int jj = t & (kBsCols - 1), col = cg * kBsCols + jj;
+  const bool live = col < L;
   const int64_t hbase = (int64_t)s * (J.Kcap + 1) * L2;
-  GLB double2 *__restrict__ Hinv = gp(J.Hinv) + hbase;
+  const GLB double2 *__restrict__ Hinv = gp(J.Hinv) + hbase;
   GLB double2 *__restrict__ Zh = gp(J.Zh) + hbase;
-  GLB double2 *__restrict__ T1 = gp(J.ctmp) + (int64_t)s * 2 * L2;
-  GLB double2 *__restrict__ Yn = T1 + L2;  // Y_{k+1}
   for (int k = K - 1; k >= 0; --k) {
-    // T1 = Z_k + B_{k+1}^T Y_{k+1}
+    const GLB double2 *__restrict__ Hk = Hinv + (int64_t)k * L2;
+    for (int e = t; e < L2; e += kThreads) Hs[e] = Hk[e];
+    // T = Z_k + B_{k+1}^T Y_{k+1} for this thread's rows
     const GLB double *__restrict__ Bk1 = gp(J.Bh) + (int64_t)(k + 1) * L2;
-    const GLB double2 *__restrict__ Zk = Zh + (int64_t)k * L2;
-    for (int e = t; e < Lp * L; e += kThreads) {
-      const int i = e / L, jj = e - i * L;
-      double2 acc = Zk[i * Lp + jj];
+    for (int i = t >> 4; i < Lp; i += kThreads / kBsCols) {
+      double2 acc = live ? Zh[(int64_t)k * L2 + i * Lp + col] : make_double2(0.0, 0.0);
       if (k < K - 1) {
         for (int c = 0; c <= i; ++c) {  // (B^T)[i][c] = B[c][i], B upper
           const double bv = Bk1[c * Lp + i];
-          const double2 y = Yn[c * Lp + jj];
+          const double2 y = Yn[c * kBsCols + jj];
           acc.x = fma(bv, y.x, acc.x);
           acc.y = fma(bv, y.y, acc.y);
         }
       }
-      T1[i * Lp + jj] = acc;
+      Ts[i * kBsCols + jj] = acc;
     }
     __syncthreads();
-    const GLB double2 *__restrict__ Hk = Hinv + (int64_t)k * L2;
-    for (int e = t; e < Lp * L; e += kThreads) {
-      const int i = e / L, jj = e - i * L;
+    for (int i = t >> 4; i < Lp; i += kThreads / kBsCols) {
       double2 acc = make_double2(0.0, 0.0);
       for (int c = 0; c < Lp; ++c) {
-        const double2 r = cmulb(Hk[i * Lp + c], T1[c * Lp + jj]);
+        const double2 r = cmulb(Hs[i * Lp + c], Ts[c * kBsCols + jj]);
         acc.x += r.x;
         acc.y += r.y;
       }
-      Zh[(int64_t)k * L2 + i * Lp + jj] = acc;
-    }
-    __syncthreads();
-    for (int e = t; e < Lp * L; e += kThreads) {
-      const int i = e / L, jj = e - i * L;
-      Yn[i * Lp + jj] = Zh[(int64_t)k * L2 + i * Lp + jj];
+      Yn[i * kBsCols + jj] = acc;
+      if (live) Zh[(int64_t)k * L2 + i * Lp + col] = acc;
     }
     __syncthreads();
   }
 }
 
 hipError_t launch_b_backsolve(const BJobDesc &hj, int K, hipStream_t st) {
-  hipLaunchKernelGGL(b_backsolve, dim3(hj.S), dim3(kThreads), 0, st, hj, K);
+  const int ng = (hj.L + kBsCols - 1) / kBsCols;
+  hipLaunchKernelGGL(b_backsolve, dim3(hj.S * ng), dim3(kThreads), 0, st, hj, K);
   return hipGetLastError();
 }
 

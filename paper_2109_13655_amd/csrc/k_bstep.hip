@@ -1,0 +1,525 @@
+// Block Lanczos step on the n x Lp blocks (Lp = 16, 32 or 64), FP64 MFMA.
+//
+// Step k turns W = A^T A Q_k into Q_{k+1} by block classical Gram-Schmidt
+// against Q_k, applied twice (the first projection explicitly, so that a
+// new block much smaller than W is still resolved), and CholeskyQR2:
+//
+//   alpha:  W' = W - Q_{k-1} B_k^T (in place);  P = Q_k^T W'
+//   beta:   W2 = W' - Q_k P (not stored);  C = Q_k^T W2,  G2 = W2^T W2
+//   small1: A_k = sym(P);  R1 = chol(G2 - C^T C);  T = (P + C) R1^-1
+//   gamma0: Y = W' R1^-1 - Q_k T (not stored);  G3 = Y^T Y
+//   small2: R2 = chol(G3);  M = R1^-1 R2^-1;  N = T R2^-1;  B_{k+1} = R2 R1
+//   gamma:  Q_{k+1} = Y R2^-1 = W' M - Q_k N
+//
+// A new direction whose Cholesky pivot falls below kDeflTol^2 times its own
+// squared norm before the projection is rounding noise (the space is
+// exhausted) and is deflated: zero row in R, zero column of Q_{k+1}.  The
+// second pass of the method (regenerating Q_k for the moments) runs alpha
+// without Gram matrices and gamma, the same kernels, so the basis is
+// reproduced bit for bit.
+//
+// Tall kernels: a job's rows are cut into 64-row chunks; each of its nvb
+// workgroups (4 waves, one 16-row panel each) walks the chunks vb, vb + nvb,
+// ... and keeps its Gram partial sums in MFMA accumulators.  The partials are
+// reduced in a fixed order, so results do not depend on timing or on which
+// other jobs share the launch.
+#include "csvd_impl.h"
+
+namespace csvd {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kPanel = 64;              // rows per chunk (4 waves x 16 rows)
+constexpr int kSS = kBlockMaxLp + 1;    // LDS row stride of staged Lp x Lp matrices
+constexpr int kPSMax = kBlockMaxLp + 16;  // LDS row stride of staged panels (largest)
+constexpr int kMaxTiles = 7;            // Gram output tiles per wave (Lp = 64: 16 + 10 over 4 waves)
+
+__device__ __forceinline__ int bfind2(const int *__restrict__ toff, int njob, int g) {
+  int lo = 0, hi = njob - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (toff[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// panel row stride in LDS: consecutive rows land 32 banks apart
+__device__ __forceinline__ int panel_stride(int LP) { return LP == 16 ? 16 : LP + 16; }
+
+// D[nt] += X(rows row0 .. row0 + 15) S for the 16-column tiles nt < Lp/16.
+// MFMA f64 16x16x4: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16)
+// and holds D(l / 16 + 4 v, l % 16).  The contraction index c is split as
+// c = q * KS + ks (q = l / 16), so each lane reads KS consecutive entries of
+// its row with wide loads.
+__device__ __forceinline__ void panel_mm(const GLB double *__restrict__ X, int64_t row0, int64_t n, int LP,
+                                         const double *S, v4d (&D)[4]) {
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
+  const int KS = LP >> 2, NT = LP >> 4;
+  const int64_t row = row0 + rl;
+  double a[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) a[i] = 0.0;
+  if (row < n) {
+    const GLB double2 *p = reinterpret_cast<const GLB double2 *>(X + row * LP + q * KS);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (2 * i < KS) {
+        const double2 v = p[i];
+        a[2 * i] = v.x;
+        a[2 * i + 1] = v.y;
+      }
+  }
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    if (ks < KS) {
+      const double *sr = S + (q * KS + ks) * kSS + rl;
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
+        if (nt < NT) D[nt] = mfma4(a[ks], sr[16 * nt], D[nt]);
+    }
+  }
+}
+
+// element (row0 + l/16 + 4v, 16 nt + l%16) of a row-major n x Lp block
+__device__ __forceinline__ void load_dl(const GLB double *__restrict__ X, int64_t row0, int64_t n, int LP,
+                                        v4d (&D)[4]) {
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
+  const int NT = LP >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row0 + q + 4 * v;
+      D[nt][v] = (nt < NT && row < n) ? X[row * LP + 16 * nt + rl] : 0.0;
+    }
+  }
+}
+
+__device__ __forceinline__ void store_dl(GLB double *__restrict__ X, int64_t row0, int64_t n, int LP,
+                                         const v4d (&D)[4]) {
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
+  const int NT = LP >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row0 + q + 4 * v;
+      if (nt < NT && row < n) X[row * LP + 16 * nt + rl] = D[nt][v];
+    }
+  }
+}
+
+__device__ __forceinline__ void zero4(v4d (&D)[4]) {
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) D[nt] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+// Gram output tile tau of a wave: tau < nfull -> tile (ti, tj) of X^T Y
+// (mat 0, nfull = NT^2 or 0); else the upper tiles ti <= tj of Y^T Y (mat 1),
+// row by row.
+__device__ __forceinline__ void gram_tile(int tau, int NT, int nfull, int &mat, int &ti, int &tj) {
+  if (tau < nfull) {
+    mat = 0;
+    ti = tau / NT;
+    tj = tau - ti * NT;
+  } else {
+    int u = tau - nfull;
+    ti = 0;
+    while (u >= NT - ti) {
+      u -= NT - ti;
+      ++ti;
+    }
+    mat = 1;
+    tj = ti + u;
+  }
+}
+
+// Stages the wave's panels (Q part and new part, D layout) and accumulates
+// this wave's Gram tiles over the 64 rows of the chunk.
+__device__ __forceinline__ void gram_chunk(const v4d (&Xd)[4], const v4d (&Yd)[4], int LP, int nfull, int ntile,
+                                           double *Xs, double *Ys, v4d (&acc)[kMaxTiles]) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const int NT = LP >> 4, PS = panel_stride(LP);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (nt < NT) {
+        const int rr = 16 * w + q + 4 * v;
+        if (nfull) Xs[rr * PS + 16 * nt + rl] = Xd[nt][v];
+        Ys[rr * PS + 16 * nt + rl] = Yd[nt][v];
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kMaxTiles; ++i) {
+    const int tau = w + 4 * i;
+    if (tau < ntile) {
+      int mat, ti, tj;
+      gram_tile(tau, NT, nfull, mat, ti, tj);
+      const double *Am = mat == 0 ? Xs : Ys;
+#pragma unroll
+      for (int ks = 0; ks < 16; ++ks) {
+        const int rr = 4 * ks + q;
+        acc[i] = mfma4(Am[rr * PS + 16 * ti + rl], Ys[rr * PS + 16 * tj + rl], acc[i]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// partial sums of workgroup vb: gpart[(vb * 2 + mat) * L2 + r * Lp + c]
+__device__ __forceinline__ void store_gram(const BJobDesc &J, int vb, int nfull, int ntile,
+                                           const v4d (&acc)[kMaxTiles]) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const int LP = J.Lp, NT = LP >> 4, L2 = LP * LP;
+  GLB double *P = gp(J.gpart) + (int64_t)vb * 2 * L2;
+#pragma unroll
+  for (int i = 0; i < kMaxTiles; ++i) {
+    const int tau = w + 4 * i;
+    if (tau < ntile) {
+      int mat, ti, tj;
+      gram_tile(tau, NT, nfull, mat, ti, tj);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[mat * L2 + (16 * ti + q + 4 * v) * LP + 16 * tj + rl] = acc[i][v];
+    }
+  }
+}
+
+__device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, int LP, bool trans, bool neg,
+                                          double *dst) {
+  for (int e = threadIdx.x; e < LP * LP; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    const double v = trans ? src[c * LP + r] : src[e];
+    dst[r * kSS + c] = neg ? -v : v;
+  }
+}
+
+// ---------------------------------------------------------- tall passes
+// mode kTallAlpha: W' = W - Q_{k-1} B_k^T stored in place; Gram Q_k^T W'
+//   (when grams = 1).
+// mode kTallBeta:  W2 = X - Q_k P with X = W' (init: Vpad, no Q term);
+//   Grams Q_k^T W2 and W2^T W2.
+// mode kTallGamma0: Y = X R1^-1 - Q_k T (init: no Q term); Gram Y^T Y.
+enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
+
+__global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__ jobs, int njob,
+                                                    const int *__restrict__ toff, const int64_t *__restrict__ clock,
+                                                    int mode, int grams, int init) {
+  __shared__ double S1[kBlockMaxLp * kSS], S2[kBlockMaxLp * kSS];
+  __shared__ double Xs[kPanel * kPSMax], Ys[kPanel * kPSMax];
+  const int g = blockIdx.x;
+  const int j = bfind2(toff, njob, g);
+  const BJobDesc &J = jobs[j];
+  const int k = (int)(*clock - J.start_clock);
+  if (k >= J.Kstop) return;
+  const int vb = g - toff[j];
+  const int LP = J.Lp, L2 = LP * LP, NT = LP >> 4;
+  const int t = threadIdx.x, w = t >> 6;
+  const int64_t n = J.n, nL = n * LP;
+  GLB double *X = init ? gp(J.Vpad) : gp(J.W);
+  const GLB double *Qc = gp(J.Q) + (int64_t)(k % 3) * nL;
+  const GLB double *Pv = gp(J.Q) + (int64_t)((k + 2) % 3) * nL;
+  const bool useQ = !init && (mode != kTallAlpha || k > 0);
+  if (mode == kTallAlpha) {
+    if (useQ) stage_mat(gp(J.Bh) + (int64_t)k * L2, LP, true, true, S2);  // -B_k^T
+  } else if (mode == kTallBeta) {
+    if (useQ) stage_mat(gp(J.red), LP, false, true, S2);  // -P
+  } else {
+    stage_mat(gp(J.scr) + L2, LP, false, false, S1);           // R1^-1
+    if (useQ) stage_mat(gp(J.scr) + 2 * L2, LP, false, true, S2);  // -T
+  }
+  __syncthreads();
+  const int nfull = (mode == kTallGamma0) ? 0 : NT * NT;
+  const int ntile = nfull + ((mode == kTallAlpha) ? 0 : NT * (NT + 1) / 2);
+  v4d acc[kMaxTiles];
+#pragma unroll
+  for (int i = 0; i < kMaxTiles; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int ch = vb; ch < J.nchunk; ch += J.nvb) {
+    const int64_t r0 = (int64_t)ch * kPanel + 16 * w;
+    v4d D[4];
+    if (mode == kTallGamma0) {
+      zero4(D);
+      panel_mm(X, r0, n, LP, S1, D);
+    } else {
+      load_dl(X, r0, n, LP, D);
+    }
+    if (useQ) panel_mm(mode == kTallAlpha ? Pv : Qc, r0, n, LP, S2, D);
+    if (mode == kTallAlpha && useQ) store_dl(X, r0, n, LP, D);
+    if (grams) {
+      v4d Qd[4];
+      if (nfull && !init) load_dl(Qc, r0, n, LP, Qd);
+      else zero4(Qd);
+      gram_chunk(Qd, D, LP, nfull, ntile, Xs, Ys, acc);
+    }
+  }
+  if (grams) store_gram(J, vb, nfull, ntile, acc);
+}
+
+// ------------------------------------------------------------------ gamma
+// Q_{k+1} = W' M_k - Q_k N_k; init = 1: Q_0 = Vpad M_init.
+__global__ __launch_bounds__(kThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
+                                                     const int *__restrict__ toff, const int64_t *__restrict__ clock,
+                                                     int init) {
+  __shared__ double S1[kBlockMaxLp * kSS], S2[kBlockMaxLp * kSS];
+  const int g = blockIdx.x;
+  const int j = bfind2(toff, njob, g);
+  const BJobDesc &J = jobs[j];
+  const int k = (int)(*clock - J.start_clock);
+  if (k >= J.Kstop) return;
+  const int vb = g - toff[j];
+  const int LP = J.Lp, L2 = LP * LP;
+  const int t = threadIdx.x, w = t >> 6;
+  const int64_t n = J.n, nL = n * LP;
+  const GLB double *X = init ? gp(J.Vpad) : gp(J.W);
+  const GLB double *Qc = gp(J.Q) + (int64_t)(k % 3) * nL;
+  GLB double *Qn = gp(J.Q) + (int64_t)((init ? k : k + 1) % 3) * nL;
+  stage_mat(gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2, LP, false, false, S1);
+  if (!init) stage_mat(gp(J.Nh) + (int64_t)k * L2, LP, false, true, S2);
+  __syncthreads();
+  for (int ch = vb; ch < J.nchunk; ch += J.nvb) {
+    const int64_t r0 = (int64_t)ch * kPanel + 16 * w;
+    v4d D[4];
+    zero4(D);
+    panel_mm(X, r0, n, LP, S1, D);
+    if (!init) panel_mm(Qc, r0, n, LP, S2, D);
+    store_dl(Qn, r0, n, LP, D);
+  }
+  (void)t;
+}
+
+// ----------------------------------------------------------------- reduce
+// red[(d0 + m) L2 + e] = sum over the workgroups vb of gpart[(vb * 2 + m0 +
+// m) L2 + e], m < nm, in a fixed order: 8 interleaved partial sums combined
+// in order.  Grid (njob, 2 * 64 * 64 / 32); block = 32 outputs x 8 groups.
+__global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict__ jobs,
+                                                      const int64_t *__restrict__ clock, int m0, int nm, int d0) {
+  __shared__ double part[8][32];
+  const BJobDesc &J = jobs[blockIdx.x];
+  const int k = (int)(*clock - J.start_clock);
+  if (k >= J.Kstop) return;
+  const int L2 = J.Lp * J.Lp;
+  if ((int)blockIdx.y * 32 >= nm * L2) return;
+  const int t = threadIdx.x, grp = t >> 5;
+  const int o = blockIdx.y * 32 + (t & 31);
+  const GLB double *__restrict__ P = gp(J.gpart) + (int64_t)m0 * L2;
+  double s = 0.0;
+  for (int vb = grp; vb < J.nvb; vb += 8) s += P[(int64_t)vb * 2 * L2 + o];
+  part[grp][t & 31] = s;
+  __syncthreads();
+  if (grp == 0) {
+    double r = part[0][t];
+#pragma unroll
+    for (int h = 1; h < 8; ++h) r += part[h][t];
+    gp(J.red)[(int64_t)d0 * L2 + o] = r;
+  }
+}
+
+// ------------------------------------------------------- small matrices
+// Right-looking Cholesky of the symmetric matrix in A (LDS, stride kSS) in
+// place, upper factor.  A pivot <= thr[c] deflates column c: zero row in R.
+// Row c is scaled one phase late (phase c + 1) so that each phase needs a
+// single barrier.
+__device__ void chol_defl(double *A, int LP, const double *thr, int *dead) {
+  const int t = threadIdx.x;
+  int dprev = 1;
+  double invprev = 0.0, pivprev = 0.0;
+  for (int c = 0; c <= LP; ++c) {
+    if (c > 0) {
+      const int r = c - 1;
+      for (int jj = r + t; jj < LP; jj += kThreads)
+        A[r * kSS + jj] = (jj == r) ? pivprev : (dprev ? 0.0 : A[r * kSS + jj] * invprev);
+    }
+    if (c == LP) break;
+    const double d = A[c * kSS + c];
+    const int dd = !(d > thr[c]);
+    const double piv = dd ? 0.0 : sqrt(d);
+    const double inv = dd ? 0.0 : 1.0 / piv;
+    if (!dd) {
+      const int rem = LP - c - 1;
+      for (int e = t; e < rem * rem; e += kThreads) {
+        const int i = c + 1 + e / rem, jj = c + 1 + e % rem;
+        if (jj >= i) A[i * kSS + jj] -= (A[c * kSS + i] * inv) * (A[c * kSS + jj] * inv);
+      }
+    }
+    if (t == 0) dead[c] = dd;
+    dprev = dd;
+    invprev = inv;
+    pivprev = piv;
+    __syncthreads();
+  }
+  __syncthreads();
+}
+
+// X = R^+ for the upper factor R (zero rows at deflated columns): the inverse
+// on the kept rows and columns, zero elsewhere.  Thread c builds column c.
+__device__ void tri_inv(const double *R, int LP, const int *dead, double *X) {
+  const int t = threadIdx.x;
+  if (t < LP) {
+    const int c = t;
+    for (int i = LP - 1; i > c; --i) X[i * kSS + c] = 0.0;
+    for (int i = c; i >= 0; --i) {
+      double v = 0.0;
+      if (!dead[i] && !dead[c]) {
+        v = (i == c) ? 1.0 : 0.0;
+        for (int l2 = i + 1; l2 <= c; ++l2) v -= R[i * kSS + l2] * X[l2 * kSS + c];
+        v /= R[i * kSS + i];
+      }
+      X[i * kSS + c] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// G from the reduced upper tiles: entry (r, c) lives at (r, c) when the tile
+// of r is not below the tile of c, else at (c, r)
+__device__ __forceinline__ double gram_sym(const GLB double *G, int LP, int r, int c) {
+  return ((r >> 4) <= (c >> 4)) ? G[r * LP + c] : G[c * LP + r];
+}
+
+// reduced slots: red[0] = P, red[1] = C, red[2] = G2 (upper tiles), red[3] =
+// G3 (upper tiles); scr = R1, R1^-1, T
+__global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict__ jobs,
+                                                      const int64_t *__restrict__ clock, int init) {
+  __shared__ double Pm[kBlockMaxLp * kSS], A[kBlockMaxLp * kSS], Ri[kBlockMaxLp * kSS], Cm[kBlockMaxLp * kSS];
+  __shared__ int dead[kBlockMaxLp];
+  __shared__ double thr[kBlockMaxLp];
+  const BJobDesc &J = jobs[blockIdx.x];
+  const int k = (int)(*clock - J.start_clock);
+  if (k >= J.Kstop) return;
+  const int LP = J.Lp, L2 = LP * LP, t = threadIdx.x;
+  const GLB double *red = gp(J.red);
+  for (int e = t; e < L2; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    Pm[r * kSS + c] = init ? 0.0 : red[e];
+    Cm[r * kSS + c] = init ? 0.0 : red[L2 + e];
+    A[r * kSS + c] = gram_sym(red + 2 * L2, LP, r, c);
+  }
+  __syncthreads();
+  // Deflation test of column c: its part outside the span of Q_k and of the
+  // earlier columns is below kDeflTol times its own norm ||w'_c|| (the norm
+  // before the projection, ||P(:, c)||^2 + G2(c, c)), or below 1e-14 ||A^T A||.
+  if (t < LP) {
+    double own = A[t * kSS + t];
+    for (int i = 0; i < LP; ++i) own = fma(Pm[i * kSS + t], Pm[i * kSS + t], own);
+    const double flo = init ? 0.0 : (1e-14 * J.dscale) * (1e-14 * J.dscale);
+    thr[t] = fmax(kDeflTol * kDeflTol * own, flo);
+  }
+  __syncthreads();  // the thresholds read the diagonal before the correction below
+  if (init) {
+    if (t < LP) gp(J.beta0)[t] = sqrt(fmax(A[t * kSS + t], 0.0));
+  } else {
+    GLB double *Ak = gp(J.Ah) + (int64_t)k * L2;
+    for (int e = t; e < L2; e += kThreads) {
+      const int r = e / LP, c = e - r * LP;
+      Ak[e] = 0.5 * (Pm[r * kSS + c] + Pm[c * kSS + r]);
+      // G2 - C^T C: the second projection W2 - Q C
+      double s = 0.0;
+      for (int l2 = 0; l2 < LP; ++l2) s = fma(Cm[l2 * kSS + r], Cm[l2 * kSS + c], s);
+      A[r * kSS + c] -= s;
+    }
+  }
+  __syncthreads();
+  chol_defl(A, LP, thr, dead);
+  tri_inv(A, LP, dead, Ri);
+  GLB double *R1 = gp(J.scr), *R1i = R1 + L2, *T = R1 + 2 * L2;
+  for (int e = t; e < L2; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    R1[e] = (c >= r) ? A[r * kSS + c] : 0.0;
+    R1i[e] = Ri[r * kSS + c];
+    double s = 0.0;
+    if (!init)
+      for (int l2 = 0; l2 <= c; ++l2) s = fma(Pm[r * kSS + l2] + Cm[r * kSS + l2], Ri[l2 * kSS + c], s);
+    T[e] = s;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict__ jobs,
+                                                      const int64_t *__restrict__ clock, int init) {
+  __shared__ double A[kBlockMaxLp * kSS], X[kBlockMaxLp * kSS], Y[kBlockMaxLp * kSS], Z[kBlockMaxLp * kSS];
+  __shared__ int dead[kBlockMaxLp];
+  __shared__ double thr[kBlockMaxLp];
+  const BJobDesc &J = jobs[blockIdx.x];
+  const int k = (int)(*clock - J.start_clock);
+  if (k >= J.Kstop) return;
+  const int LP = J.Lp, L2 = LP * LP, t = threadIdx.x;
+  const GLB double *red = gp(J.red);
+  const GLB double *R1 = gp(J.scr), *R1i = R1 + L2, *T = R1 + 2 * L2;
+  for (int e = t; e < L2; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    A[r * kSS + c] = gram_sym(red + 3 * L2, LP, r, c);
+    Y[r * kSS + c] = init ? 0.0 : T[e];
+    Z[r * kSS + c] = R1i[e];
+  }
+  __syncthreads();
+  if (t < LP) thr[t] = kDeflTol * kDeflTol * A[t * kSS + t];
+  __syncthreads();
+  chol_defl(A, LP, thr, dead);
+  if (t == 0) {
+    int nd = 0;
+    for (int c = 0; c < LP; ++c) nd += dead[c];
+    gp(J.flags)[0] = nd;
+  }
+  tri_inv(A, LP, dead, X);  // R2^+
+  GLB double *M = gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2;
+  GLB double *N = gp(J.Nh) + (int64_t)k * L2;
+  for (int e = t; e < L2; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    double s = 0.0;
+    for (int l2 = r; l2 <= c; ++l2) s = fma(Z[r * kSS + l2], X[l2 * kSS + c], s);
+    M[e] = s;
+    if (!init) {
+      double s2 = 0.0;
+      for (int l2 = 0; l2 <= c; ++l2) s2 = fma(Y[r * kSS + l2], X[l2 * kSS + c], s2);
+      N[e] = s2;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < L2; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    Z[r * kSS + c] = R1[e];
+  }
+  __syncthreads();
+  GLB double *B = gp(J.Bh) + (int64_t)(init ? 0 : k + 1) * L2;
+  for (int e = t; e < L2; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    double s = 0.0;
+    for (int l2 = r; l2 <= c; ++l2) s = fma(A[r * kSS + l2], Z[l2 * kSS + c], s);
+    B[e] = s;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st) {
+  hipLaunchKernelGGL(bs_tall, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode, grams,
+                     init);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st) {
+  hipLaunchKernelGGL(bs_gamma, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, hipStream_t st) {
+  hipLaunchKernelGGL(bs_reduce, dim3(b.njob, 2 * kBlockMaxLp * kBlockMaxLp / 32), dim3(kThreads), 0, st, b.jobs,
+                     b.clock, m0, nm, d0);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_small1(const BBatch &b, int init, hipStream_t st) {
+  hipLaunchKernelGGL(bs_small1, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_bs_small2(const BBatch &b, int init, hipStream_t st) {
+  hipLaunchKernelGGL(bs_small2, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  return hipGetLastError();
+}
+
+}  // namespace csvd

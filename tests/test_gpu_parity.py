@@ -98,16 +98,24 @@ def test_solutions_and_moments_match_oracle(transform):
         cs.csvd_destroy(ctx)
 
 
+def _mid_problem():
+    sig = np.linspace(0.02, 1.0, 1100)
+    return synth.givens_known(1300, 1100, sigma=sig, nrot=3000, config=85, a=0.40, b=0.41)
+
+
 @pytest.mark.parametrize("transform", [cs.CSVD_PLAIN, cs.CSVD_EXP])
-@pytest.mark.parametrize("L", [8, 5])
-def test_block_moments_match_oracle(transform, L):
+@pytest.mark.parametrize("L,small", [(8, False), (5, False), (8, True)])
+def test_block_moments_match_oracle(transform, L, small):
     """Block solver (one block Lanczos basis for all shifts, two passes):
-    moments S_0..S_M against the oracle's direct solves; L = 5 exercises the
-    seeded padding columns of the block."""
-    I = _small_problem()
+    moments S_0..S_M against the oracle's direct solves.  L = 5 exercises the
+    seeded padding columns (the block is 16 wide).  small = True forces the
+    block basis on n = 250, where 16 columns exhaust the space in about 16
+    steps and deflation takes over: a looser bound (the automatic choice
+    uses the per-column solver there)."""
+    I = _small_problem() if small else _mid_problem()
     M, N = 4, 16
     V = synth.v_in(I.n, L, 3)
-    say("block moments", transform, L)
+    say("block moments", transform, L, "n", I.n)
     ctx = make_ctx(I)
     try:
         p = cs.csvd_params_default(L=L, M=M, N=N, transform=transform, solve_rtol=1e-12,
@@ -121,22 +129,27 @@ def test_block_moments_match_oracle(transform, L):
         for k in range(M + 1):
             Sk = cs.csvd_get_moment(ctx, k, I.n, L)
             scale = 2 * np.abs(c[:, k]).sum() * ymax
-            assert np.linalg.norm(Sk - S_o[k]) <= 1e-9 * scale, (k, np.linalg.norm(Sk - S_o[k]), scale)
+            bound = (1e-6 if small else 1e-9) * scale
+            assert np.linalg.norm(Sk - S_o[k]) <= bound, (k, np.linalg.norm(Sk - S_o[k]), scale)
     finally:
         cs.csvd_destroy(ctx)
 
 
 def test_block_and_single_solvers_agree():
     """Both solvers give the same triplets on the same problem."""
-    I = _small_problem()
+    I = _mid_problem()
     V = synth.v_in(I.n, 8, 12)
     ctx = make_ctx(I)
     try:
         out = []
         for solver in (cs.CSVD_SOLVER_BLOCK, cs.CSVD_SOLVER_SINGLE):
             p = cs.csvd_params_default(L=8, M=4, N=16, ell=2, norm_a=1.0, solver=solver)
-            cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+            st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+            info = cs.csvd_get_info(ctx)
             out.append(cs.csvd_get_triplets(ctx, I.m, I.n))
+            say("solver", solver, "status", st, "steps", info.iterations, "total", info.iterations_total,
+                "converged", info.converged, "deflated", info.deflated, "est", info.max_solve_resid_est,
+                "resid", out[-1][3].max() if out[-1][3].size else None)
         (s1, U1, V1, r1), (s2, U2, V2, r2) = out
         assert s1.size == s2.size > 0
         np.testing.assert_allclose(s1, s2, rtol=1e-10)
