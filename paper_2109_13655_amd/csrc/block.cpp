@@ -7,6 +7,8 @@
 
 namespace csvd {
 
+static int lp_bit(int Lp) { return Lp == 16 ? 1 : (Lp == 32 ? 2 : 4); }
+
 size_t BlockJob::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int Kcap, int L, int Kmom) {
   (void)nnz;
   const int64_t L2 = (int64_t)Lp * Lp;
@@ -117,6 +119,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   solo.total2 = J.tiles2;
   solo.totalr = J.nvb;
   solo.totals = S;
+  solo.lpmask = lp_bit(Lp);
   return hipStreamSynchronize(st);  // host vectors are temporaries
 }
 
@@ -245,6 +248,8 @@ hipError_t BEngine::rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &d
   b.total2 = t2[nj];
   b.totalr = tr[nj];
   b.totals = ts[nj];
+  b.lpmask = 0;
+  for (int i = 0; i < nj; ++i) b.lpmask |= lp_bit(descs[i].Lp);
   b.clock = d_clock_.as<int64_t>();
   return hipSuccess;
 }

@@ -133,6 +133,7 @@ struct BBatch {
   int njob;
   const int *toff1, *toff2, *toffr, *toffs;  // tiles of A, A^T, row chunks, shifts
   int total1, total2, totalr, totals;
+  int lpmask;  // block widths present: bit 0 -> 16, bit 1 -> 32, bit 2 -> 64
   const int64_t *clock;
 };
 

@@ -28,6 +28,7 @@
 namespace csvd {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 constexpr int kPanel = 64;              // rows per chunk (4 waves x 16 rows)
 constexpr int kSS = kBlockMaxLp + 1;    // LDS row stride of staged Lp x Lp matrices
@@ -47,68 +48,65 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// panel row stride in LDS: consecutive rows land 32 banks apart
-__device__ __forceinline__ int panel_stride(int LP) { return LP == 16 ? 16 : LP + 16; }
+// panel row stride in LDS (LP == 16 ? 16 : LP + 16): consecutive rows land
+// 32 banks apart
 
 // D[nt] += X(rows row0 .. row0 + 15) S for the 16-column tiles nt < Lp/16.
 // MFMA f64 16x16x4: lane l supplies A(l % 16, l / 16) and B(l / 16, l % 16)
 // and holds D(l / 16 + 4 v, l % 16).  The contraction index c is split as
 // c = q * KS + ks (q = l / 16), so each lane reads KS consecutive entries of
 // its row with wide loads.
-__device__ __forceinline__ void panel_mm(const GLB double *__restrict__ X, int64_t row0, int64_t n, int LP,
+template <int LP>
+__device__ __forceinline__ void panel_mm(const GLB double *__restrict__ X, int64_t row0, int64_t n,
                                          const double *S, v4d (&D)[4]) {
+  constexpr int KS = LP / 4, NT = LP / 16;
   const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
-  const int KS = LP >> 2, NT = LP >> 4;
   const int64_t row = row0 + rl;
-  double a[16];
+  double a[KS];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) a[i] = 0.0;
+  for (int i = 0; i < KS; ++i) a[i] = 0.0;
   if (row < n) {
-    const GLB double2 *p = reinterpret_cast<const GLB double2 *>(X + row * LP + q * KS);
+    const GLB v2d *p = reinterpret_cast<const GLB v2d *>(X + row * LP + q * KS);
 #pragma unroll
-    for (int i = 0; i < 8; ++i)
-      if (2 * i < KS) {
-        const double2 v = p[i];
-        a[2 * i] = v.x;
-        a[2 * i + 1] = v.y;
-      }
+    for (int i = 0; i < KS / 2; ++i) {
+      const v2d v = p[i];
+      a[2 * i] = v.x;
+      a[2 * i + 1] = v.y;
+    }
   }
 #pragma unroll
-  for (int ks = 0; ks < 16; ++ks) {
-    if (ks < KS) {
-      const double *sr = S + (q * KS + ks) * kSS + rl;
+  for (int ks = 0; ks < KS; ++ks) {
+    const double *sr = S + (q * KS + ks) * kSS + rl;
 #pragma unroll
-      for (int nt = 0; nt < 4; ++nt)
-        if (nt < NT) D[nt] = mfma4(a[ks], sr[16 * nt], D[nt]);
-    }
+    for (int nt = 0; nt < NT; ++nt) D[nt] = mfma4(a[ks], sr[16 * nt], D[nt]);
   }
 }
 
 // element (row0 + l/16 + 4v, 16 nt + l%16) of a row-major n x Lp block
-__device__ __forceinline__ void load_dl(const GLB double *__restrict__ X, int64_t row0, int64_t n, int LP,
-                                        v4d (&D)[4]) {
+template <int LP>
+__device__ __forceinline__ void load_dl(const GLB double *__restrict__ X, int64_t row0, int64_t n, v4d (&D)[4]) {
+  constexpr int NT = LP / 16;
   const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
-  const int NT = LP >> 4;
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
+  for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = row0 + q + 4 * v;
-      D[nt][v] = (nt < NT && row < n) ? X[row * LP + 16 * nt + rl] : 0.0;
+      D[nt][v] = (row < n) ? X[row * LP + 16 * nt + rl] : 0.0;
     }
   }
 }
 
-__device__ __forceinline__ void store_dl(GLB double *__restrict__ X, int64_t row0, int64_t n, int LP,
-                                         const v4d (&D)[4]) {
+template <int LP>
+__device__ __forceinline__ void store_dl(GLB double *__restrict__ X, int64_t row0, int64_t n, const v4d (&D)[4]) {
+  constexpr int NT = LP / 16;
   const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
-  const int NT = LP >> 4;
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
+  for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int64_t row = row0 + q + 4 * v;
-      if (nt < NT && row < n) X[row * LP + 16 * nt + rl] = D[nt][v];
+      if (row < n) X[row * LP + 16 * nt + rl] = D[nt][v];
     }
   }
 }
@@ -140,19 +138,18 @@ __device__ __forceinline__ void gram_tile(int tau, int NT, int nfull, int &mat, 
 
 // Stages the wave's panels (Q part and new part, D layout) and accumulates
 // this wave's Gram tiles over the 64 rows of the chunk.
-__device__ __forceinline__ void gram_chunk(const v4d (&Xd)[4], const v4d (&Yd)[4], int LP, int nfull, int ntile,
-                                           double *Xs, double *Ys, v4d (&acc)[kMaxTiles]) {
+template <int LP>
+__device__ __forceinline__ void gram_chunk(const v4d (&Xd)[4], const v4d (&Yd)[4], int nfull, int ntile, double *Xs,
+                                           double *Ys, v4d (&acc)[kMaxTiles]) {
+  constexpr int NT = LP / 16, PS = (LP == 16) ? 16 : LP + 16;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
-  const int NT = LP >> 4, PS = panel_stride(LP);
 #pragma unroll
-  for (int nt = 0; nt < 4; ++nt) {
+  for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      if (nt < NT) {
-        const int rr = 16 * w + q + 4 * v;
-        if (nfull) Xs[rr * PS + 16 * nt + rl] = Xd[nt][v];
-        Ys[rr * PS + 16 * nt + rl] = Yd[nt][v];
-      }
+      const int rr = 16 * w + q + 4 * v;
+      if (nfull) Xs[rr * PS + 16 * nt + rl] = Xd[nt][v];
+      Ys[rr * PS + 16 * nt + rl] = Yd[nt][v];
     }
   }
   __syncthreads();
@@ -208,18 +205,20 @@ __device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, in
 // mode kTallGamma0: Y = X R1^-1 - Q_k T (init: no Q term); Gram Y^T Y.
 enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
 
+template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__ jobs, int njob,
                                                     const int *__restrict__ toff, const int64_t *__restrict__ clock,
                                                     int mode, int grams, int init) {
-  __shared__ double S1[kBlockMaxLp * kSS], S2[kBlockMaxLp * kSS];
+  __shared__ double S1[LP * kSS], S2[LP * kSS];
   __shared__ double Xs[kPanel * kPSMax], Ys[kPanel * kPSMax];
+  constexpr int L2 = LP * LP, NT = LP / 16;
   const int g = blockIdx.x;
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
+  if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
   const int vb = g - toff[j];
-  const int LP = J.Lp, L2 = LP * LP, NT = LP >> 4;
   const int t = threadIdx.x, w = t >> 6;
   const int64_t n = J.n, nL = n * LP;
   GLB double *X = init ? gp(J.Vpad) : gp(J.W);
@@ -245,17 +244,17 @@ __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__
     v4d D[4];
     if (mode == kTallGamma0) {
       zero4(D);
-      panel_mm(X, r0, n, LP, S1, D);
+      panel_mm<LP>(X, r0, n, S1, D);
     } else {
-      load_dl(X, r0, n, LP, D);
+      load_dl<LP>(X, r0, n, D);
     }
-    if (useQ) panel_mm(mode == kTallAlpha ? Pv : Qc, r0, n, LP, S2, D);
-    if (mode == kTallAlpha && useQ) store_dl(X, r0, n, LP, D);
+    if (useQ) panel_mm<LP>(mode == kTallAlpha ? Pv : Qc, r0, n, S2, D);
+    if (mode == kTallAlpha && useQ) store_dl<LP>(X, r0, n, D);
     if (grams) {
       v4d Qd[4];
-      if (nfull && !init) load_dl(Qc, r0, n, LP, Qd);
-      else zero4(Qd);
-      gram_chunk(Qd, D, LP, nfull, ntile, Xs, Ys, acc);
+      zero4(Qd);
+      if (nfull && !init) load_dl<LP>(Qc, r0, n, Qd);
+      gram_chunk<LP>(Qd, D, nfull, ntile, Xs, Ys, acc);
     }
   }
   if (grams) store_gram(J, vb, nfull, ntile, acc);
@@ -263,18 +262,20 @@ __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__
 
 // ------------------------------------------------------------------ gamma
 // Q_{k+1} = W' M_k - Q_k N_k; init = 1: Q_0 = Vpad M_init.
+template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff, const int64_t *__restrict__ clock,
                                                      int init) {
-  __shared__ double S1[kBlockMaxLp * kSS], S2[kBlockMaxLp * kSS];
+  __shared__ double S1[LP * kSS], S2[LP * kSS];
+  constexpr int L2 = LP * LP;
   const int g = blockIdx.x;
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
+  if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
   const int vb = g - toff[j];
-  const int LP = J.Lp, L2 = LP * LP;
-  const int t = threadIdx.x, w = t >> 6;
+  const int w = threadIdx.x >> 6;
   const int64_t n = J.n, nL = n * LP;
   const GLB double *X = init ? gp(J.Vpad) : gp(J.W);
   const GLB double *Qc = gp(J.Q) + (int64_t)(k % 3) * nL;
@@ -286,11 +287,10 @@ __global__ __launch_bounds__(kThreads) void bs_gamma(const BJobDesc *__restrict_
     const int64_t r0 = (int64_t)ch * kPanel + 16 * w;
     v4d D[4];
     zero4(D);
-    panel_mm(X, r0, n, LP, S1, D);
-    if (!init) panel_mm(Qc, r0, n, LP, S2, D);
-    store_dl(Qn, r0, n, LP, D);
+    panel_mm<LP>(X, r0, n, S1, D);
+    if (!init) panel_mm<LP>(Qc, r0, n, S2, D);
+    store_dl<LP>(Qn, r0, n, D);
   }
-  (void)t;
 }
 
 // ----------------------------------------------------------------- reduce
@@ -495,14 +495,28 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
 }
 
 // ---------------------------------------------------------------- launchers
+// one launch per block width present in the batch (blocks of jobs of another
+// width return at once)
 hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st) {
-  hipLaunchKernelGGL(bs_tall, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode, grams,
-                     init);
+  if (b.lpmask & 1)
+    hipLaunchKernelGGL(bs_tall<16>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
+                       grams, init);
+  if (b.lpmask & 2)
+    hipLaunchKernelGGL(bs_tall<32>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
+                       grams, init);
+  if (b.lpmask & 4)
+    hipLaunchKernelGGL(bs_tall<64>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
+                       grams, init);
   return hipGetLastError();
 }
 
 hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st) {
-  hipLaunchKernelGGL(bs_gamma, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+  if (b.lpmask & 1)
+    hipLaunchKernelGGL(bs_gamma<16>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+  if (b.lpmask & 2)
+    hipLaunchKernelGGL(bs_gamma<32>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+  if (b.lpmask & 4)
+    hipLaunchKernelGGL(bs_gamma<64>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
   return hipGetLastError();
 }
 
