@@ -119,131 +119,264 @@ hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st) {
 }
 
 // ------------------------------------------------------ per-shift block LU
-// One block per (job, shift).  H in LDS (complex, stride Lp+1), inverted in
-// place by Gauss-Jordan elimination without pivoting.
+// One workgroup per (job, shift).  The four products of a step run on FP64
+// MFMA (16x16x4) with operands staged in LDS; each wave owns a 16-row band
+// of the Lp x Lp result in the MFMA output layout: lane l holds rows
+// 16 w + l/16 + 4 v (v < 4) of the 16-column tiles tj, column 16 tj + l%16.
+// H_k is inverted in that register layout by Gauss-Jordan elimination
+// without pivoting (Im H_k is positive definite); the pivot row and column
+// of each elimination step are broadcast through double-buffered LDS, one
+// barrier per step.  All Lp columns of Z are carried (the first L are the
+// right-hand sides).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma4b(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int LP>
 __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__ jobs, int njob,
                                                     const int *__restrict__ toffs, const int64_t *__restrict__ clock,
                                                     int init) {
-  __shared__ double2 H[kBlockMaxLp * (kBlockMaxLp + 1)];
-  __shared__ double2 colk[kBlockMaxLp];
+  constexpr int NT = LP / 16, KS = LP / 4, L2 = LP * LP, SS = LP + 1;
+  __shared__ double LB[LP * SS];
+  __shared__ double Pr[LP * SS], Pi[LP * SS];
+  __shared__ double2 rowb[2][LP], colb[2][LP];
+  __shared__ double rsum[4][LP];
   const int g = blockIdx.x;
   const int j = bfind(toffs, njob, g);
   const BJobDesc &J = jobs[j];
+  if (J.Lp != LP) return;
   const int s = g - toffs[j];
-  const int Lp = J.Lp, L2 = Lp * Lp, L = J.L;
-  const int ld = Lp + 1;
-  const int t = threadIdx.x;
+  const int L = J.L;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
   const int64_t hbase = (int64_t)s * (J.Kcap + 1) * L2;
   GLB double2 *__restrict__ Hinv = gp(J.Hinv) + hbase;
   GLB double2 *__restrict__ Zh = gp(J.Zh) + hbase;
-  GLB double2 *__restrict__ T1 = gp(J.ctmp) + (int64_t)s * 2 * L2;
-  GLB double2 *__restrict__ T2 = T1 + L2;
   if (init) {
     for (int e = t; e < L2; e += kThreads) Zh[e] = make_double2(gp(J.Bh)[e], 0.0);  // Z_0 = R_0
     return;
   }
+  const bool act = w < NT;
   const double2 z = gp(J.shift)[s];
   const GLB double *__restrict__ Ak = gp(J.Ah) + (int64_t)k * L2;
   const GLB double *__restrict__ Bk = gp(J.Bh) + (int64_t)k * L2;
   const GLB double *__restrict__ Bk1 = gp(J.Bh) + (int64_t)(k + 1) * L2;
+  // ---- stage B_k and H_{k-1}^{-1}
+  for (int e = t; e < L2; e += kThreads) LB[(e / LP) * SS + (e % LP)] = Bk[e];
   if (k > 0) {
-    // T1 = Hinv_{k-1} B_k^T
     const GLB double2 *__restrict__ Hp = Hinv + (int64_t)(k - 1) * L2;
     for (int e = t; e < L2; e += kThreads) {
-      const int i = e / Lp, jj = e - i * Lp;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int c = 0; c < Lp; ++c) {
-        const double bv = Bk[jj * Lp + c];
-        const double2 h = Hp[i * Lp + c];
-        acc.x = fma(h.x, bv, acc.x);
-        acc.y = fma(h.y, bv, acc.y);
-      }
-      T1[e] = acc;
+      const double2 h = Hp[e];
+      Pr[(e / LP) * SS + (e % LP)] = h.x;
+      Pi[(e / LP) * SS + (e % LP)] = h.y;
     }
-    __syncthreads();
   }
-  for (int e = t; e < L2; e += kThreads) {
-    const int i = e / Lp, jj = e - i * Lp;
-    double2 h = make_double2((i == jj ? z.x : 0.0) - Ak[e], (i == jj) ? z.y : 0.0);
+  __syncthreads();
+  v4d Dr[4], Di[4];
+  // ---- T1 = H_{k-1}^{-1} B_k^T
+  if (k > 0 && act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) Dr[tj] = Di[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + q;
+      const double ar = Pr[(16 * w + rl) * SS + c], ai = Pi[(16 * w + rl) * SS + c];
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const double b = LB[(16 * tj + rl) * SS + c];  // (B^T)(c, 16 tj + rl)
+        Dr[tj] = mfma4b(ar, b, Dr[tj]);
+        Di[tj] = mfma4b(ai, b, Di[tj]);
+      }
+    }
+  }
+  __syncthreads();
+  if (k > 0 && act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + q + 4 * v, jj = 16 * tj + rl;
+        Pr[i * SS + jj] = Dr[tj][v];
+        Pi[i * SS + jj] = Di[tj][v];
+      }
+  }
+  __syncthreads();
+  // ---- H = z I - A_k - B_k T1
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + q + 4 * v, jj = 16 * tj + rl;
+        Dr[tj][v] = (i == jj ? z.x : 0.0) - Ak[i * LP + jj];
+        Di[tj][v] = (i == jj ? z.y : 0.0);
+      }
     if (k > 0) {
-      for (int c = 0; c < Lp; ++c) {
-        const double bv = Bk[i * Lp + c];
-        const double2 tv = T1[c * Lp + jj];
-        h.x = fma(-bv, tv.x, h.x);
-        h.y = fma(-bv, tv.y, h.y);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int c = 4 * ks + q;
+        const double a = -LB[(16 * w + rl) * SS + c];
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) {
+          Dr[tj] = mfma4b(a, Pr[c * SS + 16 * tj + rl], Dr[tj]);
+          Di[tj] = mfma4b(a, Pi[c * SS + 16 * tj + rl], Di[tj]);
+        }
       }
     }
-    H[i * ld + jj] = h;
+    // pivot row and column 0
+    if (w == 0 && q == 0)
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) rowb[0][16 * tj + rl] = make_double2(Dr[tj][0], Di[tj][0]);
+    if (rl == 0)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) colb[0][16 * w + q + 4 * v] = make_double2(Dr[0][v], Di[0][v]);
   }
   __syncthreads();
-  // Gauss-Jordan inverse in place
-  for (int c = 0; c < Lp; ++c) {
-    const double2 piv = H[c * ld + c];
-    const double2 inv = cdivb(make_double2(1.0, 0.0), piv);
-    if (t < Lp) colk[t] = H[t * ld + c];
-    __syncthreads();
-    if (t < Lp) H[c * ld + t] = (t == c) ? inv : cmulb(H[c * ld + t], inv);
-    __syncthreads();
-    for (int e = t; e < L2; e += kThreads) {
-      const int i = e / Lp, jj = e - i * Lp;
-      if (i == c) continue;
-      const double2 f = colk[i];
-      if (jj == c) {
-        const double2 v = cmulb(f, inv);
-        H[i * ld + jj] = make_double2(-v.x, -v.y);
-      } else {
-        const double2 r = cmulb(f, H[c * ld + jj]);
-        H[i * ld + jj] = make_double2(H[i * ld + jj].x - r.x, H[i * ld + jj].y - r.y);
+  // ---- Gauss-Jordan inverse in registers
+#pragma unroll
+  for (int c = 0; c < LP; ++c) {
+    const int cb = c & 1;
+    const double2 p = colb[cb][c];
+    const double den = p.x * p.x + p.y * p.y;
+    const double2 inv = make_double2(p.x / den, -p.y / den);
+    if (act) {
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const int jj = 16 * tj + rl;
+        const double2 rj = rowb[cb][jj];
+        const double2 gj = cmulb(rj, inv);  // scaled pivot row entry
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = 16 * w + q + 4 * v;
+          const double2 f = colb[cb][i];
+          double2 h = make_double2(Dr[tj][v], Di[tj][v]);
+          if (i == c && jj == c) {
+            h = inv;
+          } else if (i == c) {
+            h = gj;
+          } else if (jj == c) {
+            const double2 fi = cmulb(f, inv);
+            h = make_double2(-fi.x, -fi.y);
+          } else {
+            const double2 d = cmulb(f, gj);
+            h = make_double2(h.x - d.x, h.y - d.y);
+          }
+          Dr[tj][v] = h.x;
+          Di[tj][v] = h.y;
+        }
+      }
+      if (c + 1 < LP) {
+        const int c1 = c + 1;
+        if (w == c1 / 16 && q == (c1 & 3))
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj)
+            rowb[cb ^ 1][16 * tj + rl] = make_double2(Dr[tj][(c1 & 15) >> 2], Di[tj][(c1 & 15) >> 2]);
+        if (rl == (c1 & 15))
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            colb[cb ^ 1][16 * w + q + 4 * v] = make_double2(Dr[c1 >> 4][v], Di[c1 >> 4][v]);
       }
     }
     __syncthreads();
   }
+  // ---- store H_k^{-1}; stage it for the next product
   GLB double2 *__restrict__ Hk = Hinv + (int64_t)k * L2;
-  for (int e = t; e < L2; e += kThreads) Hk[e] = H[(e / Lp) * ld + (e % Lp)];
-  // T2 = Hinv_k Z_k (columns < L), Z_{k+1} = B_{k+1} T2
-  const GLB double2 *__restrict__ Zk = Zh + (int64_t)k * L2;
-  for (int e = t; e < Lp * L; e += kThreads) {
-    const int i = e / L, jj = e - i * L;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int c = 0; c < Lp; ++c) {
-      const double2 r = cmulb(H[i * ld + c], Zk[c * Lp + jj]);
-      acc.x += r.x;
-      acc.y += r.y;
-    }
-    T2[i * Lp + jj] = acc;
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + q + 4 * v, jj = 16 * tj + rl;
+        Hk[i * LP + jj] = make_double2(Dr[tj][v], Di[tj][v]);
+        Pr[i * SS + jj] = Dr[tj][v];
+        Pi[i * SS + jj] = Di[tj][v];
+      }
   }
   __syncthreads();
-  GLB double2 *__restrict__ Zn = Zh + (int64_t)(k + 1) * L2;
-  for (int e = t; e < Lp * L; e += kThreads) {
-    const int i = e / L, jj = e - i * L;
-    double2 acc = make_double2(0.0, 0.0);
-    for (int c = i; c < Lp; ++c) {  // B_{k+1} is upper triangular
-      const double bv = Bk1[i * Lp + c];
-      const double2 tv = T2[c * Lp + jj];
-      acc.x = fma(bv, tv.x, acc.x);
-      acc.y = fma(bv, tv.y, acc.y);
+  // ---- T2 = H_k^{-1} Z_k
+  const GLB double2 *__restrict__ Zk = Zh + (int64_t)k * L2;
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) Dr[tj] = Di[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + q;
+      const double ar = Pr[(16 * w + rl) * SS + c], ai = Pi[(16 * w + rl) * SS + c];
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const double2 zz = Zk[c * LP + 16 * tj + rl];
+        Dr[tj] = mfma4b(ar, zz.x, Dr[tj]);
+        Dr[tj] = mfma4b(-ai, zz.y, Dr[tj]);
+        Di[tj] = mfma4b(ar, zz.y, Di[tj]);
+        Di[tj] = mfma4b(ai, zz.x, Di[tj]);
+      }
     }
-    Zn[i * Lp + jj] = acc;
+  }
+  __syncthreads();
+  for (int e = t; e < L2; e += kThreads) LB[(e / LP) * SS + (e % LP)] = Bk1[e];
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + q + 4 * v, jj = 16 * tj + rl;
+        Pr[i * SS + jj] = Dr[tj][v];
+        Pi[i * SS + jj] = Di[tj][v];
+      }
+  }
+  __syncthreads();
+  // ---- Z_{k+1} = B_{k+1} T2 and the residual norms of the first L columns
+  GLB double2 *__restrict__ Zn = Zh + (int64_t)(k + 1) * L2;
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) Dr[tj] = Di[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int c = 4 * ks + q;
+      const double a = LB[(16 * w + rl) * SS + c];
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        Dr[tj] = mfma4b(a, Pr[c * SS + 16 * tj + rl], Dr[tj]);
+        Di[tj] = mfma4b(a, Pi[c * SS + 16 * tj + rl], Di[tj]);
+      }
+    }
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) {
+      double ss = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + q + 4 * v, jj = 16 * tj + rl;
+        Zn[i * LP + jj] = make_double2(Dr[tj][v], Di[tj][v]);
+        ss += Dr[tj][v] * Dr[tj][v] + Di[tj][v] * Di[tj][v];
+      }
+      ss += __shfl_xor(ss, 16);
+      ss += __shfl_xor(ss, 32);
+      if (q == 0) rsum[w][16 * tj + rl] = ss;
+    }
   }
   __syncthreads();
   if (t < L) {
     double nr = 0.0;
-    for (int i = 0; i < Lp; ++i) {
-      const double2 v = Zn[i * Lp + t];
-      nr += v.x * v.x + v.y * v.y;
-    }
+#pragma unroll
+    for (int ww = 0; ww < NT; ++ww) nr += rsum[ww][t];
     const double b0 = gp(J.beta0)[t];
     const double r = b0 > 0.0 ? sqrt(nr) / b0 : 0.0;
-    gp(J.res)[(int64_t)s * Lp + t] = r;
+    gp(J.res)[(int64_t)s * LP + t] = r;
     if (r > J.tol) atomicAdd(gp(J.active) + (k & 1), 1);
   }
   if (s == 0 && t == 0) gp(J.active)[(k + 1) & 1] = 0;
 }
 
 hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st) {
-  hipLaunchKernelGGL(b_shift, dim3(b.totals), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffs, b.clock, init);
+  if (b.lpmask & 1)
+    hipLaunchKernelGGL(b_shift<16>, dim3(b.totals), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffs, b.clock, init);
+  if (b.lpmask & 2)
+    hipLaunchKernelGGL(b_shift<32>, dim3(b.totals), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffs, b.clock, init);
+  if (b.lpmask & 4)
+    hipLaunchKernelGGL(b_shift<64>, dim3(b.totals), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffs, b.clock, init);
   return hipGetLastError();
 }
 
