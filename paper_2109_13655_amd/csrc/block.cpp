@@ -15,7 +15,7 @@ size_t BlockJob::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, 
   const int64_t nvb = std::min<int64_t>((n + kBlockPanel - 1) / kBlockPanel, kBlockMaxVB);
   size_t b = 0;
   b += 8 * (size_t)(m * Lp);                       // U
-  b += 8 * (size_t)(5 * n * Lp);                   // Q ring, W, Vpad
+  b += 8 * (size_t)((kMomWindow + 2 + 2) * n * Lp);  // Q ring, W, Vpad
   b += 8 * (size_t)(nvb * 2 * L2);                 // partial Gram matrices
   b += 8 * (size_t)(7 * L2);                       // reduced Gram matrices, R1, R1^-1, T
   b += 8 * (size_t)(4 * (Kcap + 1) * L2);          // A, B, M, N histories
@@ -59,7 +59,8 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.cstride = cstride;
   J.tol = tol;
   J.U = (double *)take(8 * (size_t)(m * Lp));
-  J.Q = (double *)take(8 * (size_t)(3 * n * Lp));
+  J.nring = kMomWindow + 2;
+  J.Q = (double *)take(8 * (size_t)(J.nring * n * Lp));
   J.W = (double *)take(8 * (size_t)(n * Lp));
   J.Vpad = (double *)take(8 * (size_t)(n * Lp));
   J.gpart = (double *)take(8 * (size_t)(J.nvb * 2 * L2));
@@ -168,7 +169,7 @@ hipError_t BEngine::start(BlockJob *j) {
   j->pass = 1;
   j->converged = false;
   j->K = 0;
-  hipError_t e = hipMemsetAsync(J.Q, 0, 8 * (size_t)3 * J.n * J.Lp, st_);
+  hipError_t e = hipMemsetAsync(J.Q, 0, 8 * (size_t)J.nring * J.n * J.Lp, st_);
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(J.active, 0, 16, st_);
   if (e != hipSuccess) return e;
@@ -195,10 +196,11 @@ hipError_t BEngine::enter_pass2(BlockJob *j) {
   if (e != hipSuccess) return e;
   if ((e = launch_b_fcoef(J, j->K, st_)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(J.Sout, 0, 8 * (size_t)J.npad * J.Kmom * J.L, st_)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(J.Q, 0, 8 * (size_t)3 * J.n * J.Lp, st_)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(J.Q, 0, 8 * (size_t)J.nring * J.n * J.Lp, st_)) != hipSuccess) return e;
   J.start_clock = (int)clock_;
   J.Kstop = j->K;
   j->pass = 2;
+  j->mflushed = 0;
   if ((e = j->sync_desc(st_)) != hipSuccess) return e;
   BBatch b = j->solo;
   b.clock = d_clock_.as<int64_t>();
@@ -287,16 +289,14 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
       dirty2_ = false;
     }
     const BBatch &b = b2_;
-    // moments first: Sout += Q_k F_k uses Q_k before the slot is reused
+    // moments of the last window: S += sum Q_k F_k over kMomWindow steps,
+    // before the ring slots of that window are reused
     for (BlockJob *j : p2_) {
-      const BJobDesc &J = j->h;
-      const int k = (int)(clock_ - J.start_clock);
-      if (k >= j->K) continue;
-      const int64_t nL = (int64_t)J.n * J.Lp;
-      const int KL = J.Kmom * J.L;
-      if ((e = launch_gemm_ta(J.n, KL, J.Lp, 1.0, J.Q + (int64_t)(k % 3) * nL, J.Lp,
-                              J.F + (int64_t)k * KL * J.Lp, J.Lp, 1.0, J.Sout, J.npad, st_)) != hipSuccess)
-        return e;
+      const int k = (int)(clock_ - j->h.start_clock);
+      if (k <= j->K && k - j->mflushed == kMomWindow) {
+        if ((e = launch_b_moments(j->h, j->mflushed, kMomWindow, st_)) != hipSuccess) return e;
+        j->mflushed = k;
+      }
     }
     if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
@@ -347,6 +347,12 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
   for (BlockJob *j : p2_) {
     const int steps = (int)(clock_ - j->h.start_clock);
     if (steps >= j->K) {
+      // the rest of the last window (steps past K did no work, so the ring
+      // still holds it)
+      if (j->mflushed < j->K &&
+          (e = launch_b_moments(j->h, j->mflushed, j->K - j->mflushed, st_)) != hipSuccess)
+        return e;
+      j->mflushed = j->K;
       j->pass = 3;
       finished->push_back(j);
       dirty2_ = true;

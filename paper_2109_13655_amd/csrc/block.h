@@ -21,6 +21,7 @@ struct BlockJob {
   bool converged = false;
   int64_t steps_total = 0; // over all passes and rounds
   int64_t steps_last = 0;  // pass-1 steps of the last round
+  int mflushed = 0;        // second-pass steps whose moments are already in Sout
   static size_t bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int Kcap, int L, int Kmom);
   hipError_t create(const int *rp, const int *ci, const double *va, const int *rpT, const int *ciT,
                     const double *vaT, int64_t m, int64_t n, int64_t nnz, int L, int Lp, int S, int Kcap, int Kmom,

@@ -101,6 +101,7 @@ struct BJobDesc {
   int G2, lgG2, E2, rpt2, tiles2;  // tiling of the A^T product (n rows)
   int nchunk;                      // 64-row chunks of the tall kernels
   int nvb;                         // workgroups per tall kernel (each walks chunks vb, vb + nvb, ...)
+  int nring;                       // slots of the basis ring: Q_k in slot k mod nring
   int Kcap;                        // capacity of the per-step histories
   int Kstop;                       // steps of the current pass that do work (later steps are no-ops)
   int start_clock;                 // engine clock of step 0 of the current pass
@@ -109,7 +110,7 @@ struct BJobDesc {
   double tol;
   double dscale;                   // ||A||^2 estimate: scale of the deflation test
   double *U;                       // m x Lp
-  double *Q;                       // 3 x (n x Lp): slot (k mod 3) holds Q_k
+  double *Q;                       // nring x (n x Lp): slot (k mod nring) holds Q_k
   double *W;                       // n x Lp work block
   double *Vpad;                    // n x Lp: the padded starting block
   double *gpart;                   // nvb x 2 x Lp x Lp partial Gram matrices
@@ -141,10 +142,14 @@ constexpr int kBlockMaxLp = 64;   // widest block of the block Lanczos engine
 constexpr int kBlockMinLp = 16;   // narrowest (MFMA tile width)
 constexpr int kBlockPanel = 64;   // rows per chunk of the tall kernels
 constexpr int kBlockMaxVB = 256;  // workgroups per job in the tall kernels
+constexpr int kMomWindow = 16;   // second-pass steps per moment accumulation (basis ring = window + 2)
 constexpr double kDeflTol = 1e-10;  // relative size below which a new basis direction is deflated
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);
 hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st);
+// S += sum_{b < T} Q_{k0+b} F_{k0+b} for one job (second pass): the basis
+// blocks are read from the ring, F from the coefficient history
+hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st);
 // Tall kernels of one block step (see k_bstep.hip).  mode 0 (alpha): W' =
 // W - Q_{k-1} B_k^T and (grams = 1) the partial Gram matrix Q_k^T W'; mode 1
 // (beta): partial Gram matrices of W2 = W' - Q_k P; mode 2 (gamma0): partial

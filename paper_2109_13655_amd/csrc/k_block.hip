@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict_
     const int k = (int)(ck - J.start_clock);
     if (k >= J.Kstop) continue;
     const int64_t nL = (int64_t)J.n * J.Lp;
-    tile_spmm(gp(J.rp), gp(J.ci), gp(J.va), gp(J.Q) + (int64_t)(k % 3) * nL, gp(J.U), J.m, g - toff[j], J.rpt1,
+    tile_spmm(gp(J.rp), gp(J.ci), gp(J.va), gp(J.Q) + (int64_t)(k % J.nring) * nL, gp(J.U), J.m, g - toff[j], J.rpt1,
               J.lgLp, J.G1, J.lgG1, J.E1, gsum);
   }
 }
@@ -134,6 +134,15 @@ __device__ __forceinline__ v4d mfma4b(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// element v of a v4d / tile tj of a 4-tile array with runtime indexes
+// (select chains: no scratch, no code growth)
+__device__ __forceinline__ double pick4b(const v4d &x, int v) {
+  return v == 0 ? x[0] : (v == 1 ? x[1] : (v == 2 ? x[2] : x[3]));
+}
+__device__ __forceinline__ double pick_tile(const v4d (&x)[4], int tj, int v) {
+  return tj == 0 ? x[0][v] : (tj == 1 ? x[1][v] : (tj == 2 ? x[2][v] : x[3][v]));
+}
+
 template <int LP>
 __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__ jobs, int njob,
                                                     const int *__restrict__ toffs, const int64_t *__restrict__ clock,
@@ -165,13 +174,29 @@ __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__
   const GLB double *__restrict__ Bk = gp(J.Bh) + (int64_t)k * L2;
   const GLB double *__restrict__ Bk1 = gp(J.Bh) + (int64_t)(k + 1) * L2;
   // ---- stage B_k and H_{k-1}^{-1}
-  for (int e = t; e < L2; e += kThreads) LB[(e / LP) * SS + (e % LP)] = Bk[e];
-  if (k > 0) {
-    const GLB double2 *__restrict__ Hp = Hinv + (int64_t)(k - 1) * L2;
-    for (int e = t; e < L2; e += kThreads) {
-      const double2 h = Hp[e];
-      Pr[(e / LP) * SS + (e % LP)] = h.x;
-      Pi[(e / LP) * SS + (e % LP)] = h.y;
+  constexpr int IT = (L2 + kThreads - 1) / kThreads;
+  {
+    double bv[IT];
+    double2 hv[IT];
+    const GLB double2 *__restrict__ Hp = Hinv + (int64_t)(k > 0 ? k - 1 : 0) * L2;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      bv[it] = (e < L2) ? Bk[e] : 0.0;
+      hv[it] = make_double2(0.0, 0.0);
+      if (e < L2 && k > 0) {
+        const double2 h = Hp[e];
+        hv[it] = h;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      if (e < L2) {
+        LB[(e / LP) * SS + (e % LP)] = bv[it];
+        Pr[(e / LP) * SS + (e % LP)] = hv[it].x;
+        Pi[(e / LP) * SS + (e % LP)] = hv[it].y;
+      }
     }
   }
   __syncthreads();
@@ -236,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__
   }
   __syncthreads();
   // ---- Gauss-Jordan inverse in registers
-#pragma unroll
+#pragma unroll 1
   for (int c = 0; c < LP; ++c) {
     const int cb = c & 1;
     const double2 p = colb[cb][c];
@@ -270,14 +295,15 @@ __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__
       }
       if (c + 1 < LP) {
         const int c1 = c + 1;
+        const int vv = (c1 & 15) >> 2, tc = c1 >> 4;
         if (w == c1 / 16 && q == (c1 & 3))
 #pragma unroll
           for (int tj = 0; tj < NT; ++tj)
-            rowb[cb ^ 1][16 * tj + rl] = make_double2(Dr[tj][(c1 & 15) >> 2], Di[tj][(c1 & 15) >> 2]);
+            rowb[cb ^ 1][16 * tj + rl] = make_double2(pick4b(Dr[tj], vv), pick4b(Di[tj], vv));
         if (rl == (c1 & 15))
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            colb[cb ^ 1][16 * w + q + 4 * v] = make_double2(Dr[c1 >> 4][v], Di[c1 >> 4][v]);
+            colb[cb ^ 1][16 * w + q + 4 * v] = make_double2(pick_tile(Dr, tc, v), pick_tile(Di, tc, v));
       }
     }
     __syncthreads();
@@ -316,7 +342,19 @@ __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__
     }
   }
   __syncthreads();
-  for (int e = t; e < L2; e += kThreads) LB[(e / LP) * SS + (e % LP)] = Bk1[e];
+  {
+    double bv[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      bv[it] = (e < L2) ? Bk1[e] : 0.0;
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      if (e < L2) LB[(e / LP) * SS + (e % LP)] = bv[it];
+    }
+  }
   if (act) {
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj)
@@ -400,7 +438,24 @@ __global__ __launch_bounds__(kThreads) void b_backsolve(BJobDesc J, int K) {
   GLB double2 *__restrict__ Zh = gp(J.Zh) + hbase;
   for (int k = K - 1; k >= 0; --k) {
     const GLB double2 *__restrict__ Hk = Hinv + (int64_t)k * L2;
-    for (int e = t; e < L2; e += kThreads) Hs[e] = Hk[e];
+    {
+      constexpr int IT = kBlockMaxLp * kBlockMaxLp / kThreads;
+      double2 hv[IT];
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = t + it * kThreads;
+        hv[it] = make_double2(0.0, 0.0);
+        if (e < L2) {
+          const double2 h = Hk[e];
+          hv[it] = h;
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < IT; ++it) {
+        const int e = t + it * kThreads;
+        if (e < L2) Hs[e] = hv[it];
+      }
+    }
     // T = Z_k + B_{k+1}^T Y_{k+1} for this thread's rows
     const GLB double *__restrict__ Bk1 = gp(J.Bh) + (int64_t)(k + 1) * L2;
     for (int i = t >> 4; i < Lp; i += kThreads / kBsCols) {
@@ -463,6 +518,96 @@ hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st) {
   if (g > 16384) g = 16384;
   if (g < 1) g = 1;
   hipLaunchKernelGGL(b_fcoef, dim3((unsigned)g), dim3(256), 0, st, hj, K);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ moment accumulation
+// S(r, col) += sum_b sum_c Q_{k0+b}(r, c) F_{k0+b}(c, col), S column-major
+// (ld npad), F column-major per step (Lp x KL).  Workgroup: 64 rows x 192
+// columns; each wave a 16-row panel (MFMA 16x16x4, contraction index split
+// as in the tall kernels), F_b slices staged in LDS, the result added to S
+// through an LDS transpose so that each column segment is written whole.
+constexpr int kMomCols = 192;
+
+template <int LP>
+__global__ __launch_bounds__(kThreads) void b_moments(BJobDesc J, int k0, int T) {
+  constexpr int KS = LP / 4, NTL = kMomCols / 16, FS = kMomCols + 1;
+  __shared__ double Fs[LP * FS];
+  __shared__ double Cs[64 * 65];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const int64_t n = J.n, nL = n * LP;
+  const int KL = J.Kmom * J.L;
+  const int64_t rb = (int64_t)blockIdx.x * 64, r0 = rb + 16 * w;
+  const int col0 = blockIdx.y * kMomCols;
+  v4d acc[NTL];
+#pragma unroll
+  for (int i = 0; i < NTL; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < T; ++b) {
+    const int k = k0 + b;
+    const GLB double *__restrict__ Fk = gp(J.F) + (int64_t)k * KL * LP;
+    __syncthreads();
+    // F_b slice: LP x 192, loaded 16 entries per thread at a time so that the
+    // loads of a batch are all in flight before the LDS stores
+    constexpr int IT = LP * kMomCols / kThreads, BATCH = 16;
+#pragma unroll
+    for (int i0 = 0; i0 < IT; i0 += BATCH) {
+      double fv[BATCH];
+#pragma unroll
+      for (int i = 0; i < BATCH; ++i) {
+        const int e = t + (i0 + i) * kThreads;
+        const int col = e / LP, c = e % LP;
+        fv[i] = (i0 + i < IT && col0 + col < KL) ? Fk[(int64_t)(col0 + col) * LP + c] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < BATCH; ++i) {
+        const int e = t + (i0 + i) * kThreads;
+        if (i0 + i < IT) Fs[(e % LP) * FS + e / LP] = fv[i];
+      }
+    }
+    __syncthreads();
+    const GLB double *__restrict__ Qk = gp(J.Q) + (int64_t)(k % J.nring) * nL;
+    double a[KS];
+    const int64_t row = r0 + rl;
+#pragma unroll
+    for (int i = 0; i < KS; ++i) a[i] = (row < n) ? Qk[row * LP + q * KS + i] : 0.0;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const double *fr = Fs + (q * KS + ks) * FS + rl;
+#pragma unroll
+      for (int tt = 0; tt < NTL; ++tt) acc[tt] = mfma4b(a[ks], fr[16 * tt], acc[tt]);
+    }
+  }
+  // add to S in column segments of 64 rows: 64 columns at a time via LDS
+  for (int cg = 0; cg < kMomCols; cg += 64) {
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < NTL; ++tt) {
+      if (16 * tt >= cg && 16 * tt < cg + 64)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Cs[(16 * tt - cg + rl) * 65 + 16 * w + q + 4 * v] = acc[tt][v];
+    }
+    __syncthreads();
+    for (int e = t; e < 64 * 64; e += kThreads) {
+      const int cl = e >> 6, rr = e & 63;
+      const int col = col0 + cg + cl;
+      const int64_t row = rb + rr;
+      if (col < KL && row < n) {
+        GLB double *sp = gp(J.Sout) + (int64_t)col * J.npad + row;
+        *sp += Cs[cl * 65 + rr];
+      }
+    }
+  }
+}
+
+hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st) {
+  if (T <= 0) return hipSuccess;
+  const int KL = hj.Kmom * hj.L;
+  const dim3 g((unsigned)((hj.n + 63) / 64), (unsigned)((KL + kMomCols - 1) / kMomCols));
+  switch (hj.Lp) {
+    case 16: hipLaunchKernelGGL(b_moments<16>, g, dim3(kThreads), 0, st, hj, k0, T); break;
+    case 32: hipLaunchKernelGGL(b_moments<32>, g, dim3(kThreads), 0, st, hj, k0, T); break;
+    default: hipLaunchKernelGGL(b_moments<64>, g, dim3(kThreads), 0, st, hj, k0, T); break;
+  }
   return hipGetLastError();
 }
 

@@ -188,12 +188,22 @@ __device__ __forceinline__ void store_gram(const BJobDesc &J, int vb, int nfull,
   }
 }
 
-__device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, int LP, bool trans, bool neg,
-                                          double *dst) {
-  for (int e = threadIdx.x; e < LP * LP; e += kThreads) {
-    const int r = e / LP, c = e - r * LP;
-    const double v = trans ? src[c * LP + r] : src[e];
-    dst[r * kSS + c] = neg ? -v : v;
+// LP x LP matrix from global to LDS (stride kSS), optionally transposed or
+// negated; fixed trip count, all loads of a thread issued before its stores
+template <int LP>
+__device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, bool trans, bool neg, double *dst) {
+  constexpr int IT = (LP * LP + kThreads - 1) / kThreads;
+  double v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * kThreads;
+    const int r = e / LP, c = e % LP;
+    v[it] = (e < LP * LP) ? (trans ? src[c * LP + r] : src[e]) : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * kThreads;
+    if (e < LP * LP) dst[(e / LP) * kSS + (e % LP)] = neg ? -v[it] : v[it];
   }
 }
 
@@ -222,16 +232,16 @@ __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__
   const int t = threadIdx.x, w = t >> 6;
   const int64_t n = J.n, nL = n * LP;
   GLB double *X = init ? gp(J.Vpad) : gp(J.W);
-  const GLB double *Qc = gp(J.Q) + (int64_t)(k % 3) * nL;
-  const GLB double *Pv = gp(J.Q) + (int64_t)((k + 2) % 3) * nL;
+  const GLB double *Qc = gp(J.Q) + (int64_t)(k % J.nring) * nL;
+  const GLB double *Pv = gp(J.Q) + (int64_t)((k + J.nring - 1) % J.nring) * nL;
   const bool useQ = !init && (mode != kTallAlpha || k > 0);
   if (mode == kTallAlpha) {
-    if (useQ) stage_mat(gp(J.Bh) + (int64_t)k * L2, LP, true, true, S2);  // -B_k^T
+    if (useQ) stage_mat<LP>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
   } else if (mode == kTallBeta) {
-    if (useQ) stage_mat(gp(J.red), LP, false, true, S2);  // -P
+    if (useQ) stage_mat<LP>(gp(J.red), false, true, S2);  // -P
   } else {
-    stage_mat(gp(J.scr) + L2, LP, false, false, S1);           // R1^-1
-    if (useQ) stage_mat(gp(J.scr) + 2 * L2, LP, false, true, S2);  // -T
+    stage_mat<LP>(gp(J.scr) + L2, false, false, S1);           // R1^-1
+    if (useQ) stage_mat<LP>(gp(J.scr) + 2 * L2, false, true, S2);  // -T
   }
   __syncthreads();
   const int nfull = (mode == kTallGamma0) ? 0 : NT * NT;
@@ -278,10 +288,10 @@ __global__ __launch_bounds__(kThreads) void bs_gamma(const BJobDesc *__restrict_
   const int w = threadIdx.x >> 6;
   const int64_t n = J.n, nL = n * LP;
   const GLB double *X = init ? gp(J.Vpad) : gp(J.W);
-  const GLB double *Qc = gp(J.Q) + (int64_t)(k % 3) * nL;
-  GLB double *Qn = gp(J.Q) + (int64_t)((init ? k : k + 1) % 3) * nL;
-  stage_mat(gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2, LP, false, false, S1);
-  if (!init) stage_mat(gp(J.Nh) + (int64_t)k * L2, LP, false, true, S2);
+  const GLB double *Qc = gp(J.Q) + (int64_t)(k % J.nring) * nL;
+  GLB double *Qn = gp(J.Q) + (int64_t)((init ? k : k + 1) % J.nring) * nL;
+  stage_mat<LP>(gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2, false, false, S1);
+  if (!init) stage_mat<LP>(gp(J.Nh) + (int64_t)k * L2, false, true, S2);
   __syncthreads();
   for (int ch = vb; ch < J.nchunk; ch += J.nvb) {
     const int64_t r0 = (int64_t)ch * kPanel + 16 * w;
@@ -321,177 +331,322 @@ __global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict
 }
 
 // ------------------------------------------------------- small matrices
-// Right-looking Cholesky of the symmetric matrix in A (LDS, stride kSS) in
-// place, upper factor.  A pivot <= thr[c] deflates column c: zero row in R.
-// Row c is scaled one phase late (phase c + 1) so that each phase needs a
-// single barrier.
-__device__ void chol_defl(double *A, int LP, const double *thr, int *dead) {
-  const int t = threadIdx.x;
-  int dprev = 1;
-  double invprev = 0.0, pivprev = 0.0;
-  for (int c = 0; c <= LP; ++c) {
-    if (c > 0) {
-      const int r = c - 1;
-      for (int jj = r + t; jj < LP; jj += kThreads)
-        A[r * kSS + jj] = (jj == r) ? pivprev : (dprev ? 0.0 : A[r * kSS + jj] * invprev);
-    }
-    if (c == LP) break;
-    const double d = A[c * kSS + c];
-    const int dd = !(d > thr[c]);
-    const double piv = dd ? 0.0 : sqrt(d);
-    const double inv = dd ? 0.0 : 1.0 / piv;
-    if (!dd) {
-      const int rem = LP - c - 1;
-      for (int e = t; e < rem * rem; e += kThreads) {
-        const int i = c + 1 + e / rem, jj = c + 1 + e % rem;
-        if (jj >= i) A[i * kSS + jj] -= (A[c * kSS + i] * inv) * (A[c * kSS + jj] * inv);
-      }
-    }
-    if (t == 0) dead[c] = dd;
-    dprev = dd;
-    invprev = inv;
-    pivprev = piv;
-    __syncthreads();
-  }
-  __syncthreads();
-}
-
-// X = R^+ for the upper factor R (zero rows at deflated columns): the inverse
-// on the kept rows and columns, zero elsewhere.  Thread c builds column c.
-__device__ void tri_inv(const double *R, int LP, const int *dead, double *X) {
-  const int t = threadIdx.x;
-  if (t < LP) {
-    const int c = t;
-    for (int i = LP - 1; i > c; --i) X[i * kSS + c] = 0.0;
-    for (int i = c; i >= 0; --i) {
-      double v = 0.0;
-      if (!dead[i] && !dead[c]) {
-        v = (i == c) ? 1.0 : 0.0;
-        for (int l2 = i + 1; l2 <= c; ++l2) v -= R[i * kSS + l2] * X[l2 * kSS + c];
-        v /= R[i * kSS + i];
-      }
-      X[i * kSS + c] = v;
-    }
-  }
-  __syncthreads();
-}
-
+// One workgroup per job.  Lp x Lp matrices live in registers in the MFMA
+// output layout (wave w < Lp/16 holds rows 16 w + l/16 + 4 v, columns
+// 16 tj + l%16); products run on MFMA from LDS operands; the Cholesky
+// factorisation and the triangular inverse advance one row per step with a
+// single barrier, the active row broadcast through double-buffered LDS.
+// D (+)= sign * A * B or sign * A^T * B with A, B in LDS (stride LP + 1)
 // G from the reduced upper tiles: entry (r, c) lives at (r, c) when the tile
 // of r is not below the tile of c, else at (c, r)
 __device__ __forceinline__ double gram_sym(const GLB double *G, int LP, int r, int c) {
   return ((r >> 4) <= (c >> 4)) ? G[r * LP + c] : G[c * LP + r];
 }
 
+template <int LP, bool TA>
+__device__ __forceinline__ void mm_lds(const double *A, const double *B, double sign, v4d (&D)[4]) {
+  constexpr int NT = LP / 16, KS = LP / 4, SS = LP + 1;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  if (w >= NT) return;
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int c = 4 * ks + q;
+    const double a = sign * (TA ? A[c * SS + 16 * w + rl] : A[(16 * w + rl) * SS + c]);
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) D[tj] = mfma4(a, B[c * SS + 16 * tj + rl], D[tj]);
+  }
+}
+
+template <int LP>
+__device__ __forceinline__ void regs_to_lds(const v4d (&D)[4], double *X) {
+  constexpr int NT = LP / 16, SS = LP + 1;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  if (w >= NT) return;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[(16 * w + q + 4 * v) * SS + 16 * tj + rl] = D[tj][v];
+}
+
+template <int LP>
+__device__ __forceinline__ void regs_to_glb(const v4d (&D)[4], GLB double *X) {
+  constexpr int NT = LP / 16;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  if (w >= NT) return;
+#pragma unroll
+  for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[(16 * w + q + 4 * v) * LP + 16 * tj + rl] = D[tj][v];
+}
+
+// LP x LP row-major global -> LDS (stride LP + 1); the trip count is fixed,
+// so all loads are issued before the first LDS store
+template <int LP>
+__device__ __forceinline__ void glb_to_lds(const GLB double *src, double *X, bool neg) {
+  constexpr int SS = LP + 1, IT = (LP * LP + kThreads - 1) / kThreads;
+  double v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * kThreads;
+    v[it] = (e < LP * LP) ? src[e] : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int e = threadIdx.x + it * kThreads;
+    if (e < LP * LP) X[(e / LP) * SS + (e % LP)] = neg ? -v[it] : v[it];
+  }
+}
+
+// element v of a v4d with a runtime index (select chain, no scratch)
+__device__ __forceinline__ double pick4(const v4d &x, int v) {
+  return v == 0 ? x[0] : (v == 1 ? x[1] : (v == 2 ? x[2] : x[3]));
+}
+__device__ __forceinline__ void put4(v4d &x, int v, double val) {
+  x[0] = v == 0 ? val : x[0];
+  x[1] = v == 1 ? val : x[1];
+  x[2] = v == 2 ? val : x[2];
+  x[3] = v == 3 ? val : x[3];
+}
+
+// Right-looking Cholesky (upper factor) of the symmetric matrix in D, in
+// place, with deflation: a pivot <= thr[c] zeroes row c of R.  rowb: 2 x LP.
+// Each step reads everything it needs from LDS up front and updates its 16
+// entries without branches (selects), so the step costs one LDS round trip
+// and one barrier.
+template <int LP>
+__device__ __forceinline__ void chol_regs(v4d (&D)[4], const double *thr, int *dead, double (*rowb)[kBlockMaxLp]) {
+  constexpr int NT = LP / 16;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const bool act = w < NT;
+  const int i0 = 16 * w + q;  // rows i0 + 4 v
+  if (act && w == 0 && q == 0)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) rowb[0][16 * tj + rl] = D[tj][0];
+  __syncthreads();
+#pragma unroll 1
+  for (int c = 0; c < LP; ++c) {
+    const int cb = c & 1;
+    const double d = rowb[cb][c];
+    const double th = thr[c];
+    double rjv[4], riv[4];
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) rjv[tj] = rowb[cb][16 * tj + rl];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) riv[v] = rowb[cb][act ? i0 + 4 * v : 0];
+    const int dd = !(d > th);
+    const double piv = dd ? 0.0 : sqrt(d);
+    const double ip = dd ? 0.0 : 1.0 / piv;
+    if (act) {
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const int jj = 16 * tj + rl;
+        const double rj = rjv[tj] * ip;
+        const double rowc = (jj < c) ? 0.0 : (jj == c ? piv : rj);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int i = i0 + 4 * v;
+          const double a = D[tj][v];
+          const double upd = a - (riv[v] * ip) * rj;
+          D[tj][v] = (i == c) ? rowc : ((i > c && jj > c) ? upd : a);
+        }
+      }
+      const int c1 = c + 1;
+      if (c1 < LP && w == c1 / 16 && q == (c1 & 3))
+#pragma unroll
+        for (int tj = 0; tj < NT; ++tj) rowb[cb ^ 1][16 * tj + rl] = pick4(D[tj], (c1 & 15) >> 2);
+    }
+    if (t == 0) dead[c] = dd;
+    __syncthreads();
+  }
+}
+
+// X = R^+ of the upper factor R (in LDS Rs, zero rows at deflated columns):
+// the inverse on the kept rows and columns, zero elsewhere, in the register
+// layout; rows from the bottom up, each finished row broadcast once.
+template <int LP>
+__device__ __forceinline__ void trinv_regs(const double *Rs, const int *dead, v4d (&X)[4],
+                                           double (*rowb)[kBlockMaxLp]) {
+  constexpr int NT = LP / 16, SS = LP + 1;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const bool act = w < NT;
+  const int i0 = 16 * w + q;
+  if (act)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * v, jj = 16 * tj + rl;
+        X[tj][v] = (i == jj && !dead[i]) ? 1.0 : 0.0;
+      }
+#pragma unroll 1
+  for (int i = LP - 1; i >= 0; --i) {
+    const int cb = i & 1;
+    if (act && w == i / 16 && q == (i & 3)) {
+      const double di = Rs[i * SS + i];
+      const double rdi = dead[i] ? 0.0 : 1.0 / di;
+      const int vi = (i & 15) >> 2;
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) {
+        const double x = pick4(X[tj], vi) * rdi;
+        put4(X[tj], vi, x);
+        rowb[cb][16 * tj + rl] = x;
+      }
+    }
+    __syncthreads();
+    if (act) {
+      double xr[4], rc[4];
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) xr[tj] = rowb[cb][16 * tj + rl];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) rc[v] = Rs[(i0 + 4 * v) * SS + i];
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[tj][v] = (i0 + 4 * v < i) ? X[tj][v] - rc[v] * xr[tj] : X[tj][v];
+    }
+  }
+  __syncthreads();
+}
+
 // reduced slots: red[0] = P, red[1] = C, red[2] = G2 (upper tiles), red[3] =
 // G3 (upper tiles); scr = R1, R1^-1, T
+template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict__ jobs,
                                                       const int64_t *__restrict__ clock, int init) {
-  __shared__ double Pm[kBlockMaxLp * kSS], A[kBlockMaxLp * kSS], Ri[kBlockMaxLp * kSS], Cm[kBlockMaxLp * kSS];
+  constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
+  __shared__ double Pm[LP * SS], Cm[LP * SS], Ws[LP * SS];
+  __shared__ double rowb[2][kBlockMaxLp];
   __shared__ int dead[kBlockMaxLp];
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
+  if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
-  const int LP = J.Lp, L2 = LP * LP, t = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const bool act = w < NT;
   const GLB double *red = gp(J.red);
-  for (int e = t; e < L2; e += kThreads) {
-    const int r = e / LP, c = e - r * LP;
-    Pm[r * kSS + c] = init ? 0.0 : red[e];
-    Cm[r * kSS + c] = init ? 0.0 : red[L2 + e];
-    A[r * kSS + c] = gram_sym(red + 2 * L2, LP, r, c);
+  if (init) {
+    for (int e = t; e < L2; e += kThreads) Pm[(e / LP) * SS + (e % LP)] = Cm[(e / LP) * SS + (e % LP)] = 0.0;
+  } else {
+    glb_to_lds<LP>(red, Pm, false);
+    glb_to_lds<LP>(red + L2, Cm, false);
   }
+  v4d D[4];
+  if (act)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) D[tj][v] = gram_sym(red + 2 * L2, LP, 16 * w + q + 4 * v, 16 * tj + rl);
   __syncthreads();
   // Deflation test of column c: its part outside the span of Q_k and of the
   // earlier columns is below kDeflTol times its own norm ||w'_c|| (the norm
   // before the projection, ||P(:, c)||^2 + G2(c, c)), or below 1e-14 ||A^T A||.
   if (t < LP) {
-    double own = A[t * kSS + t];
-    for (int i = 0; i < LP; ++i) own = fma(Pm[i * kSS + t], Pm[i * kSS + t], own);
+    double own = gram_sym(red + 2 * L2, LP, t, t);
+    for (int i = 0; i < LP; ++i) own = fma(Pm[i * SS + t], Pm[i * SS + t], own);
     const double flo = init ? 0.0 : (1e-14 * J.dscale) * (1e-14 * J.dscale);
     thr[t] = fmax(kDeflTol * kDeflTol * own, flo);
+    if (init) gp(J.beta0)[t] = sqrt(fmax(gram_sym(red + 2 * L2, LP, t, t), 0.0));
   }
-  __syncthreads();  // the thresholds read the diagonal before the correction below
-  if (init) {
-    if (t < LP) gp(J.beta0)[t] = sqrt(fmax(A[t * kSS + t], 0.0));
-  } else {
+  if (!init) {
     GLB double *Ak = gp(J.Ah) + (int64_t)k * L2;
     for (int e = t; e < L2; e += kThreads) {
       const int r = e / LP, c = e - r * LP;
-      Ak[e] = 0.5 * (Pm[r * kSS + c] + Pm[c * kSS + r]);
-      // G2 - C^T C: the second projection W2 - Q C
-      double s = 0.0;
-      for (int l2 = 0; l2 < LP; ++l2) s = fma(Cm[l2 * kSS + r], Cm[l2 * kSS + c], s);
-      A[r * kSS + c] -= s;
+      Ak[e] = 0.5 * (Pm[r * SS + c] + Pm[c * SS + r]);
     }
+    mm_lds<LP, true>(Cm, Cm, -1.0, D);  // G2 - C^T C
   }
   __syncthreads();
-  chol_defl(A, LP, thr, dead);
-  tri_inv(A, LP, dead, Ri);
+  chol_regs<LP>(D, thr, dead, rowb);
   GLB double *R1 = gp(J.scr), *R1i = R1 + L2, *T = R1 + 2 * L2;
+  regs_to_glb<LP>(D, R1);
+  regs_to_lds<LP>(D, Ws);
+  __syncthreads();
+  v4d X[4];
+  trinv_regs<LP>(Ws, dead, X, rowb);
+  regs_to_glb<LP>(X, R1i);
+  // T = (P + C) R1^-1
   for (int e = t; e < L2; e += kThreads) {
     const int r = e / LP, c = e - r * LP;
-    R1[e] = (c >= r) ? A[r * kSS + c] : 0.0;
-    R1i[e] = Ri[r * kSS + c];
-    double s = 0.0;
-    if (!init)
-      for (int l2 = 0; l2 <= c; ++l2) s = fma(Pm[r * kSS + l2] + Cm[r * kSS + l2], Ri[l2 * kSS + c], s);
-    T[e] = s;
+    Pm[r * SS + c] += Cm[r * SS + c];
   }
+  regs_to_lds<LP>(X, Ws);
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) D[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+    if (!init) mm_lds<LP, false>(Pm, Ws, 1.0, D);
+  }
+  regs_to_glb<LP>(D, T);
 }
 
+template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict__ jobs,
                                                       const int64_t *__restrict__ clock, int init) {
-  __shared__ double A[kBlockMaxLp * kSS], X[kBlockMaxLp * kSS], Y[kBlockMaxLp * kSS], Z[kBlockMaxLp * kSS];
+  constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
+  __shared__ double Rs[LP * SS], Xs[LP * SS], Os[LP * SS];
+  __shared__ double rowb[2][kBlockMaxLp];
   __shared__ int dead[kBlockMaxLp];
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
+  if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
-  const int LP = J.Lp, L2 = LP * LP, t = threadIdx.x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const bool act = w < NT;
   const GLB double *red = gp(J.red);
   const GLB double *R1 = gp(J.scr), *R1i = R1 + L2, *T = R1 + 2 * L2;
-  for (int e = t; e < L2; e += kThreads) {
-    const int r = e / LP, c = e - r * LP;
-    A[r * kSS + c] = gram_sym(red + 3 * L2, LP, r, c);
-    Y[r * kSS + c] = init ? 0.0 : T[e];
-    Z[r * kSS + c] = R1i[e];
-  }
+  v4d D[4];
+  if (act)
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) D[tj][v] = gram_sym(red + 3 * L2, LP, 16 * w + q + 4 * v, 16 * tj + rl);
+  if (t < LP) thr[t] = kDeflTol * kDeflTol * gram_sym(red + 3 * L2, LP, t, t);
   __syncthreads();
-  if (t < LP) thr[t] = kDeflTol * kDeflTol * A[t * kSS + t];
-  __syncthreads();
-  chol_defl(A, LP, thr, dead);
+  chol_regs<LP>(D, thr, dead, rowb);
   if (t == 0) {
     int nd = 0;
     for (int c = 0; c < LP; ++c) nd += dead[c];
     gp(J.flags)[0] = nd;
   }
-  tri_inv(A, LP, dead, X);  // R2^+
-  GLB double *M = gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2;
-  GLB double *N = gp(J.Nh) + (int64_t)k * L2;
-  for (int e = t; e < L2; e += kThreads) {
-    const int r = e / LP, c = e - r * LP;
-    double s = 0.0;
-    for (int l2 = r; l2 <= c; ++l2) s = fma(Z[r * kSS + l2], X[l2 * kSS + c], s);
-    M[e] = s;
-    if (!init) {
-      double s2 = 0.0;
-      for (int l2 = 0; l2 <= c; ++l2) s2 = fma(Y[r * kSS + l2], X[l2 * kSS + c], s2);
-      N[e] = s2;
+  regs_to_lds<LP>(D, Rs);
+  __syncthreads();
+  v4d X[4];
+  trinv_regs<LP>(Rs, dead, X, rowb);  // R2^+
+  regs_to_lds<LP>(X, Xs);
+  glb_to_lds<LP>(R1i, Os, false);
+  __syncthreads();
+  v4d E[4];
+  // M = R1^-1 R2^-1
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) E[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+    mm_lds<LP, false>(Os, Xs, 1.0, E);
+  }
+  regs_to_glb<LP>(E, gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2);
+  __syncthreads();
+  if (!init) {
+    // N = T R2^-1
+    glb_to_lds<LP>(T, Os, false);
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int tj = 0; tj < NT; ++tj) E[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+      mm_lds<LP, false>(Os, Xs, 1.0, E);
     }
+    regs_to_glb<LP>(E, gp(J.Nh) + (int64_t)k * L2);
+    __syncthreads();
   }
+  // B_{k+1} = R2 R1
+  glb_to_lds<LP>(R1, Os, false);
   __syncthreads();
-  for (int e = t; e < L2; e += kThreads) {
-    const int r = e / LP, c = e - r * LP;
-    Z[r * kSS + c] = R1[e];
+  if (act) {
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj) E[tj] = v4d{0.0, 0.0, 0.0, 0.0};
+    mm_lds<LP, false>(Rs, Os, 1.0, E);
   }
-  __syncthreads();
-  GLB double *B = gp(J.Bh) + (int64_t)(init ? 0 : k + 1) * L2;
-  for (int e = t; e < L2; e += kThreads) {
-    const int r = e / LP, c = e - r * LP;
-    double s = 0.0;
-    for (int l2 = r; l2 <= c; ++l2) s = fma(A[r * kSS + l2], Z[l2 * kSS + c], s);
-    B[e] = s;
-  }
+  regs_to_glb<LP>(E, gp(J.Bh) + (int64_t)(init ? 0 : k + 1) * L2);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -527,12 +682,16 @@ hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, hipStream_t
 }
 
 hipError_t launch_bs_small1(const BBatch &b, int init, hipStream_t st) {
-  hipLaunchKernelGGL(bs_small1, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small1<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small1<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small1<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
   return hipGetLastError();
 }
 
 hipError_t launch_bs_small2(const BBatch &b, int init, hipStream_t st) {
-  hipLaunchKernelGGL(bs_small2, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small2<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small2<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small2<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
   return hipGetLastError();
 }
 
