@@ -25,6 +25,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# DRAM-side bytes per launch of the two sparse products of the block step at
+# c2, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy
+# (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
+# measured on (sha256 of csrc/k_bspmm.hip) and for the c2 workload.
+SPMM_TRAFFIC_C2 = {"sha256": "92dfc1d48619929b1f9a6e98e2af976c195a6543ea0ad3766f6e30185bd2531e",
+                   "bytes": (245553.6 * 2.0 + 100000.0 + 249270.7 * 2.0 + 50000.0) * 1024.0}
+
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
@@ -47,39 +54,82 @@ def workload(name):
 
 
 def cpu_baseline(W, iters_gpu, seconds=15.0):
-    """The oracle's per-shift COCG timed on the host for a bounded number of
-    iterations on the same matrix and right-hand sides, scaled to one full
-    solve (N/2 shifts x the iteration count the GPU needed)."""
+    """The oracle's per-shift COCG (oracle/krylov.py, scipy CSR products) run
+    for a bounded time on the full matrix, shift 1 of N/2, all L columns.
+    One solve is extrapolated from the measured seconds per iteration times an
+    iteration count: the larger of the Krylov dimension per column the GPU
+    solve needed (its block steps) and the count the measured residual decay
+    of the sample predicts for solve_rtol, times N/2 shifts and ell rounds."""
     import numpy as np
     import synth
     from oracle import krylov, quadrature as Q
     I = W["I"]
     shifts, c = Q.moment_coeffs(W["a"], W["b"], W["N"], W["M"], 0.1, Q.PLAIN)
     V = synth.v_in(I.n, W["L"], 2, 0)
-    j = 0
-    t0 = time.perf_counter()
-    _, it, res, sec = krylov.cocg(I, shifts[j], V, tol=1e-300, maxit=10 ** 9, time_limit=seconds)
+    tol = W.get("solve_rtol", 1e-11)
+    _, it, res, sec = krylov.cocg(I, shifts[0], V, tol=1e-300, maxit=10 ** 9, time_limit=seconds)
     per_it = sec / max(it, 1)
-    per_solve = per_it * iters_gpu * (W["N"] // 2) * W.get("ell", 1)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
+    worst = float(np.max(res)) if np.size(res) else 1.0
+    rate = -np.log10(max(worst, 1e-300)) / max(it, 1)  # decades per iteration
+    it_rate = int(np.ceil(-np.log10(tol) / rate)) if rate > 0 else None
+    iters = max(iters_gpu, it_rate or 0)
+    per_solve = per_it * iters * (W["N"] // 2) * W.get("ell", 1)
+    threads = os.environ.get("OMP_NUM_THREADS", "unset")
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1,
             "kind": "oracle",
-            "sample": (f"oracle COCG (scipy CSR products, single-threaded) on shift 1 of {W['N'] // 2}, "
-                       f"all {W['L']} columns, {it} iterations in {sec:.1f}s on the full matrix; "
-                       f"scaled by {W['N'] // 2} shifts x {iters_gpu} iterations (extrapolated); "
-                       f"OMP_NUM_THREADS={threads}")}
+            "sample": (f"oracle COCG (scipy CSR products, one thread) on shift 1 of {W['N'] // 2}, all {W['L']} "
+                       f"columns of the full matrix: {it} iterations in {sec:.1f} s, worst relative residual "
+                       f"{worst:.2e}; one solve = {per_it * 1e3:.1f} ms/iteration x {iters} iterations "
+                       f"(max of the GPU block steps {iters_gpu} and the sample's decay rate "
+                       f"{'%.2e' % rate} decades/iteration -> {it_rate}) x {W['N'] // 2} shifts x ell "
+                       f"{W.get('ell', 1)} (extrapolated); OMP_NUM_THREADS={threads}")}
+
+
+def spmm_traffic(config):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2109_13655_amd", "csrc", "k_bspmm.hip")
+    try:
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if config != "c2" or h != SPMM_TRAFFIC_C2["sha256"]:
+        return None
+    return SPMM_TRAFFIC_C2["bytes"]
+
+
+def roofline(info, config):
+    """The sparse products: the block solver's K1 (U = A Q_k) and K2
+    (W = A^T U) together; the per-column solver's K2 (A^T product fused with
+    the Lanczos update).  Algorithmic bytes per launch from the library
+    (matrix + one read of the gathered block + the written block), times from
+    HIP events recorded on the solve's stream around sampled launches."""
+    if info.solver == 1:  # CSVD_SOLVER_BLOCK
+        b = info.spmm_a_bytes + info.spmm_at_bytes
+        t = info.spmm_a_ms + info.spmm_at_ms
+        name = "b_spmm_a + b_spmm_at (U = A Q_k, W = A^T U on n x Lp blocks)"
+    else:
+        b, t = info.spmm_at_bytes, info.spmm_at_ms
+        name = "k2_spmm_lanczos (A^T product + Lanczos update + window store)"
+    ach = b / (t * 1e-3) / 1e9 if t > 0 else None
+    traffic = spmm_traffic(config) if info.solver == 1 else None
+    return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": traffic,
+            "bytes_per_launch": b, "avg_launch_ms": t, "samples": int(info.spmm_samples)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--max-iters", type=int, default=0)
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (a kernel of known traffic for "
+                         "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is single-GPU by design "
@@ -93,6 +143,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 1 GiB read + 1 GiB written")
+        del src, dst
     W = workload(args.config)
     I = W["I"]
     log("workload", W["desc"], "nnz", I.nnz, "interval", W["a"], W["b"])
@@ -157,26 +215,18 @@ def main():
         "max_rel_residual": float(resid.max()) if resid.size else None,
         "t_hat": int(info.t_hat),
         "lanczos_steps": int(info.iterations_total),
+        "solver": {1: "block", 2: "single"}.get(int(info.solver), str(info.solver)),
+        "deflated": int(info.deflated),
         "converged": bool(info.converged),
         "status": status,
         "phase_ms": {"solve": info.t_solve_ms, "lowrank": info.t_lowrank_ms, "qr": info.t_qr_ms,
                      "extract": info.t_extract_ms},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k2_spmm_lanczos (A^T product + Lanczos update + window store)",
-            "achieved": at_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (at_gbs / HBM_PEAK_GBS) if at_gbs else None,
-            "traffic": None,
-            "bytes_per_launch": info.spmm_at_bytes,
-            "avg_launch_ms": info.spmm_at_ms,
-            "samples": int(info.spmm_samples),
-        },
+        "roofline": roofline(info, args.config),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle COCG sample)")
-        out["cpu_baseline"] = cpu_baseline(W, info.iterations_total)
+        W["solve_rtol"] = p.solve_rtol
+        out["cpu_baseline"] = cpu_baseline(W, int(info.iterations))
     print(json.dumps(out), flush=True)
 
 

@@ -30,7 +30,6 @@ __device__ __forceinline__ int bfind(const int *__restrict__ toff, int njob, int
 
 static int bgrid(int total, int cap) { return total < 1 ? 1 : (total < cap ? total : cap); }
 
-constexpr int kEB = 8;  // max thread slots per tile in the sparse products
 
 __device__ __forceinline__ double2 cmulb(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -45,78 +44,6 @@ __device__ __forceinline__ double2 cdivb(double2 a, double2 b) {
   }
 }
 
-// ------------------------------------------------------ sparse products
-// y = M x for the rows of one tile; slot layout ((row * G) + g) * Lp + col as
-// in the single-vector kernels (G lane groups split each row's nonzeros).
-__device__ __forceinline__ void tile_spmm(const GLB int *__restrict__ rp, const GLB int *__restrict__ ci,
-                                          const GLB double *__restrict__ va, const GLB double *__restrict__ x,
-                                          GLB double *__restrict__ y, int64_t nrows, int tile, int rpt, int lg,
-                                          int G, int lgG, int E, double *gsum) {
-  const int t = threadIdx.x;
-  const int Lp = 1 << lg;
-  const int col = t & (Lp - 1);
-  const int gi = (t >> lg) & (G - 1);
-  for (int q = 0; q < E; ++q) {
-    const int rloc = (q * kThreads + t) >> (lg + lgG);
-    const int64_t row = (int64_t)tile * rpt + rloc;
-    double acc = 0.0;
-    if (row < nrows) {
-      const int en = rp[row + 1];
-#pragma unroll 4
-      for (int p = rp[row] + gi; p < en; p += G) acc = fma(va[p], x[((int64_t)ci[p] << lg) + col], acc);
-    }
-    if (G > 1) {
-      gsum[t] = acc;
-      __syncthreads();
-      if (gi == 0)
-        for (int h = 1; h < G; ++h) acc += gsum[t + (h << lg)];
-      __syncthreads();
-    }
-    if (gi == 0 && row < nrows) y[(row << lg) + col] = acc;
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict__ jobs, int njob,
-                                                     const int *__restrict__ toff, int total,
-                                                     const int64_t *__restrict__ clock) {
-  __shared__ double gsum[kThreads];
-  const int64_t ck = *clock;
-  for (int g = blockIdx.x; g < total; g += gridDim.x) {
-    const int j = bfind(toff, njob, g);
-    const BJobDesc &J = jobs[j];
-    const int k = (int)(ck - J.start_clock);
-    if (k >= J.Kstop) continue;
-    const int64_t nL = (int64_t)J.n * J.Lp;
-    tile_spmm(gp(J.rp), gp(J.ci), gp(J.va), gp(J.Q) + (int64_t)(k % J.nring) * nL, gp(J.U), J.m, g - toff[j], J.rpt1,
-              J.lgLp, J.G1, J.lgG1, J.E1, gsum);
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void b_spmm_at(const BJobDesc *__restrict__ jobs, int njob,
-                                                      const int *__restrict__ toff, int total,
-                                                      const int64_t *__restrict__ clock) {
-  __shared__ double gsum[kThreads];
-  const int64_t ck = *clock;
-  for (int g = blockIdx.x; g < total; g += gridDim.x) {
-    const int j = bfind(toff, njob, g);
-    const BJobDesc &J = jobs[j];
-    if ((int)(ck - J.start_clock) >= J.Kstop) continue;
-    tile_spmm(gp(J.rpT), gp(J.ciT), gp(J.vaT), gp(J.U), gp(J.W), J.n, g - toff[j], J.rpt2, J.lgLp, J.G2, J.lgG2,
-              J.E2, gsum);
-  }
-}
-
-hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st) {
-  hipLaunchKernelGGL(b_spmm_a, dim3(bgrid(b.total1, 4096)), dim3(kThreads), 0, st, b.jobs, b.njob, b.toff1, b.total1,
-                     b.clock);
-  return hipGetLastError();
-}
-
-hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st) {
-  hipLaunchKernelGGL(b_spmm_at, dim3(bgrid(b.total2, 4096)), dim3(kThreads), 0, st, b.jobs, b.njob, b.toff2, b.total2,
-                     b.clock);
-  return hipGetLastError();
-}
 
 // ------------------------------------------------------ per-shift block LU
 // One workgroup per (job, shift).  The four products of a step run on FP64
