@@ -539,8 +539,9 @@ int run_finalize(SolveRun &R) {
   HIPCHK(ctx, Xq.alloc(sizeof(double) * npad * LM));
   HIPCHK(ctx, tau1.alloc(sizeof(double) * LM));
   HIPCHK(ctx, hipMemcpyAsync(Xq.p, ctx->d_S.p, sizeof(double) * npad * LM, hipMemcpyDeviceToDevice, st));
-  HIPCHK(ctx, launch_hh_make(Xq.as<double>(), npad, (int)n, 0, tau1.as<double>(), st));
-  for (int j = 0; j + 1 < LM; ++j) HIPCHK(ctx, launch_hh_step(Xq.as<double>(), npad, (int)n, LM, j, tau1.as<double>(), st));
+  DevBuf ws1;
+  HIPCHK(ctx, ws1.alloc(sizeof(double) * hh_blocked_ws_doubles(LM)));
+  HIPCHK(ctx, hh_qr_blocked(Xq.as<double>(), npad, (int)n, LM, tau1.as<double>(), ws1.as<double>(), st));
   // R (LM x LM upper) to the host, R^T back as a column-major LMe x LMe block
   const int LMe = LM + (LM & 1);
   std::vector<double> Rh((size_t)LM * LM);
@@ -595,13 +596,16 @@ int run_finalize(SolveRun &R) {
     for (int c = 0; c < r; ++c)
       for (int i = 0; i < LM; ++i) Z[(size_t)c * LM + i] = Jm[(size_t)perm[c] * LMe + i];
     XFER(h2d_cols(ctx, Vt.as<double>(), npad, Z.data(), LM, r, st));
-    HIPCHK(ctx, launch_hh_apply(Xq.as<double>(), npad, (int)n, -LM, tau1.as<double>(), Vt.as<double>(), npad, r, st));
+    DevBuf wsr;
+    HIPCHK(ctx, wsr.alloc(sizeof(double) * hh_blocked_ws_doubles(r)));
+    HIPCHK(ctx, hh_apply_blocked(Xq.as<double>(), npad, (int)n, LM, ws1.as<double>(), Vt.as<double>(), npad, r,
+                                 wsr.as<double>(), st));
     HIPCHK(ctx, hipStreamSynchronize(st));
   }
   double t1 = now_ms();
   // ---- step 4: X = A V~, [U~, B] = qr(X)
   const int re = r + (r & 1);
-  DevBuf Vrow, Xrow, Xa, tau2;
+  DevBuf Vrow, Xrow, Xa, tau2, ws2;
   std::vector<double> Bh;
   if (r > 0) {
     HIPCHK(ctx, Vrow.alloc(sizeof(double) * n * r));
@@ -613,8 +617,8 @@ int run_finalize(SolveRun &R) {
     HIPCHK(ctx, launch_spmm_rowmajor((int)m, r, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
                                      Vrow.as<double>(), Xrow.as<double>(), st));
     HIPCHK(ctx, launch_row_to_col((int)m, r, Xrow.as<double>(), r, Xa.as<double>(), mpad, st));
-    HIPCHK(ctx, launch_hh_make(Xa.as<double>(), mpad, (int)m, 0, tau2.as<double>(), st));
-    for (int j = 0; j + 1 < r; ++j) HIPCHK(ctx, launch_hh_step(Xa.as<double>(), mpad, (int)m, r, j, tau2.as<double>(), st));
+    HIPCHK(ctx, ws2.alloc(sizeof(double) * hh_blocked_ws_doubles(r)));
+    HIPCHK(ctx, hh_qr_blocked(Xa.as<double>(), mpad, (int)m, r, tau2.as<double>(), ws2.as<double>(), st));
     Bh.assign((size_t)r * r, 0.0);
     std::vector<double> Rb((size_t)r * r);
     XFER(d2h_cols(ctx, Rb.data(), Xa.as<double>(), mpad, r, r, st));
@@ -700,7 +704,10 @@ int run_finalize(SolveRun &R) {
                             ctx->d_V.as<double>(), npad, st));
     HIPCHK(ctx, hipMemsetAsync(ctx->d_U.p, 0, ctx->d_U.bytes, st));
     XFER(h2d_cols(ctx, ctx->d_U.as<double>(), mpad, Ps.data(), r, t, st));
-    HIPCHK(ctx, launch_hh_apply(Xa.as<double>(), mpad, (int)m, -r, tau2.as<double>(), ctx->d_U.as<double>(), mpad, t, st));
+    DevBuf wsu;
+    HIPCHK(ctx, wsu.alloc(sizeof(double) * hh_blocked_ws_doubles(t)));
+    HIPCHK(ctx, hh_apply_blocked(Xa.as<double>(), mpad, (int)m, r, ws2.as<double>(), ctx->d_U.as<double>(), mpad, t,
+                                 wsu.as<double>(), st));
     HIPCHK(ctx, launch_sign_fix(ctx->d_U.as<double>(), mpad, (int)m, ctx->d_V.as<double>(), npad, (int)n, t, st));
     // residuals: ||A v - s u|| and ||A^T u - s v||
     DevBuf vr, ur, av, atu, o1, o2;

@@ -220,6 +220,17 @@ hipError_t launch_hh_apply(const double *Xr, int64_t ldr, int rows, int j, const
                            int64_t ldz, int zcols, hipStream_t st);
 hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, double *V, int64_t ldv,
                               int vrows, int step, double tol, int *counter, hipStream_t st);
+constexpr int kHB = 32;  // panel width of the blocked Householder QR
+// workspace (doubles) of the blocked QR of a rows x cols matrix: partial sums,
+// W, V^T V and the T factors of every panel (kept for hh_apply_blocked)
+size_t hh_blocked_ws_doubles(int cols);
+// blocked Householder QR in place (R on and above the diagonal, reflectors
+// below, tau); ws: hh_blocked_ws_doubles(cols) doubles, keeps the T factors
+hipError_t hh_qr_blocked(double *X, int64_t ld, int rows, int cols, double *tau, double *ws, hipStream_t st);
+// Z <- Q Z with the reflectors and T factors of hh_qr_blocked (ws of the QR,
+// read only); ws_rw: hh_blocked_ws_doubles(ncols) doubles of scratch
+hipError_t hh_apply_blocked(const double *X, int64_t ld, int rows, int nref, const double *ws, double *Z,
+                            int64_t ldz, int ncols, double *ws_rw, hipStream_t st);
 hipError_t launch_col_norms(const double *A, int64_t lda, int rows, int cols, double *out, hipStream_t st);
 hipError_t launch_copy_block(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t rows, int cols,
                              hipStream_t st);

@@ -313,6 +313,344 @@ hipError_t launch_resid_cols(const double *X, const double *Y, int64_t ldy, cons
 // on the device with unit and random operands).
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// ----------------------------------------------------------- blocked QR
+// Householder QR in panels of kHB columns (LAPACK's blocked form): each panel
+// is factored by the reflector kernels above; its reflectors are gathered as
+// I - V T V^T (T upper triangular, from V^T V and tau), and the trailing
+// columns are updated with two tall products on FP64 MFMA:
+//   W = V^T C  (partial sums per workgroup over row chunks, fixed-order
+//              reduction),  C -= V (T^T W).
+// Q Z is applied the same way panel by panel, from the last: Z -= V (T (V^T Z)).
+// V is read as a view of the factored columns: column i of the panel that
+// starts at j0 is 0 above row j0 + i, 1 at row j0 + i, X below.
+typedef double v4dd __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4dd mfma4d(double a, double b, v4dd c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double vview(const double *X, int64_t ld, int j0, int i, int jb, int64_t r) {
+  const int64_t d = (int64_t)j0 + i;
+  if (i >= jb || r < d) return 0.0;
+  if (r == d) return 1.0;
+  return X[(j0 + i) * ld + r];
+}
+
+constexpr int kTGChunk = 64;
+constexpr int kTGMaxVB = 256;
+
+// partial W over the row chunks of workgroup vb: part[vb][i][c], i < kHB,
+// c < p2.  C(r, c) is column-major (ldc), or (cv = 1) the same V view.
+__global__ __launch_bounds__(256) void k_tg_part(const double *__restrict__ X, int64_t ld, int j0, int jb,
+                                                  int64_t rows, const double *__restrict__ C, int64_t ldc, int cv,
+                                                  int p2, int nvb, double *__restrict__ part) {
+  __shared__ double Vs[kTGChunk][kHB + 1];
+  __shared__ double Cs[kTGChunk][64 + 1];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const int vb = blockIdx.x, col0 = blockIdx.y * 64;
+  const int64_t r0 = j0, nchunk = (rows - r0 + kTGChunk - 1) / kTGChunk;
+  // wave w: output tiles (ti, tj) = (w >> 2 ... ): 2 x 4 tiles of 16 x 16 over 4 waves
+  v4dd acc[2];
+  acc[0] = acc[1] = v4dd{0.0, 0.0, 0.0, 0.0};
+  for (int64_t ch = vb; ch < nchunk; ch += nvb) {
+    const int64_t rb = r0 + ch * kTGChunk;
+    __syncthreads();
+    for (int e = t; e < kTGChunk * kHB; e += 256) {
+      const int i = e / kTGChunk, rr = e % kTGChunk;
+      const int64_t r = rb + rr;
+      Vs[rr][i] = (r < rows) ? vview(X, ld, j0, i, jb, r) : 0.0;
+    }
+    for (int e = t; e < kTGChunk * 64; e += 256) {
+      const int c = e / kTGChunk, rr = e % kTGChunk;
+      const int64_t r = rb + rr;
+      double v = 0.0;
+      if (r < rows && col0 + c < p2) v = cv ? vview(X, ld, j0, col0 + c, jb, r) : C[(int64_t)(col0 + c) * ldc + r];
+      Cs[rr][c] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s2 = 0; s2 < 2; ++s2) {
+      const int tau = w + 4 * s2;  // 0..7: ti = tau / 4, tj = tau % 4
+      const int ti = tau >> 2, tj = tau & 3;
+#pragma unroll
+      for (int ks = 0; ks < kTGChunk / 4; ++ks) {
+        const int k = 4 * ks + q;
+        acc[s2] = mfma4d(Vs[k][16 * ti + rl], Cs[k][16 * tj + rl], acc[s2]);
+      }
+    }
+  }
+  double *P = part + (int64_t)vb * kHB * p2;
+#pragma unroll
+  for (int s2 = 0; s2 < 2; ++s2) {
+    const int tau = w + 4 * s2;
+    const int ti = tau >> 2, tj = tau & 3;
+    const int c = col0 + 16 * tj + rl;
+    if (c < p2)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[(int64_t)(16 * ti + q + 4 * v) * p2 + c] = acc[s2][v];
+  }
+}
+
+// W[i][c] = sum_vb part[vb][i][c] in a fixed order (8 interleaved sums)
+__global__ __launch_bounds__(256) void k_tg_reduce(const double *__restrict__ part, int nvb, int total,
+                                                    double *__restrict__ W) {
+  __shared__ double sp[8][32];
+  const int t = threadIdx.x, grp = t >> 5;
+  const int o = blockIdx.x * 32 + (t & 31);
+  double s = 0.0;
+  if (o < total)
+    for (int vb = grp; vb < nvb; vb += 8) s += part[(int64_t)vb * total + o];
+  sp[grp][t & 31] = s;
+  __syncthreads();
+  if (grp == 0 && o < total) {
+    double r = sp[0][t];
+    for (int h = 1; h < 8; ++h) r += sp[h][t];
+    W[o] = r;
+  }
+}
+
+// T (kHB x kHB, row-major, upper) from G = V^T V (kHB x kHB row-major) and
+// tau: T(j, j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).
+__global__ __launch_bounds__(256) void k_tmat(const double *__restrict__ G, const double *__restrict__ tau, int j0,
+                                               int jb, double *__restrict__ T) {
+  __shared__ double Ts[kHB][kHB + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < kHB * kHB; e += 256) Ts[e / kHB][e % kHB] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < jb; ++j) {
+    const double tj = tau[j0 + j];
+    if (t < j) {
+      double s = 0.0;
+      for (int l2 = t; l2 < j; ++l2) s = fma(Ts[t][l2], G[l2 * kHB + j], s);
+      Ts[t][j] = -tj * s;
+    }
+    if (t == 0) Ts[j][j] = tj;
+    __syncthreads();
+  }
+  for (int e = t; e < kHB * kHB; e += 256) T[e] = Ts[e / kHB][e % kHB];
+}
+
+// C(r, c) -= sum_i V(r, i) W2(i, c), r >= j0, with W2 = T^T W (trans = 1) or
+// T W; 64 rows x 64 columns per workgroup, C written back in column segments
+// through LDS.
+__global__ __launch_bounds__(256) void k_tu(const double *__restrict__ X, int64_t ld, int j0, int jb, int64_t rows,
+                                             const double *__restrict__ T, int trans, const double *__restrict__ W,
+                                             int p2, double *__restrict__ C, int64_t ldc) {
+  __shared__ double Ts[kHB][kHB + 1];
+  __shared__ double Ws[kHB][64 + 1];
+  __shared__ double W2[kHB][64 + 1];
+  __shared__ double Cs[64][65];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const int64_t rb = (int64_t)j0 + (int64_t)blockIdx.x * 64;
+  const int col0 = blockIdx.y * 64;
+  for (int e = t; e < kHB * kHB; e += 256) {
+    const int i = e / kHB, k = e % kHB;
+    Ts[i][k] = trans ? T[k * kHB + i] : T[e];
+  }
+  for (int e = t; e < kHB * 64; e += 256) {
+    const int i = e / 64, c = e % 64;
+    Ws[i][c] = (col0 + c < p2) ? W[(int64_t)i * p2 + col0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < kHB * 64; e += 256) {
+    const int i = e / 64, c = e % 64;
+    double s = 0.0;
+    for (int k = 0; k < kHB; ++k) s = fma(Ts[i][k], Ws[k][c], s);
+    W2[i][c] = s;
+  }
+  __syncthreads();
+  v4dd acc[4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) acc[tj] = v4dd{0.0, 0.0, 0.0, 0.0};
+  const int64_t r = rb + 16 * w + rl;
+#pragma unroll
+  for (int ks = 0; ks < kHB / 4; ++ks) {
+    const int k = 4 * ks + q;
+    const double a = (r < rows) ? vview(X, ld, j0, k, jb, r) : 0.0;
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[tj] = mfma4d(a, W2[k][16 * tj + rl], acc[tj]);
+  }
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Cs[16 * tj + rl][16 * w + q + 4 * v] = acc[tj][v];
+  __syncthreads();
+  for (int e = t; e < 64 * 64; e += 256) {
+    const int c = e >> 6, rr = e & 63;
+    const int64_t row = rb + rr;
+    if (col0 + c < p2 && row < rows) C[(int64_t)(col0 + c) * ldc + row] -= Cs[c][rr];
+  }
+}
+
+// Panel factorisation: reflector j of the panel [j0, jend) in three
+// row-parallel launches.  pf_dots: per row block, T_c = sum_{r > j} X(r, j)
+// X(r, c) for c = j .. jend-1 (T_j = ||x(j+1:)||^2).  pf_coef (one block):
+// fixed-order sums, beta = -sign(x_j) sqrt(x_j^2 + T_j), scale = 1/(x_j -
+// beta), tau = (beta - x_j)/beta and w_c = tau (X(j, c) + scale T_c) for c > j.
+// pf_update: X(r, j) <- scale X(r, j) (the reflector, r > j), X(j, j) <- beta,
+// X(r, c) -= w_c v_r for c > j (v_j = 1).  Same formulas as make_reflector
+// and k_hh_step, with the work spread over all rows.
+constexpr int kPFRows = 512;  // rows per workgroup in the panel kernels
+
+__global__ __launch_bounds__(256) void k_pf_dots(const double *__restrict__ X, int64_t ld, int rows, int j, int jend,
+                                                  double *__restrict__ part) {
+  __shared__ double red[kHB][256 / 64];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int nc = jend - j;
+  const int64_t rb = (int64_t)j + 1 + (int64_t)blockIdx.x * kPFRows;
+  double acc[kHB];
+#pragma unroll
+  for (int c = 0; c < kHB; ++c) acc[c] = 0.0;
+  for (int64_t r = rb + t; r < rb + kPFRows && r < rows; r += 256) {
+    const double x = X[(int64_t)j * ld + r];
+#pragma unroll
+    for (int c = 0; c < kHB; ++c)
+      if (c < nc) acc[c] = fma(x, X[(int64_t)(j + c) * ld + r], acc[c]);
+  }
+  // fixed-order reduction: within the wave by xor-shuffles, then over waves
+#pragma unroll
+  for (int c = 0; c < kHB; ++c) {
+    double v = acc[c];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[c][wv] = v;
+  }
+  __syncthreads();
+  if (t < nc) part[(int64_t)blockIdx.x * kHB + t] = red[t][0] + red[t][1] + red[t][2] + red[t][3];
+}
+
+__global__ __launch_bounds__(64) void k_pf_coef(const double *__restrict__ part, int nb, double *__restrict__ X,
+                                                 int64_t ld, int j, int jend, double *__restrict__ tau,
+                                                 double *__restrict__ coef) {
+  // coef[0] = scale, coef[1] = beta, coef[2 + c] = w for column j + c (c >= 1)
+  __shared__ double T[kHB];
+  __shared__ double sh[2];
+  const int t = threadIdx.x, nc = jend - j;
+  if (t < nc) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * kHB + t];
+    T[t] = s;
+  }
+  __syncthreads();
+  if (t == 0) {
+    const double x0 = X[(int64_t)j * ld + j], xn2 = T[0];
+    double scale = 0.0, beta = x0, tj = 0.0;
+    if (xn2 != 0.0) {
+      beta = -copysign(sqrt(x0 * x0 + xn2), x0);
+      scale = 1.0 / (x0 - beta);
+      tj = (beta - x0) / beta;
+    }
+    tau[j] = tj;
+    sh[0] = scale;
+    sh[1] = tj;
+    coef[0] = scale;
+    coef[1] = beta;
+  }
+  __syncthreads();
+  if (t >= 1 && t < nc) coef[2 + t] = sh[1] * (X[(int64_t)(j + t) * ld + j] + sh[0] * T[t]);
+}
+
+__global__ __launch_bounds__(256) void k_pf_update(double *__restrict__ X, int64_t ld, int rows, int j, int jend,
+                                                    const double *__restrict__ coef) {
+  const int nc = jend - j;
+  const double scale = coef[0], beta = coef[1];
+  const int64_t r = (int64_t)j + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  double v;
+  if (r == j) {
+    v = 1.0;
+    X[(int64_t)j * ld + j] = beta;
+  } else {
+    v = X[(int64_t)j * ld + r] * scale;
+    X[(int64_t)j * ld + r] = v;
+  }
+  for (int c = 1; c < nc; ++c) X[(int64_t)(j + c) * ld + r] -= coef[2 + c] * v;
+}
+
+static hipError_t panel_factor(double *X, int64_t ld, int rows, int j0, int jend, double *tau, double *part,
+                               double *coef, hipStream_t st) {
+  for (int j = j0; j < jend; ++j) {
+    const int64_t below = (int64_t)rows - j - 1;
+    const int nb = (int)std::max<int64_t>(1, (below + kPFRows - 1) / kPFRows);
+    hipLaunchKernelGGL(k_pf_dots, dim3(nb), dim3(256), 0, st, X, ld, rows, j, jend, part);
+    hipLaunchKernelGGL(k_pf_coef, dim3(1), dim3(64), 0, st, part, nb, X, ld, j, jend, tau, coef);
+    const int nu = (int)((rows - j + 255) / 256);
+    hipLaunchKernelGGL(k_pf_update, dim3(nu), dim3(256), 0, st, X, ld, rows, j, jend, coef);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+size_t hh_blocked_ws_doubles(int cols) {
+  const int p2 = std::max(cols, kHB);
+  return (size_t)kTGMaxVB * kHB * p2 + (size_t)kHB * p2 + (size_t)kHB * kHB +
+         (size_t)((cols + kHB - 1) / kHB) * kHB * kHB;
+}
+
+static int tg_nvb(int64_t rows_from) {
+  const int64_t nch = (rows_from + kTGChunk - 1) / kTGChunk;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nch, kTGMaxVB));
+}
+
+// W (kHB x p2, row-major) = V^T C over rows [j0, rows)
+static hipError_t tall_vtc(const double *X, int64_t ld, int j0, int jb, int64_t rows, const double *C, int64_t ldc,
+                           int cv, int p2, double *part, double *W, hipStream_t st) {
+  const int nvb = tg_nvb(rows - j0);
+  hipLaunchKernelGGL(k_tg_part, dim3(nvb, (p2 + 63) / 64), dim3(256), 0, st, X, ld, j0, jb, rows, C, ldc, cv, p2, nvb,
+                     part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int total = kHB * p2;
+  hipLaunchKernelGGL(k_tg_reduce, dim3((total + 31) / 32), dim3(256), 0, st, part, nvb, total, W);
+  return hipGetLastError();
+}
+
+hipError_t hh_qr_blocked(double *X, int64_t ld, int rows, int cols, double *tau, double *ws, hipStream_t st) {
+  const int p2max = std::max(cols, kHB);
+  double *part = ws, *W = part + (size_t)kTGMaxVB * kHB * p2max, *G = W + (size_t)kHB * p2max;
+  double *Tall = G + (size_t)kHB * kHB;
+  hipError_t e;
+  for (int j0 = 0; j0 < cols; j0 += kHB) {
+    const int jb = std::min(kHB, cols - j0);
+    // partial sums of the panel kernels reuse the head of part (before use
+    // by the tall products of this panel)
+    if ((e = panel_factor(X, ld, rows, j0, j0 + jb, tau, part, W, st)) != hipSuccess) return e;
+    double *T = Tall + (size_t)(j0 / kHB) * kHB * kHB;
+    if ((e = tall_vtc(X, ld, j0, jb, rows, nullptr, 0, 1, kHB, part, G, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tmat, dim3(1), dim3(256), 0, st, G, tau, j0, jb, T);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int c0 = j0 + jb, p2 = cols - c0;
+    if (p2 <= 0) continue;
+    double *C = X + (int64_t)c0 * ld;
+    if ((e = tall_vtc(X, ld, j0, jb, rows, C, ld, 0, p2, part, W, st)) != hipSuccess) return e;
+    const dim3 g((unsigned)((rows - j0 + 63) / 64), (unsigned)((p2 + 63) / 64));
+    hipLaunchKernelGGL(k_tu, g, dim3(256), 0, st, X, ld, j0, jb, (int64_t)rows, T, 1, W, p2, C, ld);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t hh_apply_blocked(const double *X, int64_t ld, int rows, int nref, const double *ws, double *Z,
+                            int64_t ldz, int ncols, double *ws_rw, hipStream_t st) {
+  // Z <- Q Z, Q = H_0 ... H_{nref-1}: panels from the last to the first
+  const int p2max = std::max(ncols, kHB);
+  double *part = ws_rw, *W = part + (size_t)kTGMaxVB * kHB * p2max;
+  const int pcols = std::max(nref, kHB);
+  const double *Tall = ws + (size_t)kTGMaxVB * kHB * pcols + (size_t)kHB * pcols + (size_t)kHB * kHB;
+  hipError_t e;
+  if (ncols <= 0) return hipSuccess;
+  const int np = (nref + kHB - 1) / kHB;
+  for (int pi = np - 1; pi >= 0; --pi) {
+    const int j0 = pi * kHB, jb = std::min(kHB, nref - j0);
+    const double *T = Tall + (size_t)pi * kHB * kHB;
+    if ((e = tall_vtc(X, ld, j0, jb, rows, Z, ldz, 0, ncols, part, W, st)) != hipSuccess) return e;
+    const dim3 g((unsigned)((rows - j0 + 63) / 64), (unsigned)((ncols + 63) / 64));
+    hipLaunchKernelGGL(k_tu, g, dim3(256), 0, st, X, ld, j0, jb, (int64_t)rows, T, 0, W, ncols, Z, ldz);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // TA: A is given transposed in memory (element (r, k) at A[r * lda + k]).
 template <bool TA>
 __global__ __launch_bounds__(256) void k_gemm_mfma(int R, int N, int K, double alpha, const double *__restrict__ A,
