@@ -508,14 +508,201 @@ __device__ __forceinline__ void trinv_regs(const double *Rs, const int *dead, v4
   __syncthreads();
 }
 
+// ---------------------------------------------- blocked small factorisations
+// Cholesky with deflation and the triangular (pseudo-)inverse of an Lp x Lp
+// matrix in LDS (stride Lp + 1), on 16 x 16 tiles: one wave factors and
+// inverts each diagonal tile (sixteen steps ordered within the wave, no
+// workgroup barrier), the block row and the trailing update run as 16x16x16
+// MFMA tile products on all waves.  A deflated column has a zero row in R and
+// a zero row and column in R^+ (the inverse on the kept indices).
+
+// Orders this wave's LDS accesses: the LDS unit performs a wave's DS
+// operations in issue order, so a write by one lane is seen by a later read
+// of another lane of the same wave; only the compiler must not move memory
+// operations across this point.
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// 16x16 tile product on one wave: D (+)= op(A) B, A and B tiles in LDS with
+// strides sa, sb; TA: A read transposed
+template <bool TA>
+__device__ __forceinline__ v4d tile_mm(const double *A, int sa, const double *B, int sb, v4d D) {
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const int k = 4 * ks + q;
+    const double a = TA ? A[k * sa + rl] : A[rl * sa + k];
+    D = mfma4(a, B[k * sb + rl], D);
+  }
+  return D;
+}
+
+__device__ __forceinline__ void tile_store(double *C, int sc, v4d D, double sign) {
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[(q + 4 * v) * sc + rl] = sign * D[v];
+}
+
+__device__ __forceinline__ v4d tile_load(const double *C, int sc) {
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
+  v4d D;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) D[v] = C[(q + 4 * v) * sc + rl];
+  return D;
+}
+
+// one wave: Cholesky of the 16 x 16 diagonal tile at (16 K, 16 K) in place
+// (upper factor, rows scaled), thresholds thr[16 K + c].  Lane l keeps the
+// entries e = l + 64 u (u < 4; row e / 16, column e % 16) in registers; each
+// step broadcasts the active row through rowb (16 doubles).
+__device__ void diag_chol16(double *A, int SS, int K, const double *thr, int *dead, double *rowb) {
+  const int l = threadIdx.x & 63;
+  double *D = A + 16 * K * SS + 16 * K;
+  double a[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = l + 64 * u;
+    a[u] = D[(e >> 4) * SS + (e & 15)];
+  }
+#pragma unroll 1
+  for (int c = 0; c < 16; ++c) {
+    // owners of row c publish it (entries 16 c .. 16 c + 15: slot c >> 2)
+    const int uc = c >> 2;
+    if ((l >> 4) == (c & 3)) rowb[l & 15] = uc == 0 ? a[0] : (uc == 1 ? a[1] : (uc == 2 ? a[2] : a[3]));
+    wave_lds_sync();
+    const double d = rowb[c];
+    const int dd = !(d > thr[16 * K + c]);
+    const double piv = dd ? 0.0 : sqrt(d);
+    const double ip = dd ? 0.0 : 1.0 / piv;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = l + 64 * u, i = e >> 4, j = e & 15;
+      const double rj = rowb[j] * ip;
+      const double upd = a[u] - (rowb[i] * ip) * rj;
+      a[u] = (i == c) ? ((j < c) ? 0.0 : (j == c ? piv : rj)) : ((i > c && j > c) ? upd : a[u]);
+    }
+    if (l == 0) dead[16 * K + c] = dd;
+    wave_lds_sync();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = l + 64 * u;
+    D[(e >> 4) * SS + (e & 15)] = a[u];
+  }
+  wave_lds_sync();
+}
+
+// one wave: X_KK = R_KK^+ of the factored diagonal tile, right-looking from
+// the bottom row: row i is finished (divided by R(i, i)) and broadcast, then
+// every entry above it subtracts R(i', i) X(i, j).
+__device__ void diag_inv16(const double *A, int SS, int K, const int *dead, double *X, double *rowb) {
+  const int l = threadIdx.x & 63;
+  const double *R = A + 16 * K * SS + 16 * K;
+  double *Xd = X + 16 * K * SS + 16 * K;
+  double x[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = l + 64 * u, i = e >> 4, j = e & 15;
+    x[u] = (i == j && !dead[16 * K + i]) ? 1.0 : 0.0;
+  }
+#pragma unroll 1
+  for (int i = 15; i >= 0; --i) {
+    const int ui = i >> 2;
+    if ((l >> 4) == (i & 3)) {
+      const double rdi = dead[16 * K + i] ? 0.0 : 1.0 / R[i * SS + i];
+      double xv = (ui == 0 ? x[0] : (ui == 1 ? x[1] : (ui == 2 ? x[2] : x[3]))) * rdi;
+      x[0] = ui == 0 ? xv : x[0];
+      x[1] = ui == 1 ? xv : x[1];
+      x[2] = ui == 2 ? xv : x[2];
+      x[3] = ui == 3 ? xv : x[3];
+      rowb[l & 15] = xv;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = l + 64 * u, ii = e >> 4, j = e & 15;
+      const double v = x[u] - R[ii * SS + i] * rowb[j];
+      x[u] = (ii < i) ? v : x[u];
+    }
+    wave_lds_sync();
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = l + 64 * u;
+    Xd[(e >> 4) * SS + (e & 15)] = x[u];
+  }
+  wave_lds_sync();
+}
+
+// A (symmetric, LDS) -> R (upper tiles; lower tiles untouched), X = R^+
+// (upper tiles, lower tiles zero).  Tmp: 4 x 16 x 17 doubles of scratch.
+template <int LP>
+__device__ void chol_inv_blocked(double *A, double *X, const double *thr, int *dead, double *Tmp) {
+  constexpr int NB = LP / 16, SS = LP + 1;
+  const int t = threadIdx.x, w = t >> 6;
+  for (int e = t; e < LP * LP; e += kThreads) X[(e / LP) * SS + (e % LP)] = 0.0;
+  __syncthreads();
+#pragma unroll 1
+  for (int K = 0; K < NB; ++K) {
+    if (w == 0) {
+      diag_chol16(A, SS, K, thr, dead, Tmp);
+      diag_inv16(A, SS, K, dead, X, Tmp);
+    }
+    __syncthreads();
+    // block row: R_KJ = X_KK^T A_KJ
+    const int J = K + 1 + w;
+    if (J < NB) {
+      v4d Dm = v4d{0.0, 0.0, 0.0, 0.0};
+      Dm = tile_mm<true>(X + 16 * K * SS + 16 * K, SS, A + 16 * K * SS + 16 * J, SS, Dm);
+      tile_store(A + 16 * K * SS + 16 * J, SS, Dm, 1.0);
+    }
+    __syncthreads();
+    // trailing update: A_JJ' -= R_KJ^T R_KJ' for K < J <= J'
+    const int m = NB - K - 1;
+    const int npair = m * (m + 1) / 2;
+    for (int pi = w; pi < npair; pi += 4) {
+      int u = pi, a = 0;
+      while (u >= m - a) {
+        u -= m - a;
+        ++a;
+      }
+      const int Jr = K + 1 + a, Jc = Jr + u;
+      v4d Dm = tile_load(A + 16 * Jr * SS + 16 * Jc, SS);
+      v4d Pm = v4d{0.0, 0.0, 0.0, 0.0};
+      Pm = tile_mm<true>(A + 16 * K * SS + 16 * Jr, SS, A + 16 * K * SS + 16 * Jc, SS, Pm);
+      tile_store(A + 16 * Jr * SS + 16 * Jc, SS, Dm - Pm, 1.0);
+    }
+    __syncthreads();
+  }
+  // inverse by block diagonals: X_KJ = -X_KK sum_{K < L <= J} R_KL X_LJ
+  double *Tw = Tmp + w * 16 * 17;
+#pragma unroll 1
+  for (int d = 1; d < NB; ++d) {
+    const int K = w, J = w + d;
+    if (J < NB) {
+      v4d S = v4d{0.0, 0.0, 0.0, 0.0};
+      for (int L = K + 1; L <= J; ++L)
+        S = tile_mm<false>(A + 16 * K * SS + 16 * L, SS, X + 16 * L * SS + 16 * J, SS, S);
+      tile_store(Tw, 17, S, 1.0);
+      wave_lds_sync();
+      v4d Y = v4d{0.0, 0.0, 0.0, 0.0};
+      Y = tile_mm<false>(X + 16 * K * SS + 16 * K, SS, Tw, 17, Y);
+      tile_store(X + 16 * K * SS + 16 * J, SS, Y, -1.0);
+    }
+    __syncthreads();
+  }
+}
+
 // reduced slots: red[0] = P, red[1] = C, red[2] = G2 (upper tiles), red[3] =
 // G3 (upper tiles); scr = R1, R1^-1, T
 template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict__ jobs,
                                                       const int64_t *__restrict__ clock, int init) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
-  __shared__ double Pm[LP * SS], Cm[LP * SS], Ws[LP * SS];
-  __shared__ double rowb[2][kBlockMaxLp];
+  __shared__ double Pm[LP * SS], Cm[LP * SS], As[LP * SS], Xs[LP * SS];
+  __shared__ double Tmp[4 * 16 * 17];
   __shared__ int dead[kBlockMaxLp];
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
@@ -556,26 +743,21 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
     }
     mm_lds<LP, true>(Cm, Cm, -1.0, D);  // G2 - C^T C
   }
+  regs_to_lds<LP>(D, As);
   __syncthreads();
-  chol_regs<LP>(D, thr, dead, rowb);
+  chol_inv_blocked<LP>(As, Xs, thr, dead, Tmp);
   GLB double *R1 = gp(J.scr), *R1i = R1 + L2, *T = R1 + 2 * L2;
-  regs_to_glb<LP>(D, R1);
-  regs_to_lds<LP>(D, Ws);
-  __syncthreads();
-  v4d X[4];
-  trinv_regs<LP>(Ws, dead, X, rowb);
-  regs_to_glb<LP>(X, R1i);
-  // T = (P + C) R1^-1
   for (int e = t; e < L2; e += kThreads) {
     const int r = e / LP, c = e - r * LP;
-    Pm[r * SS + c] += Cm[r * SS + c];
+    R1[e] = ((r >> 4) < (c >> 4) || ((r >> 4) == (c >> 4) && c >= r)) ? As[r * SS + c] : 0.0;
+    R1i[e] = Xs[r * SS + c];
+    Pm[r * SS + c] += Cm[r * SS + c];  // P + C
   }
-  regs_to_lds<LP>(X, Ws);
   __syncthreads();
   if (act) {
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) D[tj] = v4d{0.0, 0.0, 0.0, 0.0};
-    if (!init) mm_lds<LP, false>(Pm, Ws, 1.0, D);
+    if (!init) mm_lds<LP, false>(Pm, Xs, 1.0, D);
   }
   regs_to_glb<LP>(D, T);
 }
@@ -584,37 +766,45 @@ template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict__ jobs,
                                                       const int64_t *__restrict__ clock, int init) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
-  __shared__ double Rs[LP * SS], Xs[LP * SS], Os[LP * SS];
-  __shared__ double rowb[2][kBlockMaxLp];
+  __shared__ double As[LP * SS], Xs[LP * SS], Os[LP * SS];
+  __shared__ double Tmp[4 * 16 * 17];
   __shared__ int dead[kBlockMaxLp];
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
   if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
-  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const int t = threadIdx.x, w = t >> 6;
   const bool act = w < NT;
   const GLB double *red = gp(J.red);
   const GLB double *R1 = gp(J.scr), *R1i = R1 + L2, *T = R1 + 2 * L2;
-  v4d D[4];
-  if (act)
+  {
+    constexpr int IT = (L2 + kThreads - 1) / kThreads;
+    double gv[IT];
 #pragma unroll
-    for (int tj = 0; tj < NT; ++tj)
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      gv[it] = (e < L2) ? gram_sym(red + 3 * L2, LP, e / LP, e % LP) : 0.0;
+    }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) D[tj][v] = gram_sym(red + 3 * L2, LP, 16 * w + q + 4 * v, 16 * tj + rl);
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      if (e < L2) As[(e / LP) * SS + (e % LP)] = gv[it];
+    }
+  }
   if (t < LP) thr[t] = kDeflTol * kDeflTol * gram_sym(red + 3 * L2, LP, t, t);
   __syncthreads();
-  chol_regs<LP>(D, thr, dead, rowb);
+  chol_inv_blocked<LP>(As, Xs, thr, dead, Tmp);
   if (t == 0) {
     int nd = 0;
     for (int c = 0; c < LP; ++c) nd += dead[c];
     gp(J.flags)[0] = nd;
   }
-  regs_to_lds<LP>(D, Rs);
-  __syncthreads();
-  v4d X[4];
-  trinv_regs<LP>(Rs, dead, X, rowb);  // R2^+
-  regs_to_lds<LP>(X, Xs);
+  // R2 with zero lower part, for B = R2 R1
+  for (int e = t; e < L2; e += kThreads) {
+    const int r = e / LP, c = e - r * LP;
+    if (!((r >> 4) < (c >> 4) || ((r >> 4) == (c >> 4) && c >= r))) As[r * SS + c] = 0.0;
+  }
   glb_to_lds<LP>(R1i, Os, false);
   __syncthreads();
   v4d E[4];
@@ -644,7 +834,7 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
   if (act) {
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) E[tj] = v4d{0.0, 0.0, 0.0, 0.0};
-    mm_lds<LP, false>(Rs, Os, 1.0, E);
+    mm_lds<LP, false>(As, Os, 1.0, E);
   }
   regs_to_glb<LP>(E, gp(J.Bh) + (int64_t)(init ? 0 : k + 1) * L2);
 }
