@@ -79,6 +79,10 @@ typedef struct {
                           /* CSVD_SOLVER_AUTO: BLOCK when it applies and n >= 64 x padded  */
                           /* L (smaller matrices exhaust the block space in a few steps), */
                           /* else SINGLE                                                  */
+  int32_t keep_basis;     /* block solver: 1 keeps the whole basis in device memory while */
+                          /* it fits (leaving 8 GB free), so the moments need no second   */
+                          /* pass; 0 always regenerates it in a second pass.  Both give   */
+                          /* the same bits.  Jobs of csvd_server never keep it            */
 } csvd_params;
 
 enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
@@ -86,7 +90,7 @@ enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
 /* Fills *p with the paper's defaults: L=16, M=8, N=32, ell=1, delta=1e-20,
  * alpha=0.1, PLAIN, FP64, solve_rtol=1e-11, max_iters=1000000,
  * spurious_eps=1e-12, seed=2109, norm_a=0, window=0, check_solves=0,
- * solver=CSVD_SOLVER_AUTO. */
+ * solver=CSVD_SOLVER_AUTO, keep_basis=1. */
 int csvd_params_default(csvd_params *p);
 
 /* Creates a context holding a device copy of A in CSR form (and of A^T,
@@ -147,6 +151,9 @@ typedef struct {
   int32_t solver;            /* solver that ran                                        */
   int32_t deflated;          /* basis directions dropped from the newest block (block solver) */
   double  rest_ms;           /* average duration of the rest of a block step (sampled) */
+  int32_t basis_stored;      /* 1: the block basis was kept in device memory (no second */
+                             /* pass); 0: regenerated, or the per-column solver          */
+  int32_t reserved0;
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);
@@ -186,6 +193,12 @@ const char *csvd_last_error(const csvd_ctx *ctx);
 
 /* Frees everything the context owns.  NULL is accepted. */
 void csvd_destroy(csvd_ctx *ctx);
+
+/* Frees the device memory a context keeps between solves: the chunks of a
+ * stored block basis (csvd_params.keep_basis), which the next solve of the
+ * same block width would reuse.  Waits for the context's stream first.
+ * Returns CSVD_OK, CSVD_EINVAL (NULL) or CSVD_EDEVICE. */
+int csvd_trim(csvd_ctx *ctx);
 
 /* ---------------------------------------------------------------------------
  * Batched solves.  Runs independent (context, interval) problems together:

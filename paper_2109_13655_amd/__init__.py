@@ -19,7 +19,7 @@ __all__ = [
     "CsvdError", "csvd_params", "csvd_info", "load", "lib_path",
     "csvd_params_default", "csvd_create", "csvd_solve_interval", "csvd_get_triplets",
     "csvd_get_info", "csvd_get_moment", "csvd_get_solution", "csvd_quadrature", "csvd_spmm",
-    "csvd_get_transpose", "csvd_dense_gemm", "csvd_last_error", "csvd_destroy", "csvd_solve_batch",
+    "csvd_get_transpose", "csvd_dense_gemm", "csvd_last_error", "csvd_destroy", "csvd_trim", "csvd_solve_batch",
     "csvd_server_create", "csvd_server_submit", "csvd_server_step", "csvd_server_poll",
     "csvd_server_cancel", "csvd_server_last_error", "csvd_server_destroy",
     "CSVD_OK", "CSVD_EINVAL", "CSVD_ENOMEM", "CSVD_ENOTCONV", "CSVD_EDEVICE", "CSVD_ESTATE",
@@ -44,6 +44,7 @@ class csvd_params(C.Structure):
         ("solve_rtol", C.c_double), ("max_iters", C.c_int32),
         ("spurious_eps", C.c_double), ("seed", C.c_uint64), ("norm_a", C.c_double),
         ("window", C.c_int32), ("check_solves", C.c_int32), ("solver", C.c_int32),
+        ("keep_basis", C.c_int32),
     ]
 
 
@@ -59,7 +60,7 @@ class csvd_info(C.Structure):
         ("spmm_samples", C.c_int64),
         ("spmm_a_bytes", C.c_double), ("spmm_at_bytes", C.c_double), ("window_bytes", C.c_double),
         ("window", C.c_int32), ("L_padded", C.c_int32), ("solver", C.c_int32), ("deflated", C.c_int32),
-        ("rest_ms", C.c_double),
+        ("rest_ms", C.c_double), ("basis_stored", C.c_int32), ("reserved0", C.c_int32),
     ]
 
     def as_dict(self):
@@ -103,6 +104,7 @@ def load(build_if_missing: bool = True):
         "csvd_dense_gemm": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
         "csvd_last_error": (C.c_char_p, [_P]),
         "csvd_destroy": (None, [_P]),
+        "csvd_trim": (C.c_int, [_P]),
         "csvd_solve_batch": (C.c_int, [C.c_int32, _P, _P, _P, C.POINTER(csvd_params), _P, _P]),
         "csvd_server_create": (C.c_int, [C.POINTER(_P), C.c_int64, C.c_int32, _P]),
         "csvd_server_submit": (C.c_int, [_P, _P, C.c_double, C.c_double, C.POINTER(csvd_params), _P,
@@ -258,6 +260,10 @@ def csvd_dense_gemm(A, B):
 def csvd_last_error(ctx) -> str:
     m = load().csvd_last_error(ctx)
     return m.decode() if m else ""
+
+
+def csvd_trim(ctx):
+    _check(load().csvd_trim(ctx), ctx)
 
 
 def csvd_destroy(ctx):

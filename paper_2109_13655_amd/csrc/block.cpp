@@ -61,6 +61,8 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.U = (double *)take(8 * (size_t)(m * Lp));
   J.nring = kMomWindow + 2;
   J.Q = (double *)take(8 * (size_t)(J.nring * n * Lp));
+  J.qC = J.nring;
+  J.qT = 1;
   J.W = (double *)take(8 * (size_t)(n * Lp));
   J.Vpad = (double *)take(8 * (size_t)(n * Lp));
   J.gpart = (double *)take(8 * (size_t)(J.nvb * 2 * L2));
@@ -101,6 +103,12 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.cmom = d_cmom.as<double2>();
   e = hipMemsetAsync(J.flags, 0, 16, st);
   if (e != hipSuccess) return e;
+  // basis table: room for the stored basis of Kcap + 2 blocks; ring mode
+  qtab.assign((size_t)(Kcap + 2 + kStoreChunk - 1) / kStoreChunk + 1, nullptr);
+  e = d_qtab.alloc(sizeof(double *) * qtab.size());
+  if (e != hipSuccess) return e;
+  J.Qtab = d_qtab.as<double *>();
+  if ((e = set_ring(st)) != hipSuccess) return e;
   // solo tables: one job
   e = d_desc.alloc(sizeof(BJobDesc));
   if (e != hipSuccess) return e;
@@ -122,6 +130,52 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   solo.totals = S;
   solo.lpmask = lp_bit(Lp);
   return hipStreamSynchronize(st);  // host vectors are temporaries
+}
+
+hipError_t BlockJob::set_ring(hipStream_t st) {
+  h.qC = h.nring;
+  h.qT = 1;
+  std::fill(qtab.begin(), qtab.end(), nullptr);
+  qtab[0] = h.Q;
+  store = false;
+  hipError_t e = hipMemcpyAsync(d_qtab.p, qtab.data(), sizeof(double *) * qtab.size(), hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  return hipStreamSynchronize(st);
+}
+
+bool BlockJob::grow_store(int kneed, hipStream_t st) {
+  const size_t bytes = sizeof(double) * (size_t)kStoreChunk * h.n * h.Lp;
+  bool changed = false;
+  while ((int64_t)chunks.size() * kStoreChunk <= kneed) {
+    if (chunks.size() + 1 >= qtab.size()) return false;
+    std::unique_ptr<DevBuf> c;
+    if (cache && !cache->empty() && cache->back()->bytes == bytes) {
+      c = std::move(cache->back());
+      cache->pop_back();
+    } else {
+      if (cache) cache->clear();  // chunks of another block width
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) != hipSuccess || fr < bytes + kStoreReserve) return false;
+      c.reset(new DevBuf());
+      if (c->alloc(bytes) != hipSuccess) return false;
+    }
+    qtab[chunks.size()] = c->as<double>();
+    chunks.push_back(std::move(c));
+    changed = true;
+  }
+  if (changed) {
+    if (hipMemcpyAsync(d_qtab.p, qtab.data(), sizeof(double *) * qtab.size(), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return false;
+    if (hipStreamSynchronize(st) != hipSuccess) return false;
+  }
+  return true;
+}
+
+void BlockJob::free_store(bool keep) {
+  if (keep && cache)
+    for (auto &c : chunks) cache->push_back(std::move(c));
+  chunks.clear();
 }
 
 hipError_t BlockJob::sync_desc(hipStream_t st) {
@@ -171,6 +225,21 @@ hipError_t BEngine::start(BlockJob *j) {
   j->K = 0;
   hipError_t e = hipMemsetAsync(J.Q, 0, 8 * (size_t)J.nring * J.n * J.Lp, st_);
   if (e != hipSuccess) return e;
+  // store mode if the first chunks fit (blocks 0 .. kBlockPoll + 1 before the first poll)
+  j->free_store(true);
+  if ((e = j->set_ring(st_)) != hipSuccess) return e;
+  if (j->want_store) {
+    J.qC = kStoreChunk;
+    J.qT = (int)j->qtab.size();
+    std::fill(j->qtab.begin(), j->qtab.end(), nullptr);
+    if (j->grow_store(std::min(kBlockPollSteps + 2, j->Kcap + 1), st_)) {
+      j->store = true;
+    } else {
+      j->free_store(false);
+      if ((e = j->set_ring(st_)) != hipSuccess) return e;
+    }
+  }
+  j->stored_last = false;
   e = hipMemsetAsync(J.active, 0, 16, st_);
   if (e != hipSuccess) return e;
   e = j->sync_desc(st_);
@@ -188,6 +257,25 @@ hipError_t BEngine::start(BlockJob *j) {
   p1_.push_back(j);
   dirty1_ = true;
   return hipSuccess;
+}
+
+// Store mode: the basis is complete in memory; solve the projected systems
+// backwards, form the coefficients and accumulate the moments from the stored
+// blocks in the same windows as the second pass would (same bits).
+hipError_t BEngine::finish_stored(BlockJob *j) {
+  BJobDesc &J = j->h;
+  hipError_t e = launch_b_backsolve(J, j->K, st_);
+  if (e != hipSuccess) return e;
+  if ((e = launch_b_fcoef(J, j->K, st_)) != hipSuccess) return e;
+  if ((e = hipMemsetAsync(J.Sout, 0, 8 * (size_t)J.npad * J.Kmom * J.L, st_)) != hipSuccess) return e;
+  for (int k0 = 0; k0 < j->K; k0 += kMomWindow)
+    if ((e = launch_b_moments(J, k0, std::min(kMomWindow, j->K - k0), st_)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st_)) != hipSuccess) return e;
+  j->free_store(true);
+  j->store = false;
+  j->stored_last = true;
+  j->pass = 3;
+  return j->set_ring(st_);
 }
 
 hipError_t BEngine::enter_pass2(BlockJob *j) {
@@ -337,8 +425,30 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
       j->steps_last = j->K;
       j->converged = (act[i] == 0);
       dirty1_ = true;
-      if ((e = enter_pass2(j)) != hipSuccess) return e;
+      if (j->store) {
+        if ((e = finish_stored(j)) != hipSuccess) return e;
+        finished->push_back(j);
+      } else if ((e = enter_pass2(j)) != hipSuccess) {
+        return e;
+      }
     } else {
+      // blocks up to Q_{steps + kBlockPoll + 1} exist before the next poll (none past Q_Kcap)
+      if (j->store && !j->grow_store(std::min(steps + kBlockPollSteps + 2, j->Kcap + 1), st_)) {
+        // out of memory for the stored basis: continue with the ring (blocks
+        // Q_{k-1} and Q_k move there) and regenerate the basis in pass 2
+        BJobDesc &J = j->h;
+        const size_t blk = sizeof(double) * (size_t)J.n * J.Lp;
+        for (int kk = std::max(steps - 1, 0); kk <= steps; ++kk) {
+          const double *src = j->qtab[kk / kStoreChunk] + (size_t)(kk % kStoreChunk) * J.n * J.Lp;
+          double *dst = J.Q + (size_t)(kk % J.nring) * J.n * J.Lp;
+          if ((e = hipMemcpyAsync(dst, src, blk, hipMemcpyDeviceToDevice, st_)) != hipSuccess) return e;
+        }
+        if ((e = hipStreamSynchronize(st_)) != hipSuccess) return e;
+        j->free_store(false);
+        if ((e = j->set_ring(st_)) != hipSuccess) return e;
+        if ((e = j->sync_desc(st_)) != hipSuccess) return e;
+        dirty1_ = true;
+      }
       keep1.push_back(j);
     }
   }

@@ -1,20 +1,34 @@
 // Host side of the block Lanczos engine (see k_block.hip for the method).
 #pragma once
 
+#include <memory>
 #include <vector>
 
 #include "engine.h"
 
 namespace csvd {
 
+// Basis blocks per allocation of the stored basis
+constexpr int kStoreChunk = 64;
+// device memory left free when the stored basis grows (bytes)
+constexpr size_t kStoreReserve = (size_t)8 << 30;
+
 // One block Lanczos problem: device histories, work blocks and the pass
 // state.  Pass 1 builds the block tridiagonal matrix and monitors every
-// (shift, column) residual; pass 2 regenerates the basis and accumulates the
-// moments into Sout.
+// (shift, column) residual.  If the whole basis fits in device memory it is
+// kept (store mode) and the moments are accumulated from it right after
+// pass 1; otherwise pass 2 regenerates the basis in a ring of kMomWindow + 2
+// blocks and accumulates the moments as it goes.
 struct BlockJob {
   BJobDesc h{};
-  DevBuf mem, d_shift, d_cmom, d_desc, d_toff;
+  DevBuf mem, d_shift, d_cmom, d_desc, d_toff, d_qtab;
   BBatch solo{};
+  std::vector<double *> qtab;                  // host copy of the basis table
+  std::vector<std::unique_ptr<DevBuf>> chunks;  // stored basis, kStoreChunk blocks each
+  std::vector<std::unique_ptr<DevBuf>> *cache = nullptr;  // chunks kept between solves (owner's)
+  bool want_store = true;  // try store mode (the server keeps the ring: its budget covers the job only)
+  bool store = false;      // store mode active for the current pass 1
+  bool stored_last = false;  // the last round's moments came from a stored basis
   int pass = 0;            // 0 idle, 1 building the basis, 2 accumulating moments, 3 done
   int K = 0;               // block steps used by the solution
   int Kcap = 0;
@@ -29,6 +43,12 @@ struct BlockJob {
                     const std::vector<double> &cre, const std::vector<double> &cim, int cstride, hipStream_t st);
   // copies the host descriptor to the device copy used by solo launches
   hipError_t sync_desc(hipStream_t st);
+  // basis table: ring mode, or store mode with chunks covering blocks
+  // 0 .. kneed (false: memory did not allow it)
+  hipError_t set_ring(hipStream_t st);
+  bool grow_store(int kneed, hipStream_t st);
+  // keep: the chunks go to the cache for the next solve; else they are freed
+  void free_store(bool keep);
 };
 
 // The per-shift recurrences (b_shift) of step k depend only on A_k, B_k and
@@ -55,6 +75,7 @@ class BEngine {
  private:
   hipError_t rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &dt, BBatch &b);
   hipError_t enter_pass2(BlockJob *j);
+  hipError_t finish_stored(BlockJob *j);
   hipError_t launch_shift(const BBatch &b, int init);
   hipStream_t st_;
   hipStream_t side_ = nullptr;

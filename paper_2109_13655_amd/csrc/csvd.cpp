@@ -204,6 +204,7 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
     return set_err(ctx, CSVD_EINVAL, "solver must be CSVD_SOLVER_AUTO, CSVD_SOLVER_BLOCK or CSVD_SOLVER_SINGLE");
   if (p->solver == CSVD_SOLVER_BLOCK && (pad_L(p->L) > kBlockMaxLp || p->precision != CSVD_FP64))
     return set_err(ctx, CSVD_EINVAL, "the block solver needs L <= 64 and CSVD_FP64");
+  if (p->keep_basis != 0 && p->keep_basis != 1) return set_err(ctx, CSVD_EINVAL, "keep_basis must be 0 or 1");
   return CSVD_OK;
 }
 
@@ -219,7 +220,7 @@ int pad_L(int L) {
 }
 
 // the block solver needs the padded width within its LDS-staged kernels
-constexpr int kBlockPoll = 4;  // block steps between convergence polls
+constexpr int kBlockPoll = kBlockPollSteps;
 
 // Automatic choice: the block basis only when the matrix has at least
 // kBlockMinRatio columns per basis column.  Below that a few block steps
@@ -366,6 +367,8 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
                                M + 1, p->solve_rtol, R.spec.shift_re, R.spec.shift_im, R.spec.c_re, R.spec.c_im,
                                M + 1, ctx->st));
     R.bjob->h.Kmom = Kmom;
+    R.bjob->want_store = (p->keep_basis != 0);
+    R.bjob->cache = &ctx->basis_cache;
     // the deflation test of the basis is relative to ||A^T A||
     double na = p->norm_a;
     if (!(na > 0)) {
@@ -761,6 +764,7 @@ int run_finalize(SolveRun &R) {
     int fl = 0;
     HIPCHK(ctx, hipMemcpy(&fl, R.bjob->h.flags, sizeof(int), hipMemcpyDeviceToHost));
     info.deflated = fl;
+    info.basis_stored = R.bjob->stored_last ? 1 : 0;
   } else {
     info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
     info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + 4.0 * n);
@@ -851,6 +855,7 @@ int csvd_params_default(csvd_params *p) {
   p->window = 0;
   p->check_solves = 0;
   p->solver = CSVD_SOLVER_AUTO;
+  p->keep_basis = 1;
   return CSVD_OK;
 }
 
@@ -909,6 +914,14 @@ int csvd_create(csvd_ctx **out, int64_t m, int64_t n, int64_t nnz, const int32_t
 }
 
 void csvd_destroy(csvd_ctx *ctx) { delete ctx; }
+
+int csvd_trim(csvd_ctx *ctx) {
+  if (!ctx) return CSVD_EINVAL;
+  ctx->err.clear();
+  if (hipStreamSynchronize(ctx->st) != hipSuccess) return set_err(ctx, CSVD_EDEVICE, "stream synchronize failed");
+  ctx->basis_cache.clear();
+  return CSVD_OK;
+}
 
 const char *csvd_last_error(const csvd_ctx *ctx) {
   if (!ctx) return "null context";
@@ -1296,6 +1309,8 @@ static int srv_admit(csvd_server *s) {
       R.run.reset();
       continue;
     }
+    // the budget covers the job's own allocation, not a stored basis
+    if (R.run->bjob) R.run->bjob->want_store = false;
     s->used += R.bytes;
     R.state = 1;
     if (R.run->block) {

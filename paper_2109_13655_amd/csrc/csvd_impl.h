@@ -101,7 +101,9 @@ struct BJobDesc {
   int G2, lgG2, E2, rpt2, tiles2;  // tiling of the A^T product (n rows)
   int nchunk;                      // 64-row chunks of the tall kernels
   int nvb;                         // workgroups per tall kernel (each walks chunks vb, vb + nvb, ...)
-  int nring;                       // slots of the basis ring: Q_k in slot k mod nring
+  int nring;                       // slots of the basis ring
+  int qC, qT;                      // basis table: Q_k at Qtab[(k / qC) mod qT] + (k mod qC) n Lp
+  double *const *Qtab;             // qT block pointers (ring: one entry, the ring, qC = nring)
   int Kcap;                        // capacity of the per-step histories
   int Kstop;                       // steps of the current pass that do work (later steps are no-ops)
   int start_clock;                 // engine clock of step 0 of the current pass
@@ -110,7 +112,7 @@ struct BJobDesc {
   double tol;
   double dscale;                   // ||A||^2 estimate: scale of the deflation test
   double *U;                       // m x Lp
-  double *Q;                       // nring x (n x Lp): slot (k mod nring) holds Q_k
+  double *Q;                       // the ring: nring x (n x Lp)
   double *W;                       // n x Lp work block
   double *Vpad;                    // n x Lp: the padded starting block
   double *gpart;                   // nvb x 2 x Lp x Lp partial Gram matrices
@@ -129,6 +131,13 @@ struct BJobDesc {
   double *Sout;                    // npad x (Kmom L) column-major moments
 };
 
+// Q_k of a block job (ring slot, or the stored basis)
+__device__ __forceinline__ GLB double *qblock(const BJobDesc &J, int k) {
+  typedef GLB double *gptr;
+  const GLB gptr *tab = (const GLB gptr *)(J.Qtab);
+  return tab[(k / J.qC) % J.qT] + (int64_t)(k % J.qC) * J.n * J.Lp;
+}
+
 struct BBatch {
   const BJobDesc *jobs;
   int njob;
@@ -142,6 +151,7 @@ constexpr int kBlockMaxLp = 64;   // widest block of the block Lanczos engine
 constexpr int kBlockMinLp = 16;   // narrowest (MFMA tile width)
 constexpr int kBlockPanel = 64;   // rows per chunk of the tall kernels
 constexpr int kBlockMaxVB = 256;  // workgroups per job in the tall kernels
+constexpr int kBlockPollSteps = 4;  // block steps between convergence polls
 constexpr int kMomWindow = 16;   // second-pass steps per moment accumulation (basis ring = window + 2)
 constexpr double kDeflTol = 1e-10;  // relative size below which a new basis direction is deflated
 

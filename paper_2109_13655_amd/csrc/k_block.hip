@@ -492,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void b_moments(BJobDesc J, int k0, int T)
       }
     }
     __syncthreads();
-    const GLB double *__restrict__ Qk = gp(J.Q) + (int64_t)(k % J.nring) * nL;
+    const GLB double *__restrict__ Qk = qblock(J, k);
     double a[KS];
     const int64_t row = r0 + rl;
 #pragma unroll

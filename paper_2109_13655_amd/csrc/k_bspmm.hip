@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict_
     const int k = (int)(ck - J.start_clock);
     if (k >= J.Kstop) continue;
     const int64_t nL = (int64_t)J.n * J.Lp;
-    tile_spmm(gp(J.rp), gp(J.ci), gp(J.va), gp(J.Q) + (int64_t)(k % J.nring) * nL, gp(J.U), J.m, g - toff[j], J.rpt1,
+    tile_spmm(gp(J.rp), gp(J.ci), gp(J.va), qblock(J, k), gp(J.U), J.m, g - toff[j], J.rpt1,
               J.lgLp, J.G1, J.lgG1, J.E1, gsum);
   }
 }

@@ -232,8 +232,8 @@ __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__
   const int t = threadIdx.x, w = t >> 6;
   const int64_t n = J.n, nL = n * LP;
   GLB double *X = init ? gp(J.Vpad) : gp(J.W);
-  const GLB double *Qc = gp(J.Q) + (int64_t)(k % J.nring) * nL;
-  const GLB double *Pv = gp(J.Q) + (int64_t)((k + J.nring - 1) % J.nring) * nL;
+  const GLB double *Qc = qblock(J, k);
+  const GLB double *Pv = qblock(J, k > 0 ? k - 1 : k);
   const bool useQ = !init && (mode != kTallAlpha || k > 0);
   if (mode == kTallAlpha) {
     if (useQ) stage_mat<LP>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
@@ -288,8 +288,8 @@ __global__ __launch_bounds__(kThreads) void bs_gamma(const BJobDesc *__restrict_
   const int w = threadIdx.x >> 6;
   const int64_t n = J.n, nL = n * LP;
   const GLB double *X = init ? gp(J.Vpad) : gp(J.W);
-  const GLB double *Qc = gp(J.Q) + (int64_t)(k % J.nring) * nL;
-  GLB double *Qn = gp(J.Q) + (int64_t)((init ? k : k + 1) % J.nring) * nL;
+  const GLB double *Qc = qblock(J, k);
+  GLB double *Qn = qblock(J, init ? k : k + 1);
   stage_mat<LP>(gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2, false, false, S1);
   if (!init) stage_mat<LP>(gp(J.Nh) + (int64_t)k * L2, false, true, S2);
   __syncthreads();

@@ -160,6 +160,38 @@ def test_block_and_single_solvers_agree():
         cs.csvd_destroy(ctx)
 
 
+def test_block_stored_basis_equals_regenerated():
+    """Keeping the block basis in device memory and regenerating it in a
+    second pass accumulate the same moments from the same blocks: the bits
+    agree.  The basis spans several storage chunks of 64 blocks here."""
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 12)
+    ctx = make_ctx(I)
+    try:
+        out = []
+        for keep in (1, 0):
+            p = cs.csvd_params_default(L=8, M=4, N=16, ell=2, norm_a=1.0, solver=cs.CSVD_SOLVER_BLOCK,
+                                       keep_basis=keep)
+            st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+            info = cs.csvd_get_info(ctx)
+            say("keep_basis", keep, "status", st, "steps", info.iterations, "stored", info.basis_stored)
+            assert st == cs.CSVD_OK and info.basis_stored == keep
+            assert info.iterations > 128
+            out.append(cs.csvd_get_triplets(ctx, I.m, I.n) + (cs.csvd_get_moment(ctx, 0, I.n, 8),))
+        # the kept chunks are reused by the next solve, and freed on request
+        st = cs.csvd_solve_interval(ctx, I.a, I.b, cs.csvd_params_default(
+            L=8, M=4, N=16, ell=2, norm_a=1.0, solver=cs.CSVD_SOLVER_BLOCK), V)
+        assert st == cs.CSVD_OK and cs.csvd_get_info(ctx).basis_stored == 1
+        out.append(cs.csvd_get_triplets(ctx, I.m, I.n) + (cs.csvd_get_moment(ctx, 0, I.n, 8),))
+        cs.csvd_trim(ctx)
+        for x, y in zip(out[0], out[1]):
+            assert np.array_equal(x, y)
+        for x, y in zip(out[0], out[2]):
+            assert np.array_equal(x, y)
+    finally:
+        cs.csvd_destroy(ctx)
+
+
 def test_prop1_on_gpu_moments():
     """Proposition 1 on the GPU output: S_k = (A^T A)^k S_0 (plain rule)."""
     I = _small_problem()
