@@ -9,6 +9,18 @@ namespace csvd {
 
 static int lp_bit(int Lp) { return Lp == 16 ? 1 : (Lp == 32 ? 2 : 4); }
 
+// Tiles of the block sparse products: rows with few nonzeros (G = 1) are
+// handled four columns per lane, kThreads / (Lp / 4) rows per tile.
+static Tiling block_tiling(int64_t rows, int64_t nnz, int Lp) {
+  Tiling t = tiling_for(rows, nnz, Lp);
+  if (t.G == 1) {
+    t.E = 1;
+    t.rpt = kThreads * 4 / Lp;
+    t.tiles = (int)((rows + t.rpt - 1) / t.rpt);
+  }
+  return t;
+}
+
 size_t BlockJob::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int Kcap, int L, int Kmom) {
   (void)nnz;
   const int64_t L2 = (int64_t)Lp * Lp;
@@ -49,7 +61,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.rp = rp; J.ci = ci; J.va = va; J.rpT = rpT; J.ciT = ciT; J.vaT = vaT;
   J.m = (int)m; J.n = (int)n; J.Lp = Lp; J.lgLp = ilog2i(Lp); J.L = L; J.S = S;
   J.npad = (int)round_up(n, kRowPad);
-  const Tiling t1 = tiling_for(m, nnz, Lp), t2 = tiling_for(n, nnz, Lp);
+  const Tiling t1 = block_tiling(m, nnz, Lp), t2 = block_tiling(n, nnz, Lp);
   J.G1 = t1.G; J.lgG1 = t1.lgG; J.E1 = t1.E; J.rpt1 = t1.rpt; J.tiles1 = t1.tiles;
   J.G2 = t2.G; J.lgG2 = t2.lgG; J.E2 = t2.E; J.rpt2 = t2.rpt; J.tiles2 = t2.tiles;
   J.nchunk = (int)((n + kBlockPanel - 1) / kBlockPanel);

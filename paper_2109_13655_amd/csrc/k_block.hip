@@ -13,8 +13,9 @@
 // residual norms ||Z_{k+1}(:, l)|| of the block Galerkin solutions.  After
 // convergence the block tridiagonal systems are solved backwards,
 //   Y_{K-1} = H_{K-1}^{-1} Z_{K-1},  Y_k = H_k^{-1} (Z_k + B_{k+1}^T Y_{k+1}),
-// the moment coefficients F_k = sum_s 2 Re(c_sk Y_{s,k}) are formed, and a
-// second pass regenerates Q_k bit for bit and accumulates S += Q_k F_k.
+// the moment coefficients F_k = sum_s 2 Re(c_sk Y_{s,k}) are formed, and
+// S += Q_k F_k is accumulated from the stored basis, or from a second pass
+// that regenerates Q_k bit for bit.
 #include "csvd_impl.h"
 
 namespace csvd {
@@ -56,6 +57,7 @@ __device__ __forceinline__ double2 cdivb(double2 a, double2 b) {
 // barrier per step.  All Lp columns of Z are carried (the first L are the
 // right-hand sides).
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ v4d mfma4b(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -348,67 +350,92 @@ hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st) {
 // ------------------------------------------------------ backward solution
 // Y_k = H_k^{-1} (Z_k + B_{k+1}^T Y_{k+1}), k = K-1 .. 0; Y_k overwrites Z_k
 // (columns < L).  The columns are independent: one workgroup per (shift,
-// group of 16 columns), H_k^{-1} staged in LDS for each step.
+// group of 16 columns).  The recurrence is sequential in k, so the operands
+// of step k - 1 (H^{-1}, B, the Z rows) are loaded into registers while step
+// k computes, and staged in LDS at the start of the next step.
 constexpr int kBsCols = 16;
 
 __global__ __launch_bounds__(kThreads) void b_backsolve(BJobDesc J, int K) {
+  constexpr int IT = kBlockMaxLp * kBlockMaxLp / kThreads, RI = kBlockMaxLp / (kThreads / kBsCols);
   __shared__ double2 Hs[kBlockMaxLp * kBlockMaxLp];
+  __shared__ double Bs[kBlockMaxLp * kBlockMaxLp];
   __shared__ double2 Ts[kBlockMaxLp * kBsCols], Yn[kBlockMaxLp * kBsCols];
   const int ng = (J.L + kBsCols - 1) / kBsCols;
   const int s = blockIdx.x / ng, cg = blockIdx.x - s * ng;
   const int Lp = J.Lp, L2 = Lp * Lp, L = J.L;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, i0 = t >> 4;
   const int jj = t & (kBsCols - 1), col = cg * kBsCols + jj;
   const bool live = col < L;
   const int64_t hbase = (int64_t)s * (J.Kcap + 1) * L2;
   const GLB double2 *__restrict__ Hinv = gp(J.Hinv) + hbase;
   GLB double2 *__restrict__ Zh = gp(J.Zh) + hbase;
-  for (int k = K - 1; k >= 0; --k) {
+  double2 hv[IT], zv[RI], zn[RI];
+  double bv[IT];
+  // operands of step k: H_k^{-1}, B_{k+1} (none for the last step), rows of Z_k
+  auto fetch = [&](int k, double2 (&z)[RI]) {
     const GLB double2 *__restrict__ Hk = Hinv + (int64_t)k * L2;
-    {
-      constexpr int IT = kBlockMaxLp * kBlockMaxLp / kThreads;
-      double2 hv[IT];
-#pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        const int e = t + it * kThreads;
-        hv[it] = make_double2(0.0, 0.0);
-        if (e < L2) {
-          const double2 h = Hk[e];
-          hv[it] = h;
-        }
-      }
-#pragma unroll
-      for (int it = 0; it < IT; ++it) {
-        const int e = t + it * kThreads;
-        if (e < L2) Hs[e] = hv[it];
-      }
-    }
-    // T = Z_k + B_{k+1}^T Y_{k+1} for this thread's rows
     const GLB double *__restrict__ Bk1 = gp(J.Bh) + (int64_t)(k + 1) * L2;
-    for (int i = t >> 4; i < Lp; i += kThreads / kBsCols) {
-      double2 acc = live ? Zh[(int64_t)k * L2 + i * Lp + col] : make_double2(0.0, 0.0);
-      if (k < K - 1) {
-        for (int c = 0; c <= i; ++c) {  // (B^T)[i][c] = B[c][i], B upper
-          const double bv = Bk1[c * Lp + i];
-          const double2 y = Yn[c * kBsCols + jj];
-          acc.x = fma(bv, y.x, acc.x);
-          acc.y = fma(bv, y.y, acc.y);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      hv[it] = make_double2(0.0, 0.0);
+      if (e < L2) hv[it] = Hk[e];
+      bv[it] = (e < L2 && k < K - 1) ? Bk1[e] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int i = i0 + r * (kThreads / kBsCols);
+      z[r] = make_double2(0.0, 0.0);
+      if (i < Lp && live) z[r] = Zh[(int64_t)k * L2 + i * Lp + col];
+    }
+  };
+  if (K > 0) fetch(K - 1, zv);
+  for (int k = K - 1; k >= 0; --k) {
+    __syncthreads();  // the previous step is done with Hs, Bs and Ts
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      const int e = t + it * kThreads;
+      if (e < L2) {
+        Hs[e] = hv[it];
+        Bs[e] = bv[it];
+      }
+    }
+    __syncthreads();
+    if (k > 0) fetch(k - 1, zn);
+    // T = Z_k + B_{k+1}^T Y_{k+1} for this thread's rows; (B^T)[i][c] = B[c][i], B upper
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int i = i0 + r * (kThreads / kBsCols);
+      if (i < Lp) {
+        double2 acc = zv[r];
+        if (k < K - 1) {
+          for (int c = 0; c <= i; ++c) {
+            const double b = Bs[c * Lp + i];
+            const double2 y = Yn[c * kBsCols + jj];
+            acc.x = fma(b, y.x, acc.x);
+            acc.y = fma(b, y.y, acc.y);
+          }
         }
+        Ts[i * kBsCols + jj] = acc;
       }
-      Ts[i * kBsCols + jj] = acc;
     }
     __syncthreads();
-    for (int i = t >> 4; i < Lp; i += kThreads / kBsCols) {
-      double2 acc = make_double2(0.0, 0.0);
-      for (int c = 0; c < Lp; ++c) {
-        const double2 r = cmulb(Hs[i * Lp + c], Ts[c * kBsCols + jj]);
-        acc.x += r.x;
-        acc.y += r.y;
+#pragma unroll
+    for (int r = 0; r < RI; ++r) {
+      const int i = i0 + r * (kThreads / kBsCols);
+      if (i < Lp) {
+        double2 acc = make_double2(0.0, 0.0);
+        for (int c = 0; c < Lp; ++c) {
+          const double2 p = cmulb(Hs[i * Lp + c], Ts[c * kBsCols + jj]);
+          acc.x += p.x;
+          acc.y += p.y;
+        }
+        Yn[i * kBsCols + jj] = acc;
+        if (live) Zh[(int64_t)k * L2 + i * Lp + col] = acc;
       }
-      Yn[i * kBsCols + jj] = acc;
-      if (live) Zh[(int64_t)k * L2 + i * Lp + col] = acc;
     }
-    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RI; ++r) zv[r] = zn[r];
   }
 }
 
@@ -450,77 +477,130 @@ hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st) {
 
 // ------------------------------------------------------ moment accumulation
 // S(r, col) += sum_b sum_c Q_{k0+b}(r, c) F_{k0+b}(c, col), S column-major
-// (ld npad), F column-major per step (Lp x KL).  Workgroup: 64 rows x 192
-// columns; each wave a 16-row panel (MFMA 16x16x4, contraction index split
-// as in the tall kernels), F_b slices staged in LDS, the result added to S
+// (ld npad), F column-major per step (Lp x KL).  A product with a long
+// contraction (T Lp) and a thin result, bound by the FP64 MFMA rate.
+// Workgroup tile: 64 WR rows x COLS columns, each wave WR tiles of 16 rows
+// (MFMA 16x16x4; lane (rl, q) supplies Q(row rl, c) with c = 4 q + ks of
+// the chunk).  The contraction runs in chunks of 16 indices: while the MFMAs
+// of one chunk run from one LDS buffer, the next chunk of F is loaded into
+// registers (then stored into the other buffer) and the next Q fragments are
+// loaded ahead, one barrier per chunk.  At the end the result is added to S
 // through an LDS transpose so that each column segment is written whole.
-constexpr int kMomCols = 192;
+constexpr int kMomKC = 16;            // contraction indices per staged chunk
+constexpr int kMomWR = 1;             // 16-row tiles per wave
+constexpr int kMomOcc = 3;            // workgroups per CU the registers are sized for
+constexpr int kMomCols = 96;          // result columns per workgroup
 
-template <int LP>
-__global__ __launch_bounds__(kThreads) void b_moments(BJobDesc J, int k0, int T) {
-  constexpr int KS = LP / 4, NTL = kMomCols / 16, FS = kMomCols + 1;
-  __shared__ double Fs[LP * FS];
-  __shared__ double Cs[64 * 65];
+template <int LP, int WR, int OCC, int COLS>
+__global__ __launch_bounds__(kThreads, OCC) void b_moments(BJobDesc J, int k0, int T) {
+  static_assert(LP % kMomKC == 0, "chunks of 16 contraction indices");
+  constexpr int NTL = COLS / 16, NCH = LP / kMomKC;
+  // LDS row stride: the k-groups q = 0, 1 of one B-fragment read hit disjoint banks
+  constexpr int FS = COLS + 4;
+  static_assert(FS % 8 == 4, "bank offset of the k-groups");
+  constexpr int FL = kMomKC * COLS / kThreads;  // F loads per thread and chunk
+  static_assert(FL * kThreads == kMomKC * COLS, "whole chunks");
+  constexpr int FBUF = kMomKC * FS, ROWS = 64 * WR, CS = ROWS + 1;
+  // epilogue column group: the transpose buffer reuses the F buffers
+  constexpr int CG = (64 * CS <= 2 * FBUF && COLS % 64 == 0) ? 64 : 32;
+  static_assert(CG * CS <= 2 * FBUF && COLS % CG == 0, "transpose fits the F buffers");
+  __shared__ double sm[2 * FBUF];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
-  const int64_t n = J.n, nL = n * LP;
+  const int64_t n = J.n;
   const int KL = J.Kmom * J.L;
-  const int64_t rb = (int64_t)blockIdx.x * 64, r0 = rb + 16 * w;
-  const int col0 = blockIdx.y * kMomCols;
-  v4d acc[NTL];
+  const int64_t rb = (int64_t)blockIdx.x * ROWS;
+  const int col0 = blockIdx.y * COLS;
+  v4d acc[WR][NTL];
 #pragma unroll
-  for (int i = 0; i < NTL; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int b = 0; b < T; ++b) {
-    const int k = k0 + b;
-    const GLB double *__restrict__ Fk = gp(J.F) + (int64_t)k * KL * LP;
-    __syncthreads();
-    // F_b slice: LP x 192, loaded 16 entries per thread at a time so that the
-    // loads of a batch are all in flight before the LDS stores
-    constexpr int IT = LP * kMomCols / kThreads, BATCH = 16;
+  for (int r = 0; r < WR; ++r)
 #pragma unroll
-    for (int i0 = 0; i0 < IT; i0 += BATCH) {
-      double fv[BATCH];
+    for (int i = 0; i < NTL; ++i) acc[r][i] = v4d{0.0, 0.0, 0.0, 0.0};
+  double fv[FL], a[WR][4], an[WR][4];
+  // chunk g: step k0 + g / NCH, contraction indices 16 (g % NCH) + 0..15
+  auto load_f = [&](int g) {
+    const GLB double *__restrict__ Fk =
+        gp(J.F) + (int64_t)(k0 + g / NCH) * KL * LP + (g % NCH) * kMomKC;
 #pragma unroll
-      for (int i = 0; i < BATCH; ++i) {
-        const int e = t + (i0 + i) * kThreads;
-        const int col = e / LP, c = e % LP;
-        fv[i] = (i0 + i < IT && col0 + col < KL) ? Fk[(int64_t)(col0 + col) * LP + c] : 0.0;
-      }
+    for (int i = 0; i < FL; ++i) {
+      const int e = t + i * kThreads, col = e >> 4, c = e & 15;
+      fv[i] = (col0 + col < KL) ? Fk[(int64_t)(col0 + col) * LP + c] : 0.0;
+    }
+  };
+  auto store_f = [&](int buf) {
+    double *Fs = sm + buf * FBUF;
 #pragma unroll
-      for (int i = 0; i < BATCH; ++i) {
-        const int e = t + (i0 + i) * kThreads;
-        if (i0 + i < IT) Fs[(e % LP) * FS + e / LP] = fv[i];
+    for (int i = 0; i < FL; ++i) {
+      const int e = t + i * kThreads;
+      Fs[(e & 15) * FS + (e >> 4)] = fv[i];
+    }
+  };
+  auto load_q = [&](int g, double (&x)[WR][4]) {
+    const GLB double *__restrict__ Qk = qblock(J, k0 + g / NCH) + (g % NCH) * kMomKC + 4 * q;
+#pragma unroll
+    for (int r = 0; r < WR; ++r) {
+      const int64_t row = rb + 16 * (w * WR + r) + rl;
+      if (row < n) {
+        const GLB v2d *p = reinterpret_cast<const GLB v2d *>(Qk + row * LP);
+        const v2d x0 = p[0], x1 = p[1];
+        x[r][0] = x0.x;
+        x[r][1] = x0.y;
+        x[r][2] = x1.x;
+        x[r][3] = x1.y;
+      } else {
+        x[r][0] = x[r][1] = x[r][2] = x[r][3] = 0.0;
       }
     }
-    __syncthreads();
-    const GLB double *__restrict__ Qk = qblock(J, k);
-    double a[KS];
-    const int64_t row = r0 + rl;
-#pragma unroll
-    for (int i = 0; i < KS; ++i) a[i] = (row < n) ? Qk[row * LP + q * KS + i] : 0.0;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const double *fr = Fs + (q * KS + ks) * FS + rl;
-#pragma unroll
-      for (int tt = 0; tt < NTL; ++tt) acc[tt] = mfma4b(a[ks], fr[16 * tt], acc[tt]);
+  };
+  const int G = T * NCH;
+  load_f(0);
+  load_q(0, a);
+  store_f(0);
+  __syncthreads();
+  for (int g = 0; g < G; ++g) {
+    const bool more = g + 1 < G;
+    if (more) {
+      load_f(g + 1);
+      load_q(g + 1, an);
     }
+    const double *Fs = sm + (g & 1) * FBUF + q * 4 * FS + rl;
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int tt = 0; tt < NTL; ++tt) {
+        const double b = Fs[ks * FS + 16 * tt];
+#pragma unroll
+        for (int r = 0; r < WR; ++r) acc[r][tt] = mfma4b(a[r][ks], b, acc[r][tt]);
+      }
+    if (more) {
+      store_f((g + 1) & 1);
+#pragma unroll
+      for (int r = 0; r < WR; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[r][i] = an[r][i];
+    }
+    __syncthreads();
   }
-  // add to S in column segments of 64 rows: 64 columns at a time via LDS
-  for (int cg = 0; cg < kMomCols; cg += 64) {
+  // add to S in column segments of ROWS rows, CG columns at a time
+  double *Cs = sm;
+#pragma unroll
+  for (int cg = 0; cg < COLS; cg += CG) {
     __syncthreads();
 #pragma unroll
     for (int tt = 0; tt < NTL; ++tt) {
-      if (16 * tt >= cg && 16 * tt < cg + 64)
+      if (16 * tt >= cg && 16 * tt < cg + CG)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Cs[(16 * tt - cg + rl) * 65 + 16 * w + q + 4 * v] = acc[tt][v];
+        for (int r = 0; r < WR; ++r)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Cs[(16 * tt - cg + rl) * CS + 16 * (w * WR + r) + q + 4 * v] = acc[r][tt][v];
     }
     __syncthreads();
-    for (int e = t; e < 64 * 64; e += kThreads) {
-      const int cl = e >> 6, rr = e & 63;
+    for (int e = t; e < CG * ROWS; e += kThreads) {
+      const int cl = e / ROWS, rr = e % ROWS;
       const int col = col0 + cg + cl;
       const int64_t row = rb + rr;
       if (col < KL && row < n) {
         GLB double *sp = gp(J.Sout) + (int64_t)col * J.npad + row;
-        *sp += Cs[cl * 65 + rr];
+        *sp += Cs[cl * CS + rr];
       }
     }
   }
@@ -529,11 +609,12 @@ __global__ __launch_bounds__(kThreads) void b_moments(BJobDesc J, int k0, int T)
 hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st) {
   if (T <= 0) return hipSuccess;
   const int KL = hj.Kmom * hj.L;
-  const dim3 g((unsigned)((hj.n + 63) / 64), (unsigned)((KL + kMomCols - 1) / kMomCols));
+  constexpr int ROWS = 64 * kMomWR, C = kMomCols;
+  const dim3 g((unsigned)((hj.n + ROWS - 1) / ROWS), (unsigned)((KL + C - 1) / C));
   switch (hj.Lp) {
-    case 16: hipLaunchKernelGGL(b_moments<16>, g, dim3(kThreads), 0, st, hj, k0, T); break;
-    case 32: hipLaunchKernelGGL(b_moments<32>, g, dim3(kThreads), 0, st, hj, k0, T); break;
-    default: hipLaunchKernelGGL(b_moments<64>, g, dim3(kThreads), 0, st, hj, k0, T); break;
+    case 16: hipLaunchKernelGGL((b_moments<16, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
+    case 32: hipLaunchKernelGGL((b_moments<32, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
+    default: hipLaunchKernelGGL((b_moments<64, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
   }
   return hipGetLastError();
 }

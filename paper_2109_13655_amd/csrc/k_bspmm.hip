@@ -1,13 +1,19 @@
 // Sparse products of the block Lanczos step (operator apply, Algorithm 1
 // step 1): U = A Q_k and W = A^T U on row-major n x Lp blocks, CSR FP64.
 //
-// A tile of rows is spread over the 256 threads as (row, lane group, column):
-// the Lp threads of a row read one 8*Lp-byte row of the gathered block per
-// nonzero (coalesced), and G lane groups split the nonzeros of a long row;
-// their partial sums are added in a fixed order through LDS.
+// Rows with few nonzeros (G = 1): Lp/4 lanes share a row, four columns each
+// (two 16-byte loads per gathered row), so a wave works on 256/Lp rows at
+// once, and four nonzeros of a row are gathered before their products are
+// added in order.  Long rows: a tile of rows is spread over the 256 threads
+// as (row, lane group, column), the Lp threads of a row read one 8*Lp-byte
+// row of the gathered block per nonzero, and G lane groups split the
+// nonzeros of the row; their partial sums are added in a fixed order through
+// LDS.  Both add each row's products in the order of its nonzeros.
 #include "csvd_impl.h"
 
 namespace csvd {
+
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int bfind_sp(const int *__restrict__ toff, int njob, int g) {
   int lo = 0, hi = njob - 1;
@@ -51,6 +57,70 @@ __device__ __forceinline__ void tile_spmm(const GLB int *__restrict__ rp, const 
   }
 }
 
+// y = M x for one tile of kThreads / (LP / 4) rows (G = 1)
+template <int LP>
+__device__ __forceinline__ void tile_rows4(const GLB int *__restrict__ rp, const GLB int *__restrict__ ci,
+                                           const GLB double *__restrict__ va, const GLB double *__restrict__ x,
+                                           GLB double *__restrict__ y, int64_t nrows, int tile) {
+  constexpr int LPR = LP / 4, RPT = kThreads / LPR, UNR = 4;
+  const int t = threadIdx.x, c0 = (t % LPR) * 4;
+  const int64_t row = (int64_t)tile * RPT + t / LPR;
+  if (row < nrows) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int e = rp[row + 1];
+    int p = rp[row];
+    for (; p + UNR <= e; p += UNR) {
+      int c[UNR];
+      double v[UNR];
+      v2d xv[UNR][2];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        c[u] = ci[p + u];
+        v[u] = va[p + u];
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const GLB v2d *xp = reinterpret_cast<const GLB v2d *>(x + (int64_t)c[u] * LP + c0);
+        xv[u][0] = xp[0];
+        xv[u][1] = xp[1];
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        acc[0] = fma(v[u], xv[u][0].x, acc[0]);
+        acc[1] = fma(v[u], xv[u][0].y, acc[1]);
+        acc[2] = fma(v[u], xv[u][1].x, acc[2]);
+        acc[3] = fma(v[u], xv[u][1].y, acc[3]);
+      }
+    }
+    for (; p < e; ++p) {
+      const double v = va[p];
+      const GLB v2d *xp = reinterpret_cast<const GLB v2d *>(x + (int64_t)ci[p] * LP + c0);
+      const v2d x0 = xp[0], x1 = xp[1];
+      acc[0] = fma(v, x0.x, acc[0]);
+      acc[1] = fma(v, x0.y, acc[1]);
+      acc[2] = fma(v, x1.x, acc[2]);
+      acc[3] = fma(v, x1.y, acc[3]);
+    }
+    GLB v2d *yp = reinterpret_cast<GLB v2d *>(y + row * LP + c0);
+    yp[0] = v2d{acc[0], acc[1]};
+    yp[1] = v2d{acc[2], acc[3]};
+  }
+}
+
+__device__ __forceinline__ void tile_any(const GLB int *__restrict__ rp, const GLB int *__restrict__ ci,
+                                         const GLB double *__restrict__ va, const GLB double *__restrict__ x,
+                                         GLB double *__restrict__ y, int64_t nrows, int tile, int rpt, int lg, int G,
+                                         int lgG, int E, double *gsum) {
+  if (G == 1) {
+    switch (lg) {
+      case 4: tile_rows4<16>(rp, ci, va, x, y, nrows, tile); return;
+      case 5: tile_rows4<32>(rp, ci, va, x, y, nrows, tile); return;
+      default: tile_rows4<64>(rp, ci, va, x, y, nrows, tile); return;
+    }
+  }
+  tile_spmm(rp, ci, va, x, y, nrows, tile, rpt, lg, G, lgG, E, gsum);
+}
+
 __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff, int total,
                                                      const int64_t *__restrict__ clock) {
@@ -62,8 +132,8 @@ __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict_
     const int k = (int)(ck - J.start_clock);
     if (k >= J.Kstop) continue;
     const int64_t nL = (int64_t)J.n * J.Lp;
-    tile_spmm(gp(J.rp), gp(J.ci), gp(J.va), qblock(J, k), gp(J.U), J.m, g - toff[j], J.rpt1,
-              J.lgLp, J.G1, J.lgG1, J.E1, gsum);
+    tile_any(gp(J.rp), gp(J.ci), gp(J.va), qblock(J, k), gp(J.U), J.m, g - toff[j], J.rpt1, J.lgLp, J.G1,
+             J.lgG1, J.E1, gsum);
   }
 }
 
@@ -76,8 +146,8 @@ __global__ __launch_bounds__(kThreads) void b_spmm_at(const BJobDesc *__restrict
     const int j = bfind_sp(toff, njob, g);
     const BJobDesc &J = jobs[j];
     if ((int)(ck - J.start_clock) >= J.Kstop) continue;
-    tile_spmm(gp(J.rpT), gp(J.ciT), gp(J.vaT), gp(J.U), gp(J.W), J.n, g - toff[j], J.rpt2, J.lgLp, J.G2, J.lgG2,
-              J.E2, gsum);
+    tile_any(gp(J.rpT), gp(J.ciT), gp(J.vaT), gp(J.U), gp(J.W), J.n, g - toff[j], J.rpt2, J.lgLp, J.G2, J.lgG2,
+             J.E2, gsum);
   }
 }
 

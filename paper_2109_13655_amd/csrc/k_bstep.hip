@@ -18,11 +18,11 @@
 // without Gram matrices and gamma, the same kernels, so the basis is
 // reproduced bit for bit.
 //
-// Tall kernels: a job's rows are cut into 64-row chunks; each of its nvb
-// workgroups (4 waves, one 16-row panel each) walks the chunks vb, vb + nvb,
-// ... and keeps its Gram partial sums in MFMA accumulators.  The partials are
-// reduced in a fixed order, so results do not depend on timing or on which
-// other jobs share the launch.
+// Tall kernels: a job's rows are cut into 128-row chunks; each of its nvb
+// workgroups (8 waves, one 16-row panel each, two waves per SIMD) walks the
+// chunks vb, vb + nvb, ... and keeps its Gram partial sums in MFMA
+// accumulators.  The partials are reduced in a fixed order, so results do not
+// depend on timing or on which other jobs share the launch.
 #include "csvd_impl.h"
 
 namespace csvd {
@@ -30,10 +30,12 @@ namespace csvd {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
 
-constexpr int kPanel = 64;              // rows per chunk (4 waves x 16 rows)
+constexpr int kPanel = 64;              // rows staged at a time for the Gram products (4 panels)
+constexpr int kTallThreads = 512;       // threads of the tall kernels (8 waves)
+constexpr int kTallRows = 128;          // rows per chunk of the tall kernels (8 panels)
 constexpr int kSS = kBlockMaxLp + 1;    // LDS row stride of staged Lp x Lp matrices
 constexpr int kPSMax = kBlockMaxLp + 16;  // LDS row stride of staged panels (largest)
-constexpr int kMaxTiles = 7;            // Gram output tiles per wave (Lp = 64: 16 + 10 over 4 waves)
+constexpr int kMaxTiles = 4;            // Gram output tiles per wave (Lp = 64: 16 + 10 over 8 waves)
 
 __device__ __forceinline__ int bfind2(const int *__restrict__ toff, int njob, int g) {
   int lo = 0, hi = njob - 1;
@@ -136,38 +138,43 @@ __device__ __forceinline__ void gram_tile(int tau, int NT, int nfull, int &mat, 
   }
 }
 
-// Stages the wave's panels (Q part and new part, D layout) and accumulates
-// this wave's Gram tiles over the 64 rows of the chunk.
+// Accumulates this wave's Gram tiles over the 128 rows of a chunk: the eight
+// waves' panels (Q part and new part, D layout) are staged 64 rows at a time
+// (waves 0-3, then 4-7), and each wave runs its tiles over the staged rows.
 template <int LP>
 __device__ __forceinline__ void gram_chunk(const v4d (&Xd)[4], const v4d (&Yd)[4], int nfull, int ntile, double *Xs,
                                            double *Ys, v4d (&acc)[kMaxTiles]) {
   constexpr int NT = LP / 16, PS = (LP == 16) ? 16 : LP + 16;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  for (int half = 0; half < 2; ++half) {
+    if ((w >> 2) == half) {
 #pragma unroll
-  for (int nt = 0; nt < NT; ++nt) {
+      for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int rr = 16 * w + q + 4 * v;
-      if (nfull) Xs[rr * PS + 16 * nt + rl] = Xd[nt][v];
-      Ys[rr * PS + 16 * nt + rl] = Yd[nt][v];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < kMaxTiles; ++i) {
-    const int tau = w + 4 * i;
-    if (tau < ntile) {
-      int mat, ti, tj;
-      gram_tile(tau, NT, nfull, mat, ti, tj);
-      const double *Am = mat == 0 ? Xs : Ys;
-#pragma unroll
-      for (int ks = 0; ks < 16; ++ks) {
-        const int rr = 4 * ks + q;
-        acc[i] = mfma4(Am[rr * PS + 16 * ti + rl], Ys[rr * PS + 16 * tj + rl], acc[i]);
+        for (int v = 0; v < 4; ++v) {
+          const int rr = 16 * (w & 3) + q + 4 * v;
+          if (nfull) Xs[rr * PS + 16 * nt + rl] = Xd[nt][v];
+          Ys[rr * PS + 16 * nt + rl] = Yd[nt][v];
+        }
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxTiles; ++i) {
+      const int tau = w + 8 * i;
+      if (tau < ntile) {
+        int mat, ti, tj;
+        gram_tile(tau, NT, nfull, mat, ti, tj);
+        const double *Am = mat == 0 ? Xs : Ys;
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+          const int rr = 4 * ks + q;
+          acc[i] = mfma4(Am[rr * PS + 16 * ti + rl], Ys[rr * PS + 16 * tj + rl], acc[i]);
+        }
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
 // partial sums of workgroup vb: gpart[(vb * 2 + mat) * L2 + r * Lp + c]
@@ -178,7 +185,7 @@ __device__ __forceinline__ void store_gram(const BJobDesc &J, int vb, int nfull,
   GLB double *P = gp(J.gpart) + (int64_t)vb * 2 * L2;
 #pragma unroll
   for (int i = 0; i < kMaxTiles; ++i) {
-    const int tau = w + 4 * i;
+    const int tau = w + 8 * i;
     if (tau < ntile) {
       int mat, ti, tj;
       gram_tile(tau, NT, nfull, mat, ti, tj);
@@ -190,19 +197,19 @@ __device__ __forceinline__ void store_gram(const BJobDesc &J, int vb, int nfull,
 
 // LP x LP matrix from global to LDS (stride kSS), optionally transposed or
 // negated; fixed trip count, all loads of a thread issued before its stores
-template <int LP>
+template <int LP, int NTH = kThreads>
 __device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, bool trans, bool neg, double *dst) {
-  constexpr int IT = (LP * LP + kThreads - 1) / kThreads;
+  constexpr int IT = (LP * LP + NTH - 1) / NTH;
   double v[IT];
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    const int e = threadIdx.x + it * kThreads;
+    const int e = threadIdx.x + it * NTH;
     const int r = e / LP, c = e % LP;
     v[it] = (e < LP * LP) ? (trans ? src[c * LP + r] : src[e]) : 0.0;
   }
 #pragma unroll
   for (int it = 0; it < IT; ++it) {
-    const int e = threadIdx.x + it * kThreads;
+    const int e = threadIdx.x + it * NTH;
     if (e < LP * LP) dst[(e / LP) * kSS + (e % LP)] = neg ? -v[it] : v[it];
   }
 }
@@ -216,7 +223,7 @@ __device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, bo
 enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
 
 template <int LP>
-__global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__ jobs, int njob,
+__global__ __launch_bounds__(kTallThreads) void bs_tall(const BJobDesc *__restrict__ jobs, int njob,
                                                     const int *__restrict__ toff, const int64_t *__restrict__ clock,
                                                     int mode, int grams, int init) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
@@ -236,12 +243,12 @@ __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__
   const GLB double *Pv = qblock(J, k > 0 ? k - 1 : k);
   const bool useQ = !init && (mode != kTallAlpha || k > 0);
   if (mode == kTallAlpha) {
-    if (useQ) stage_mat<LP>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
+    if (useQ) stage_mat<LP, kTallThreads>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
   } else if (mode == kTallBeta) {
-    if (useQ) stage_mat<LP>(gp(J.red), false, true, S2);  // -P
+    if (useQ) stage_mat<LP, kTallThreads>(gp(J.red), false, true, S2);  // -P
   } else {
-    stage_mat<LP>(gp(J.scr) + L2, false, false, S1);           // R1^-1
-    if (useQ) stage_mat<LP>(gp(J.scr) + 2 * L2, false, true, S2);  // -T
+    stage_mat<LP, kTallThreads>(gp(J.scr) + L2, false, false, S1);           // R1^-1
+    if (useQ) stage_mat<LP, kTallThreads>(gp(J.scr) + 2 * L2, false, true, S2);  // -T
   }
   __syncthreads();
   const int nfull = (mode == kTallGamma0) ? 0 : NT * NT;
@@ -249,8 +256,9 @@ __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__
   v4d acc[kMaxTiles];
 #pragma unroll
   for (int i = 0; i < kMaxTiles; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
-  for (int ch = vb; ch < J.nchunk; ch += J.nvb) {
-    const int64_t r0 = (int64_t)ch * kPanel + 16 * w;
+  const int nch = (int)((n + kTallRows - 1) / kTallRows);
+  for (int ch = vb; ch < nch; ch += J.nvb) {
+    const int64_t r0 = (int64_t)ch * kTallRows + 16 * w;
     v4d D[4];
     if (mode == kTallGamma0) {
       zero4(D);
@@ -273,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void bs_tall(const BJobDesc *__restrict__
 // ------------------------------------------------------------------ gamma
 // Q_{k+1} = W' M_k - Q_k N_k; init = 1: Q_0 = Vpad M_init.
 template <int LP>
-__global__ __launch_bounds__(kThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
+__global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff, const int64_t *__restrict__ clock,
                                                      int init) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
@@ -290,11 +298,12 @@ __global__ __launch_bounds__(kThreads) void bs_gamma(const BJobDesc *__restrict_
   const GLB double *X = init ? gp(J.Vpad) : gp(J.W);
   const GLB double *Qc = qblock(J, k);
   GLB double *Qn = qblock(J, init ? k : k + 1);
-  stage_mat<LP>(gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2, false, false, S1);
-  if (!init) stage_mat<LP>(gp(J.Nh) + (int64_t)k * L2, false, true, S2);
+  stage_mat<LP, kTallThreads>(gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2, false, false, S1);
+  if (!init) stage_mat<LP, kTallThreads>(gp(J.Nh) + (int64_t)k * L2, false, true, S2);
   __syncthreads();
-  for (int ch = vb; ch < J.nchunk; ch += J.nvb) {
-    const int64_t r0 = (int64_t)ch * kPanel + 16 * w;
+  const int nch = (int)((n + kTallRows - 1) / kTallRows);
+  for (int ch = vb; ch < nch; ch += J.nvb) {
+    const int64_t r0 = (int64_t)ch * kTallRows + 16 * w;
     v4d D[4];
     zero4(D);
     panel_mm<LP>(X, r0, n, S1, D);
@@ -844,24 +853,24 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
 // width return at once)
 hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st) {
   if (b.lpmask & 1)
-    hipLaunchKernelGGL(bs_tall<16>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
+    hipLaunchKernelGGL(bs_tall<16>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
                        grams, init);
   if (b.lpmask & 2)
-    hipLaunchKernelGGL(bs_tall<32>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
+    hipLaunchKernelGGL(bs_tall<32>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
                        grams, init);
   if (b.lpmask & 4)
-    hipLaunchKernelGGL(bs_tall<64>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
+    hipLaunchKernelGGL(bs_tall<64>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
                        grams, init);
   return hipGetLastError();
 }
 
 hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st) {
   if (b.lpmask & 1)
-    hipLaunchKernelGGL(bs_gamma<16>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+    hipLaunchKernelGGL(bs_gamma<16>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
   if (b.lpmask & 2)
-    hipLaunchKernelGGL(bs_gamma<32>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+    hipLaunchKernelGGL(bs_gamma<32>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
   if (b.lpmask & 4)
-    hipLaunchKernelGGL(bs_gamma<64>, dim3(b.totalr), dim3(kThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+    hipLaunchKernelGGL(bs_gamma<64>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
   return hipGetLastError();
 }
 
