@@ -217,6 +217,7 @@ def main():
         "lanczos_steps": int(info.iterations_total),
         "solver": {1: "block", 2: "single"}.get(int(info.solver), str(info.solver)),
         "deflated": int(info.deflated),
+        "one_pass_steps": int(info.one_pass_steps),
         "basis_stored": bool(info.basis_stored),
         "converged": bool(info.converged),
         "status": status,

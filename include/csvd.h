@@ -83,6 +83,10 @@ typedef struct {
                           /* it fits (leaving 8 GB free), so the moments need no second   */
                           /* pass; 0 always regenerates it in a second pass.  Both give   */
                           /* the same bits.  Jobs of csvd_server never keep it            */
+  int32_t cholqr_passes;  /* block solver: 0 (default) orthonormalises a new basis block  */
+                          /* with one Cholesky QR pass when the first factor R1 is well   */
+                          /* conditioned (||R1||_F ||R1^-1||_F <= 1.5 Lp, no deflated    */
+                          /* column) and with two otherwise; 2 always uses two passes     */
 } csvd_params;
 
 enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
@@ -90,7 +94,7 @@ enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
 /* Fills *p with the paper's defaults: L=16, M=8, N=32, ell=1, delta=1e-20,
  * alpha=0.1, PLAIN, FP64, solve_rtol=1e-11, max_iters=1000000,
  * spurious_eps=1e-12, seed=2109, norm_a=0, window=0, check_solves=0,
- * solver=CSVD_SOLVER_AUTO, keep_basis=1. */
+ * solver=CSVD_SOLVER_AUTO, keep_basis=1, cholqr_passes=0. */
 int csvd_params_default(csvd_params *p);
 
 /* Creates a context holding a device copy of A in CSR form (and of A^T,
@@ -153,7 +157,8 @@ typedef struct {
   double  rest_ms;           /* average duration of the rest of a block step (sampled) */
   int32_t basis_stored;      /* 1: the block basis was kept in device memory (no second */
                              /* pass); 0: regenerated, or the per-column solver          */
-  int32_t reserved0;
+  int32_t one_pass_steps;    /* block steps of the last round whose basis block took one */
+                             /* Cholesky QR pass (see csvd_params.cholqr_passes)         */
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);

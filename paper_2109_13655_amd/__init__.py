@@ -44,7 +44,7 @@ class csvd_params(C.Structure):
         ("solve_rtol", C.c_double), ("max_iters", C.c_int32),
         ("spurious_eps", C.c_double), ("seed", C.c_uint64), ("norm_a", C.c_double),
         ("window", C.c_int32), ("check_solves", C.c_int32), ("solver", C.c_int32),
-        ("keep_basis", C.c_int32),
+        ("keep_basis", C.c_int32), ("cholqr_passes", C.c_int32),
     ]
 
 
@@ -60,7 +60,7 @@ class csvd_info(C.Structure):
         ("spmm_samples", C.c_int64),
         ("spmm_a_bytes", C.c_double), ("spmm_at_bytes", C.c_double), ("window_bytes", C.c_double),
         ("window", C.c_int32), ("L_padded", C.c_int32), ("solver", C.c_int32), ("deflated", C.c_int32),
-        ("rest_ms", C.c_double), ("basis_stored", C.c_int32), ("reserved0", C.c_int32),
+        ("rest_ms", C.c_double), ("basis_stored", C.c_int32), ("one_pass_steps", C.c_int32),
     ]
 
     def as_dict(self):

@@ -259,10 +259,10 @@ hipError_t BEngine::start(BlockJob *j) {
   BBatch b = j->solo;
   b.clock = d_clock_.as<int64_t>();
   if ((e = launch_bs_tall(b, 1, 1, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_reduce(b, 0, 2, 1, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
   if ((e = launch_bs_small1(b, 1, st_)) != hipSuccess) return e;
   if ((e = launch_bs_tall(b, 2, 1, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_reduce(b, 1, 1, 3, st_)) != hipSuccess) return e;
+  if ((e = launch_bs_reduce(b, 1, 1, 3, 0, st_)) != hipSuccess) return e;
   if ((e = launch_bs_small2(b, 1, st_)) != hipSuccess) return e;
   if ((e = launch_bs_gamma(b, 1, st_)) != hipSuccess) return e;
   if ((e = launch_shift(b, 1)) != hipSuccess) return e;
@@ -372,12 +372,12 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if (timer && sample) timer->end(st_);
     if (timer && sample) timer->begin(2, st_);
     if ((e = launch_bs_tall(b, 0, 1, 0, st_)) != hipSuccess) return e;   // W', P
-    if ((e = launch_bs_reduce(b, 0, 1, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_reduce(b, 0, 1, 0, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_tall(b, 1, 1, 0, st_)) != hipSuccess) return e;   // C, G2
-    if ((e = launch_bs_reduce(b, 0, 2, 1, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_small1(b, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_tall(b, 2, 1, 0, st_)) != hipSuccess) return e;   // G3
-    if ((e = launch_bs_reduce(b, 1, 1, 3, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_reduce(b, 1, 1, 3, 1, st_)) != hipSuccess) return e;
     if ((e = launch_bs_small2(b, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_gamma(b, 0, st_)) != hipSuccess) return e;
     if ((e = launch_shift(b, 0)) != hipSuccess) return e;

@@ -205,6 +205,8 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
   if (p->solver == CSVD_SOLVER_BLOCK && (pad_L(p->L) > kBlockMaxLp || p->precision != CSVD_FP64))
     return set_err(ctx, CSVD_EINVAL, "the block solver needs L <= 64 and CSVD_FP64");
   if (p->keep_basis != 0 && p->keep_basis != 1) return set_err(ctx, CSVD_EINVAL, "keep_basis must be 0 or 1");
+  if (p->cholqr_passes != 0 && p->cholqr_passes != 2)
+    return set_err(ctx, CSVD_EINVAL, "cholqr_passes must be 0 or 2");
   return CSVD_OK;
 }
 
@@ -368,6 +370,7 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
                                M + 1, ctx->st));
     R.bjob->h.Kmom = Kmom;
     R.bjob->want_store = (p->keep_basis != 0);
+    R.bjob->h.onepass_rho = (p->cholqr_passes == 2) ? 0.0 : kOnePassRho;
     R.bjob->cache = &ctx->basis_cache;
     // the deflation test of the basis is relative to ||A^T A||
     double na = p->norm_a;
@@ -764,6 +767,9 @@ int run_finalize(SolveRun &R) {
     int fl = 0;
     HIPCHK(ctx, hipMemcpy(&fl, R.bjob->h.flags, sizeof(int), hipMemcpyDeviceToHost));
     info.deflated = fl;
+    int ops = 0;
+    HIPCHK(ctx, hipMemcpy(&ops, R.bjob->h.flags + 2, sizeof(int), hipMemcpyDeviceToHost));
+    info.one_pass_steps = ops;
     info.basis_stored = R.bjob->stored_last ? 1 : 0;
   } else {
     info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
@@ -856,6 +862,7 @@ int csvd_params_default(csvd_params *p) {
   p->check_solves = 0;
   p->solver = CSVD_SOLVER_AUTO;
   p->keep_basis = 1;
+  p->cholqr_passes = 0;
   return CSVD_OK;
 }
 

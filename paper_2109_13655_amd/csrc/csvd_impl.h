@@ -111,6 +111,7 @@ struct BJobDesc {
   int cstride;                     // row stride of cmom (M + 1)
   double tol;
   double dscale;                   // ||A||^2 estimate: scale of the deflation test
+  double onepass_rho;              // one Cholesky QR pass when rho <= this (0: always two)
   double *U;                       // m x Lp
   double *Q;                       // the ring: nring x (n x Lp)
   double *W;                       // n x Lp work block
@@ -154,6 +155,7 @@ constexpr int kBlockMaxVB = 256;  // workgroups per job in the tall kernels
 constexpr int kBlockPollSteps = 4;  // block steps between convergence polls
 constexpr int kMomWindow = 16;   // second-pass steps per moment accumulation (basis ring = window + 2)
 constexpr double kDeflTol = 1e-10;  // relative size below which a new basis direction is deflated
+constexpr double kOnePassRho = 1.5;  // one Cholesky pass when ||R1||_F ||R1^-1||_F <= 1.5 Lp
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);
 hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st);
@@ -168,7 +170,7 @@ hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st);
 hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st);
 hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st);
 // reduction of nm partial Gram matrices from slot m0 into red slots d0.. (fixed order)
-hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, hipStream_t st);
+hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, int second, hipStream_t st);
 // small1: A_k, first Cholesky, R1^-1, T.  small2: second Cholesky, M_k, N_k,
 // B_{k+1} (init = 1: M_init and B_0)
 hipError_t launch_bs_small1(const BBatch &b, int init, hipStream_t st);

@@ -11,6 +11,13 @@
 //   small2: R2 = chol(G3);  M = R1^-1 R2^-1;  N = T R2^-1;  B_{k+1} = R2 R1
 //   gamma:  Q_{k+1} = Y R2^-1 = W' M - Q_k N
 //
+// When the first Cholesky factor is well conditioned (rho = ||R1||_F
+// ||R1^-1||_F / Lp <= onepass_rho, no deflated column; rho >= 1, and rho
+// close to 1 bounds cond(R1) close to 1), Y = W' R1^-1 - Q_k T is already
+// orthonormal to working accuracy: small1 then takes M = R1^-1, N = T,
+// B_{k+1} = R1 and marks the step (flags[1]), and gamma0, its reduction and
+// small2 return at once.
+//
 // A new direction whose Cholesky pivot falls below kDeflTol^2 times its own
 // squared norm before the projection is rounding noise (the space is
 // exhausted) and is deflated: zero row in R, zero column of Q_{k+1}.  The
@@ -235,6 +242,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_tall(const BJobDesc *__restri
   if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
+  if (mode == kTallGamma0 && !init && gp(J.flags)[1]) return;  // one-pass step
   const int vb = g - toff[j];
   const int t = threadIdx.x, w = t >> 6;
   const int64_t n = J.n, nL = n * LP;
@@ -317,11 +325,13 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
 // m) L2 + e], m < nm, in a fixed order: 8 interleaved partial sums combined
 // in order.  Grid (njob, 2 * 64 * 64 / 32); block = 32 outputs x 8 groups.
 __global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict__ jobs,
-                                                      const int64_t *__restrict__ clock, int m0, int nm, int d0) {
+                                                      const int64_t *__restrict__ clock, int m0, int nm, int d0,
+                                                      int second) {
   __shared__ double part[8][32];
   const BJobDesc &J = jobs[blockIdx.x];
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
+  if (second && gp(J.flags)[1]) return;  // one-pass step: no second Gram
   const int L2 = J.Lp * J.Lp;
   if ((int)blockIdx.y * 32 >= nm * L2) return;
   const int t = threadIdx.x, grp = t >> 5;
@@ -563,34 +573,46 @@ __device__ __forceinline__ v4d tile_load(const double *C, int sc) {
 }
 
 // one wave: Cholesky of the 16 x 16 diagonal tile at (16 K, 16 K) in place
-// (upper factor, rows scaled), thresholds thr[16 K + c].  Lane l keeps the
-// entries e = l + 64 u (u < 4; row e / 16, column e % 16) in registers; each
-// step broadcasts the active row through rowb (16 doubles).
-__device__ void diag_chol16(double *A, int SS, int K, const double *thr, int *dead, double *rowb) {
-  const int l = threadIdx.x & 63;
+// (upper factor R, rows scaled), thresholds thr[16 K + c], and the inverse
+// of R in the same sweep: the elimination steps applied to the identity
+// give R^-T (row c of it final once scaled by the pivot's 1/sqrt), written
+// transposed into X's diagonal tile.  Lane l keeps the entries e = l + 64 u
+// (u < 4; row e / 16, column e % 16) of both in registers; each step
+// broadcasts the active rows through rowb (2 x 16 doubles).  A deflated
+// pivot gives a zero row of R and a zero row and column of its inverse.
+__device__ void diag_cholinv16(double *A, int SS, int K, const double *thr, int *dead, double *X, double *rowb) {
+  const int l = threadIdx.x & 63, j = l & 15;
   double *D = A + 16 * K * SS + 16 * K;
-  double a[4];
+  double *Xd = X + 16 * K * SS + 16 * K;
+  double a[4], y[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = l + 64 * u;
-    a[u] = D[(e >> 4) * SS + (e & 15)];
+    a[u] = D[(e >> 4) * SS + j];
+    y[u] = ((e >> 4) == j) ? 1.0 : 0.0;
   }
 #pragma unroll 1
   for (int c = 0; c < 16; ++c) {
     // owners of row c publish it (entries 16 c .. 16 c + 15: slot c >> 2)
     const int uc = c >> 2;
-    if ((l >> 4) == (c & 3)) rowb[l & 15] = uc == 0 ? a[0] : (uc == 1 ? a[1] : (uc == 2 ? a[2] : a[3]));
+    if ((l >> 4) == (c & 3)) {
+      rowb[j] = uc == 0 ? a[0] : (uc == 1 ? a[1] : (uc == 2 ? a[2] : a[3]));
+      rowb[16 + j] = uc == 0 ? y[0] : (uc == 1 ? y[1] : (uc == 2 ? y[2] : y[3]));
+    }
     wave_lds_sync();
     const double d = rowb[c];
     const int dd = !(d > thr[16 * K + c]);
     const double piv = dd ? 0.0 : sqrt(d);
     const double ip = dd ? 0.0 : 1.0 / piv;
+    const double rj = rowb[j] * ip, ycj = rowb[16 + j] * ip;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int e = l + 64 * u, i = e >> 4, j = e & 15;
-      const double rj = rowb[j] * ip;
-      const double upd = a[u] - (rowb[i] * ip) * rj;
+      const int i = (l >> 4) + 4 * u;
+      const double rci = rowb[i] * ip;
+      const double upd = a[u] - rci * rj;
       a[u] = (i == c) ? ((j < c) ? 0.0 : (j == c ? piv : rj)) : ((i > c && j > c) ? upd : a[u]);
+      const double yu = y[u] - rci * ycj;
+      y[u] = (i == c) ? ycj : ((i > c) ? yu : y[u]);
     }
     if (l == 0) dead[16 * K + c] = dd;
     wave_lds_sync();
@@ -598,55 +620,12 @@ __device__ void diag_chol16(double *A, int SS, int K, const double *thr, int *de
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int e = l + 64 * u;
-    D[(e >> 4) * SS + (e & 15)] = a[u];
+    D[(e >> 4) * SS + j] = a[u];
+    Xd[j * SS + (e >> 4)] = y[u];
   }
   wave_lds_sync();
 }
 
-// one wave: X_KK = R_KK^+ of the factored diagonal tile, right-looking from
-// the bottom row: row i is finished (divided by R(i, i)) and broadcast, then
-// every entry above it subtracts R(i', i) X(i, j).
-__device__ void diag_inv16(const double *A, int SS, int K, const int *dead, double *X, double *rowb) {
-  const int l = threadIdx.x & 63;
-  const double *R = A + 16 * K * SS + 16 * K;
-  double *Xd = X + 16 * K * SS + 16 * K;
-  double x[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = l + 64 * u, i = e >> 4, j = e & 15;
-    x[u] = (i == j && !dead[16 * K + i]) ? 1.0 : 0.0;
-  }
-#pragma unroll 1
-  for (int i = 15; i >= 0; --i) {
-    const int ui = i >> 2;
-    if ((l >> 4) == (i & 3)) {
-      const double rdi = dead[16 * K + i] ? 0.0 : 1.0 / R[i * SS + i];
-      double xv = (ui == 0 ? x[0] : (ui == 1 ? x[1] : (ui == 2 ? x[2] : x[3]))) * rdi;
-      x[0] = ui == 0 ? xv : x[0];
-      x[1] = ui == 1 ? xv : x[1];
-      x[2] = ui == 2 ? xv : x[2];
-      x[3] = ui == 3 ? xv : x[3];
-      rowb[l & 15] = xv;
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = l + 64 * u, ii = e >> 4, j = e & 15;
-      const double v = x[u] - R[ii * SS + i] * rowb[j];
-      x[u] = (ii < i) ? v : x[u];
-    }
-    wave_lds_sync();
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = l + 64 * u;
-    Xd[(e >> 4) * SS + (e & 15)] = x[u];
-  }
-  wave_lds_sync();
-}
-
-// A (symmetric, LDS) -> R (upper tiles; lower tiles untouched), X = R^+
-// (upper tiles, lower tiles zero).  Tmp: 4 x 16 x 17 doubles of scratch.
 template <int LP>
 __device__ void chol_inv_blocked(double *A, double *X, const double *thr, int *dead, double *Tmp) {
   constexpr int NB = LP / 16, SS = LP + 1;
@@ -656,8 +635,7 @@ __device__ void chol_inv_blocked(double *A, double *X, const double *thr, int *d
 #pragma unroll 1
   for (int K = 0; K < NB; ++K) {
     if (w == 0) {
-      diag_chol16(A, SS, K, thr, dead, Tmp);
-      diag_inv16(A, SS, K, dead, X, Tmp);
+      diag_cholinv16(A, SS, K, thr, dead, X, Tmp);
     }
     __syncthreads();
     // block row: R_KJ = X_KK^T A_KJ
@@ -755,11 +733,52 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   regs_to_lds<LP>(D, As);
   __syncthreads();
   chol_inv_blocked<LP>(As, Xs, thr, dead, Tmp);
+  // one-pass test: rho = ||R1||_F ||R1^-1||_F / Lp, sums in a fixed order
+  __shared__ int one_pass;
+  {
+    double sr = 0.0, sx = 0.0;
+    for (int e = t; e < L2; e += kThreads) {
+      const int r = e / LP, c = e - r * LP;
+      const double a = ((r >> 4) < (c >> 4) || ((r >> 4) == (c >> 4) && c >= r)) ? As[r * SS + c] : 0.0;
+      const double x = Xs[r * SS + c];
+      sr = fma(a, a, sr);
+      sx = fma(x, x, sx);
+    }
+    Tmp[t] = sr;
+    Tmp[kThreads + t] = sx;
+    __syncthreads();
+    if (w == 0) {
+      // four partial sums per lane, then a butterfly over the wave (fixed order)
+      double a = (Tmp[l] + Tmp[l + 64]) + (Tmp[l + 128] + Tmp[l + 192]);
+      double x = (Tmp[kThreads + l] + Tmp[kThreads + l + 64]) + (Tmp[kThreads + l + 128] + Tmp[kThreads + l + 192]);
+#pragma unroll
+      for (int o = 32; o >= 1; o >>= 1) {
+        a += __shfl_xor(a, o);
+        x += __shfl_xor(x, o);
+      }
+      const bool anydead = __any(l < LP && dead[l] != 0);
+      if (l == 0) {
+        const int op = (!init && !anydead && sqrt(a * x) <= J.onepass_rho * LP) ? 1 : 0;
+        one_pass = op;
+        gp(J.flags)[1] = op;
+        if (op) gp(J.flags)[0] = 0;
+        gp(J.flags)[2] = init ? 0 : gp(J.flags)[2] + op;  // one-pass steps of this round
+      }
+    }
+    __syncthreads();
+  }
+  const bool op = one_pass != 0;
   GLB double *R1 = gp(J.scr), *R1i = R1 + L2, *T = R1 + 2 * L2;
+  GLB double *Bn = gp(J.Bh) + (int64_t)(k + 1) * L2, *Mk = gp(J.Mh) + (int64_t)k * L2;
   for (int e = t; e < L2; e += kThreads) {
     const int r = e / LP, c = e - r * LP;
-    R1[e] = ((r >> 4) < (c >> 4) || ((r >> 4) == (c >> 4) && c >= r)) ? As[r * SS + c] : 0.0;
+    const double rv = ((r >> 4) < (c >> 4) || ((r >> 4) == (c >> 4) && c >= r)) ? As[r * SS + c] : 0.0;
+    R1[e] = rv;
     R1i[e] = Xs[r * SS + c];
+    if (op) {
+      Bn[e] = rv;
+      Mk[e] = Xs[r * SS + c];
+    }
     Pm[r * SS + c] += Cm[r * SS + c];  // P + C
   }
   __syncthreads();
@@ -769,6 +788,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
     if (!init) mm_lds<LP, false>(Pm, Xs, 1.0, D);
   }
   regs_to_glb<LP>(D, T);
+  if (op) regs_to_glb<LP>(D, gp(J.Nh) + (int64_t)k * L2);
 }
 
 template <int LP>
@@ -783,6 +803,7 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
   if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
+  if (!init && gp(J.flags)[1]) return;  // one-pass step: small1 wrote M, N and B
   const int t = threadIdx.x, w = t >> 6;
   const bool act = w < NT;
   const GLB double *red = gp(J.red);
@@ -874,9 +895,9 @@ hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, hipStream_t st) {
+hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, int second, hipStream_t st) {
   hipLaunchKernelGGL(bs_reduce, dim3(b.njob, 2 * kBlockMaxLp * kBlockMaxLp / 32), dim3(kThreads), 0, st, b.jobs,
-                     b.clock, m0, nm, d0);
+                     b.clock, m0, nm, d0, second);
   return hipGetLastError();
 }
 

@@ -349,6 +349,43 @@ def test_block_random_sparse_vs_dense_truth(L):
         cs.csvd_destroy(ctx)
 
 
+def test_block_one_and_two_cholqr_passes_agree():
+    """A well-conditioned new block takes one Cholesky QR pass (random sparse
+    matrices give cond(B_k) close to 1); forcing two passes everywhere gives
+    the same triplets to the residual accuracy, and both match dense truth."""
+    I = synth.random_sparse(4000, 2048, 7, config=84)
+    A = I.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    a, b = synth.interval_by_count(ev, 1024, 10)
+    s_o, U_o, V_o, sall = truth.dense_truth(I, a, b)
+    V = synth.v_in(I.n, 16, 6)
+    ctx = make_ctx(I)
+    try:
+        out = []
+        for passes in (0, 2):
+            p = cs.csvd_params_default(L=16, M=4, N=32, solve_rtol=1e-12, cholqr_passes=passes)
+            st = cs.csvd_solve_interval(ctx, a, b, p, V)
+            info = cs.csvd_get_info(ctx)
+            say("cholqr_passes", passes, "steps", info.iterations, "one-pass steps", info.one_pass_steps)
+            assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK
+            if passes == 0:
+                assert info.one_pass_steps > info.iterations // 2
+            else:
+                assert info.one_pass_steps == 0
+            sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+            np.testing.assert_allclose(sig, s_o, rtol=1e-9)
+            r_host = truth.triplet_residuals(I, sig, U, Vv, normA=sall[0])
+            assert r_host.max() <= 1e-8
+            assert truth.subspace_gap(Vv, V_o) <= 1e-6
+            out.append(sig)
+        np.testing.assert_allclose(out[0], out[1], rtol=1e-10)
+        with pytest.raises(cs.CsvdError) as e:
+            cs.csvd_solve_interval(ctx, a, b, cs.csvd_params_default(L=16, cholqr_passes=1), V)
+        assert e.value.code == cs.CSVD_EINVAL
+    finally:
+        cs.csvd_destroy(ctx)
+
+
 def test_empty_interval_and_determinism():
     I = _small_problem()
     V = synth.v_in(I.n, 4, 6)
