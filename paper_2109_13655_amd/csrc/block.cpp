@@ -21,10 +21,19 @@ static Tiling block_tiling(int64_t rows, int64_t nnz, int Lp) {
   return t;
 }
 
+// Workgroups of the tall kernels (one per CU, each walking its share of the
+// rows): the per-shift recurrences of the previous step (one workgroup per
+// shift) run beside them on the side stream, and a tall workgroup cannot
+// share a CU with one, so the tall kernels leave those CUs out.
+static int tall_workgroups(int64_t n, int S) {
+  const int64_t cap = std::max<int64_t>(kBlockMaxVB - S, kBlockMaxVB / 4);
+  return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlockPanel - 1) / kBlockPanel, cap));
+}
+
 size_t BlockJob::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int Kcap, int L, int Kmom) {
   (void)nnz;
   const int64_t L2 = (int64_t)Lp * Lp;
-  const int64_t nvb = std::min<int64_t>((n + kBlockPanel - 1) / kBlockPanel, kBlockMaxVB);
+  const int64_t nvb = tall_workgroups(n, S);
   size_t b = 0;
   b += 8 * (size_t)(m * Lp);                       // U
   b += 8 * (size_t)((kMomWindow + 2 + 2) * n * Lp);  // Q ring, W, Vpad
@@ -65,7 +74,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.G1 = t1.G; J.lgG1 = t1.lgG; J.E1 = t1.E; J.rpt1 = t1.rpt; J.tiles1 = t1.tiles;
   J.G2 = t2.G; J.lgG2 = t2.lgG; J.E2 = t2.E; J.rpt2 = t2.rpt; J.tiles2 = t2.tiles;
   J.nchunk = (int)((n + kBlockPanel - 1) / kBlockPanel);
-  J.nvb = std::min(J.nchunk, kBlockMaxVB);
+  J.nvb = tall_workgroups(n, S);
   J.Kcap = Kcap;
   J.Kmom = Kmom;
   J.cstride = cstride;

@@ -320,6 +320,126 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
   }
 }
 
+// ------------------------------------------------- tall passes, wave-local
+// The same passes with the Gram products accumulated per wave from its own
+// 16-row panels: lane (rl, q) holds X(row q + 4 v, 16 t + rl) of tile t in
+// the MFMA output layout, which is also the A and B operand layout of
+// (X^T Y)(16 ti .. , 16 tj ..) = sum_v mfma(X[ti][v], Y[tj][v]), so no LDS
+// staging and no barrier is needed inside the loop; the waves run
+// independently over the panels w, w + waves, ... of their workgroup's
+// share.  At the end the waves' sums are added in a fixed order (wave 0,
+// 1, ...) through LDS and stored as the workgroup's partial sums.
+template <int LP, int MODE, int NTH>
+__global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void bs_tall_rg(
+    const BJobDesc *__restrict__ jobs, int njob, const int *__restrict__ toff, const int64_t *__restrict__ clock,
+    int grams, int init) {
+  constexpr int NT = LP / 16, L2 = LP * LP, NW = NTH / 64;
+  constexpr int NF = (MODE == kTallGamma0) ? 0 : NT * NT;       // tiles of Q_k^T X
+  constexpr int NS = (MODE == kTallAlpha) ? 0 : NT * (NT + 1) / 2;  // upper tiles of X^T X
+  constexpr int NA = (NF + NS) > 0 ? NF + NS : 1;
+  __shared__ double SM[2 * LP * kSS];
+  double *S1 = SM, *S2 = SM + LP * kSS;
+  const int g = blockIdx.x;
+  const int j = bfind2(toff, njob, g);
+  const BJobDesc &J = jobs[j];
+  if (J.Lp != LP) return;
+  const int k = (int)(*clock - J.start_clock);
+  if (k >= J.Kstop) return;
+  if (MODE == kTallGamma0 && !init && gp(J.flags)[1]) return;  // one-pass step
+  const int vb = g - toff[j];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const int64_t n = J.n;
+  GLB double *X = init ? gp(J.Vpad) : gp(J.W);
+  const GLB double *Qc = qblock(J, k);
+  const GLB double *Pv = qblock(J, k > 0 ? k - 1 : k);
+  const bool useQ = !init && (MODE != kTallAlpha || k > 0);
+  if (MODE == kTallAlpha) {
+    if (useQ) stage_mat<LP, NTH>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
+  } else if (MODE == kTallBeta) {
+    if (useQ) stage_mat<LP, NTH>(gp(J.red), false, true, S2);  // -P
+  } else {
+    stage_mat<LP, NTH>(gp(J.scr) + L2, false, false, S1);           // R1^-1
+    if (useQ) stage_mat<LP, NTH>(gp(J.scr) + 2 * L2, false, true, S2);  // -T
+  }
+  __syncthreads();
+  v4d acc[NA];
+#pragma unroll
+  for (int i = 0; i < NA; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+  const int npanel = (int)((n + 15) / 16);
+  for (int pn = vb * NW + w; pn < npanel; pn += J.nvb * NW) {
+    const int64_t r0 = (int64_t)pn * 16;
+    v4d D[4];
+    if (MODE == kTallGamma0) {
+      zero4(D);
+      panel_mm<LP>(X, r0, n, S1, D);
+    } else {
+      load_dl<LP>(X, r0, n, D);
+    }
+    if (useQ) panel_mm<LP>(MODE == kTallAlpha ? Pv : Qc, r0, n, S2, D);
+    if (MODE == kTallAlpha && useQ) store_dl<LP>(X, r0, n, D);
+    if (grams) {
+      if (NF) {
+        v4d Qd[4];
+        zero4(Qd);
+        if (!init) load_dl<LP>(Qc, r0, n, Qd);
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[ti * NT + tj] = mfma4(Qd[ti][v], D[tj][v], acc[ti * NT + tj]);
+      }
+      if (NS) {
+        int u = NF;
+#pragma unroll
+        for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+          for (int tj = ti; tj < NT; ++tj, ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u] = mfma4(D[ti][v], D[tj][v], acc[u]);
+      }
+    }
+  }
+  if (!grams) return;
+  // fixed-order sum of the waves' tiles in LDS (the staged matrices are done)
+  double *Red = SM;  // NA x 256 doubles
+  static_assert(NA * 256 <= 2 * LP * kSS, "reduction buffer");
+  __syncthreads();
+  for (int ww = 0; ww < NW; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int i = 0; i < NA; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          double *r = Red + (i * 4 + v) * 64 + l;
+          *r = (ww == 0) ? acc[i][v] : *r + acc[i][v];
+        }
+    }
+    __syncthreads();
+  }
+  // partial sums of workgroup vb: gpart[(vb * 2 + mat) * L2 + r * Lp + c]
+  GLB double *P = gp(J.gpart) + (int64_t)vb * 2 * L2;
+  for (int e = t; e < NA * 256; e += NTH) {
+    const int i = e >> 8, v = (e >> 6) & 3, ll = e & 63, rr = ll & 15, qq = ll >> 4;
+    int mat, ti, tj;
+    if (i < NF) {
+      mat = 0;
+      ti = i / NT;
+      tj = i - ti * NT;
+    } else {
+      mat = 1;
+      int u = i - NF;
+      ti = 0;
+      while (u >= NT - ti) {
+        u -= NT - ti;
+        ++ti;
+      }
+      tj = ti + u;
+    }
+    P[mat * L2 + (16 * ti + qq + 4 * v) * LP + 16 * tj + rr] = Red[e];
+  }
+}
+
 // ----------------------------------------------------------------- reduce
 // red[(d0 + m) L2 + e] = sum over the workgroups vb of gpart[(vb * 2 + m0 +
 // m) L2 + e], m < nm, in a fixed order: 8 interleaved partial sums combined
@@ -873,15 +993,22 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
 // one launch per block width present in the batch (blocks of jobs of another
 // width return at once)
 hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st) {
-  if (b.lpmask & 1)
-    hipLaunchKernelGGL(bs_tall<16>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
-                       grams, init);
-  if (b.lpmask & 2)
-    hipLaunchKernelGGL(bs_tall<32>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
-                       grams, init);
-  if (b.lpmask & 4)
-    hipLaunchKernelGGL(bs_tall<64>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, mode,
-                       grams, init);
+  // alpha and beta: wave-local Gram products (beta at Lp = 64 holds 26 Gram
+  // tiles per wave: one wave per SIMD); gamma0: panels staged through LDS
+#define CSVD_TALL(LPV)                                                                                           \
+  if (mode == kTallAlpha)                                                                                        \
+    hipLaunchKernelGGL((bs_tall_rg<LPV, kTallAlpha, 512>), dim3(b.totalr), dim3(512), 0, st, b.jobs, b.njob,     \
+                       b.toffr, b.clock, grams, init);                                                           \
+  else if (mode == kTallBeta)                                                                                    \
+    hipLaunchKernelGGL((bs_tall_rg<LPV, kTallBeta, (LPV == 64 ? 256 : 512)>), dim3(b.totalr),                    \
+                       dim3(LPV == 64 ? 256 : 512), 0, st, b.jobs, b.njob, b.toffr, b.clock, grams, init);       \
+  else                                                                                                           \
+    hipLaunchKernelGGL(bs_tall<LPV>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, \
+                       mode, grams, init);
+  if (b.lpmask & 1) CSVD_TALL(16)
+  if (b.lpmask & 2) CSVD_TALL(32)
+  if (b.lpmask & 4) CSVD_TALL(64)
+#undef CSVD_TALL
   return hipGetLastError();
 }
 
