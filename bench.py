@@ -23,14 +23,15 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+FP64_MFMA_PEAK_TFS = 78.6  # MI355X dense FP64 matrix peak
 HBM_PEAK_GBS = 8000.0
 
 # DRAM-side bytes per launch of the two sparse products of the block step at
 # c2, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy
 # (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 of csrc/k_bspmm.hip) and for the c2 workload.
-SPMM_TRAFFIC_C2 = {"sha256": "32957dd4954dabcbc33542b6080fc80aa8e2baa685c763a3ac82c8dd60a07047",
-                   "bytes": (245531.6 * 2.0 + 100000.0 + 249261.1 * 2.0 + 50000.0) * 1024.0}
+SPMM_TRAFFIC_C2 = {"sha256": "a11d536573565865a171af39433ca82881a04271bcda9830f6b99ada4ad50863",
+                   "bytes": (244868.0 * 2.0 + 100000.9 + 250765.6 * 2.0 + 50011.1) * 1024.0}
 
 
 def log(*a):
@@ -115,6 +116,22 @@ def roofline(info, config):
     return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": traffic,
             "bytes_per_launch": b, "avg_launch_ms": t, "samples": int(info.spmm_samples)}
+
+
+def roofline_moments(info, W):
+    """The moment accumulation of the block solver, S += [Q_k0 .. Q_k0+15]
+    [F_k0; ..; F_k0+15] on FP64 MFMA: 2 n Lp (M + 1) L flops per basis block,
+    16 blocks per launch, timed with HIP events around every full launch."""
+    if info.solver != 1 or not info.moments_ms > 0:
+        return None
+    I = W["I"]
+    Lp = int(info.L_padded)
+    kmom = (W["M"] + 1) if W["ell"] == 1 else 1
+    flops = 2.0 * I.n * Lp * kmom * W["L"] * 16
+    ach = flops / (info.moments_ms * 1e-3) / 1e12
+    return {"bound": "mfma", "kernel": "b_moments (S += Q F over 16 basis blocks)", "achieved": ach,
+            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFS, "traffic": None,
+            "flops_per_launch": flops, "avg_launch_ms": info.moments_ms}
 
 
 def main():
@@ -224,6 +241,7 @@ def main():
         "phase_ms": {"solve": info.t_solve_ms, "lowrank": info.t_lowrank_ms, "qr": info.t_qr_ms,
                      "extract": info.t_extract_ms},
         "roofline": roofline(info, args.config),
+        "roofline_moments": roofline_moments(info, W),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle COCG sample)")

@@ -159,6 +159,8 @@ typedef struct {
                              /* pass); 0: regenerated, or the per-column solver          */
   int32_t one_pass_steps;    /* block steps of the last round whose basis block took one */
                              /* Cholesky QR pass (see csvd_params.cholqr_passes)         */
+  double  moments_ms;        /* block solver: average duration of one moment launch     */
+                             /* over 16 basis blocks (sampled)                          */
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);

@@ -61,6 +61,7 @@ class csvd_info(C.Structure):
         ("spmm_a_bytes", C.c_double), ("spmm_at_bytes", C.c_double), ("window_bytes", C.c_double),
         ("window", C.c_int32), ("L_padded", C.c_int32), ("solver", C.c_int32), ("deflated", C.c_int32),
         ("rest_ms", C.c_double), ("basis_stored", C.c_int32), ("one_pass_steps", C.c_int32),
+        ("moments_ms", C.c_double),
     ]
 
     def as_dict(self):

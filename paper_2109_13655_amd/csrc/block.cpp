@@ -289,8 +289,13 @@ hipError_t BEngine::finish_stored(BlockJob *j) {
   if (e != hipSuccess) return e;
   if ((e = launch_b_fcoef(J, j->K, st_)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(J.Sout, 0, 8 * (size_t)J.npad * J.Kmom * J.L, st_)) != hipSuccess) return e;
-  for (int k0 = 0; k0 < j->K; k0 += kMomWindow)
-    if ((e = launch_b_moments(J, k0, std::min(kMomWindow, j->K - k0), st_)) != hipSuccess) return e;
+  for (int k0 = 0; k0 < j->K; k0 += kMomWindow) {
+    const int T = std::min(kMomWindow, j->K - k0);
+    const bool timed = timer_ && T == kMomWindow;
+    if (timed && (e = timer_->begin(3, st_)) != hipSuccess) return e;
+    if ((e = launch_b_moments(J, k0, T, st_)) != hipSuccess) return e;
+    if (timed && (e = timer_->end(st_)) != hipSuccess) return e;
+  }
   if ((e = hipStreamSynchronize(st_)) != hipSuccess) return e;
   j->free_store(true);
   j->store = false;
@@ -366,6 +371,7 @@ hipError_t BEngine::rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &d
 }
 
 hipError_t BEngine::step(KernelTimer *timer, bool sample) {
+  timer_ = timer;
   hipError_t e;
   if (!p1_.empty()) {
     if (dirty1_) {

@@ -77,6 +77,7 @@ class BEngine {
   hipError_t enter_pass2(BlockJob *j);
   hipError_t finish_stored(BlockJob *j);
   hipError_t launch_shift(const BBatch &b, int init);
+  KernelTimer *timer_ = nullptr;  // the timer of the last step() call (moment launches are sampled)
   hipStream_t st_;
   hipStream_t side_ = nullptr;
   hipEvent_t ev_ = nullptr;

@@ -991,10 +991,11 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
     rc = check_solves(*R);
     if (rc) return rc;
   }
-  double avg[3];
-  int64_t cnt[3];
+  double avg[KernelTimer::kKinds];
+  int64_t cnt[KernelTimer::kKinds];
   HIPCHK(ctx, hipStreamSynchronize(ctx->st));
   timer.summarize(avg, cnt);
+  ctx->info.moments_ms = avg[3];
   ctx->info.spmm_a_ms = avg[0];
   ctx->info.spmm_at_ms = avg[1];
   if (R->block) ctx->info.rest_ms = avg[2];

@@ -133,8 +133,8 @@ hipError_t KernelTimer::begin(int k, hipStream_t st) {
 
 hipError_t KernelTimer::end(hipStream_t st) { return hipEventRecord(ev[used++], st); }
 
-void KernelTimer::summarize(double out[3], int64_t cnt[3]) {
-  for (int i = 0; i < 3; ++i) {
+void KernelTimer::summarize(double out[kKinds], int64_t cnt[kKinds]) {
+  for (int i = 0; i < kKinds; ++i) {
     out[i] = 0;
     cnt[i] = 0;
   }
@@ -145,7 +145,7 @@ void KernelTimer::summarize(double out[3], int64_t cnt[3]) {
       cnt[kind[i / 2]] += 1;
     }
   }
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < kKinds; ++i)
     if (cnt[i]) out[i] /= (double)cnt[i];
 }
 

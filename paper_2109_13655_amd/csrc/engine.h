@@ -114,14 +114,16 @@ struct Job {
 // Sampled HIP-event timings of the hot kernels.
 struct KernelTimer {
   std::vector<hipEvent_t> ev;  // pairs
-  std::vector<int> kind;       // 0 = A product, 1 = A^T product, 2 = window apply
+  std::vector<int> kind;       // 0 = A product, 1 = A^T product, 2 = window apply / rest of a
+                               // block step, 3 = moment window (block solver)
   size_t used = 0;
   ~KernelTimer();
   void reset() { used = 0; kind.clear(); }
   hipError_t begin(int k, hipStream_t st);
   hipError_t end(hipStream_t st);
+  static constexpr int kKinds = 4;
   // averages in ms per kind; count of samples
-  void summarize(double out[3], int64_t cnt[3]);
+  void summarize(double out[kKinds], int64_t cnt[kKinds]);
 };
 
 class Engine {

@@ -458,6 +458,8 @@ __global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict
   const int o = blockIdx.y * 32 + (t & 31);
   const GLB double *__restrict__ P = gp(J.gpart) + (int64_t)m0 * L2;
   double s = 0.0;
+  // loads of eight partials in flight, added in order
+#pragma unroll 8
   for (int vb = grp; vb < J.nvb; vb += 8) s += P[(int64_t)vb * 2 * L2 + o];
   part[grp][t & 31] = s;
   __syncthreads();
