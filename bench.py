@@ -134,6 +134,162 @@ def roofline_moments(info, W):
             "flops_per_launch": flops, "avg_launch_ms": info.moments_ms}
 
 
+def sample_interval(I, t, config):
+    """Interval holding about t singular values around the median, read off
+    a same-distribution instance of about 1000 columns."""
+    import synth
+    k = max(1, int(round(I.nnz / I.n)))
+    a, b, _, _ = synth.interval_from_sample(I.m, I.n, k, t, scale=max(1, I.n // 1000), config=config)
+    return a, b
+
+
+def bench_c3(args, cs, torch):
+    """Batched case: a pool of independent random sparse problems (m in
+    [5000, 50000], n = m/2, 8-16 nonzeros per column, N = 16, L = 32, M = 4,
+    intervals of 16-32 values around the median), solved one by one and as
+    one batch (one launch per stage for all problems)."""
+    import numpy as np
+    import synth
+    pool = synth.batch_pool(count=args.pool)
+    probs = []
+    for i, (I, t) in enumerate(pool):
+        a, b = sample_interval(I, t, 3)
+        probs.append((I, a, b, synth.v_in(I.n, 32, 3, i)))
+    log("c3 pool", len(probs), "problems, n from", min(P[0].n for P in probs), "to", max(P[0].n for P in probs))
+    p = cs.csvd_params_default(L=32, M=4, N=16, ell=args.ell)
+    ctxs = [cs.csvd_create(I.m, I.n, I.rowptr, I.colidx, I.vals) for I, _, _, _ in probs]
+
+    def resid_of(c, I):
+        _, _, _, r = cs.csvd_get_triplets(c, I.m, I.n, want_vectors=False)
+        return float(r.max()) if r.size else 0.0
+
+    def ok_count(st, res):
+        return sum(1 for x, r in zip(st, res) if x == 0 and r <= 1e-8)
+
+    # warm-up on the first problem, then sequential solves
+    cs.csvd_solve_interval(ctxs[0], probs[0][1], probs[0][2], p, probs[0][3])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_seq = []
+    for i, (c, (I, a, b, V)) in enumerate(zip(ctxs, probs)):
+        st_seq.append(cs.csvd_solve_interval(c, a, b, p, V))
+        if i % 16 == 15:
+            log(f"sequential: {i + 1} solved")
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    res_seq = [resid_of(c, P[0]) for c, P in zip(ctxs, probs)]
+    r_seq = max(res_seq)
+    stored_seq = sum(int(cs.csvd_get_info(c).basis_stored) for c in ctxs)
+    log(f"sequential: {t_seq:.3f}s, max resid {r_seq:.2e}")
+    t0 = time.perf_counter()
+    st_bat = cs.csvd_solve_batch(ctxs, [P[1] for P in probs], [P[2] for P in probs], [p] * len(probs),
+                                 [P[3] for P in probs])
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    res_bat = [resid_of(c, P[0]) for c, P in zip(ctxs, probs)]
+    r_bat = max(res_bat)
+    stored_bat = sum(int(cs.csvd_get_info(c).basis_stored) for c in ctxs)
+    log(f"batched: {t_bat:.3f}s, max resid {r_bat:.2e}")
+    t_hat = [int(cs.csvd_get_info(c).t_hat) for c in ctxs]
+    for c in ctxs:
+        cs.csvd_destroy(c)
+    n = len(probs)
+    ok_bat, ok_seq = ok_count(st_bat, res_bat), ok_count(st_seq, res_seq)
+    out = {
+        "metric": "batched interval-SVD solves/sec (c3 pool, one batch) at rel. residual <=1e-8",
+        "value": ok_bat / t_bat, "unit": "solves/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_bat * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"c3_pool_{n}_random_sparse_m5000-50000_n=m/2_8-16nnz_per_col", "N": 16, "L": 32,
+                   "M": 4, "ell": args.ell, "problems": n},
+        "sequential_value": ok_seq / t_seq, "batch_over_sequential": t_seq / t_bat,
+        "meeting_target": {"batch": ok_bat, "sequential": ok_seq, "of": n},
+        "all_solves_per_s": {"batch": n / t_bat, "sequential": n / t_seq},
+        "max_rel_residual": max(r_seq, r_bat), "status_batch": st_bat, "status_sequential": st_seq,
+        "t_hat_range": [min(t_hat), max(t_hat)], "basis_stored": {"sequential": stored_seq, "batch": stored_bat},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_c4(args, cs, torch):
+    """Served case: requests arrive at Poisson times (rate --rate per second)
+    on a pool of random sparse matrices (n log-uniform in [1e4, 3e5], m = 1.5 n,
+    12 nonzeros per column); each asks for t ~ U{8..64} values near the median
+    with N = 16, M = 4, L = 3t/4 rounded up to a multiple of 8.  The server
+    runs them with continuous batching under an HBM budget of 80% of the free
+    memory.  Reports throughput and p50 / p99 latency (done - arrival)."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(np.random.SeedSequence([2109, 13655, 4, 1]))
+    pool = synth.serving_pool(count=args.pool)
+    reqs = []
+    tarr = 0.0
+    for r in range(args.requests):
+        I = pool[int(rng.integers(len(pool)))]
+        t = int(rng.integers(8, 65))
+        L = int(math.ceil(0.75 * t / 8.0) * 8)
+        a, b = sample_interval(I, t, 4)
+        tarr += float(rng.exponential(1.0 / args.rate))
+        reqs.append(dict(I=I, t=t, L=L, a=a, b=b, arrival=tarr))
+    log("c4:", len(reqs), "requests at", args.rate, "req/s over", len(pool), "matrices")
+    ctxs = [cs.csvd_create(q["I"].m, q["I"].n, q["I"].rowptr, q["I"].colidx, q["I"].vals) for q in reqs]
+    free, _ = torch.cuda.mem_get_info()
+    srv = cs.csvd_server_create(int(0.8 * free), 64)
+    ids = [None] * len(reqs)
+    done_at = [None] * len(reqs)
+    status = [None] * len(reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nxt = 0
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt]["arrival"] <= now:
+            q = reqs[nxt]
+            p = cs.csvd_params_default(L=q["L"], M=4, N=16, ell=args.ell)
+            ids[nxt] = cs.csvd_server_submit(srv, ctxs[nxt], q["a"], q["b"], p)
+            nxt += 1
+        active = cs.csvd_server_step(srv, 32)
+        now = time.perf_counter() - t0
+        for i in range(nxt):
+            if done_at[i] is None:
+                d, st = cs.csvd_server_poll(srv, ids[i])
+                if d:
+                    done_at[i] = now
+                    status[i] = st
+                    log(f"request {i} (n {reqs[i]['I'].n}, L {reqs[i]['L']}) done at {now:.2f}s, "
+                        f"latency {now - reqs[i]['arrival']:.2f}s, status {st}")
+        if nxt == len(reqs) and all(x is not None for x in done_at):
+            break
+        if active == 0 and nxt < len(reqs):
+            time.sleep(max(0.0, min(0.01, reqs[nxt]["arrival"] - now)))
+    t_end = time.perf_counter() - t0
+    res = []
+    for i, q in enumerate(reqs):
+        _, _, _, r = cs.csvd_get_triplets(ctxs[i], q["I"].m, q["I"].n, want_vectors=False)
+        res.append(float(r.max()) if r.size else 0.0)
+    cs.csvd_server_destroy(srv)
+    for c in ctxs:
+        cs.csvd_destroy(c)
+    lat = sorted((d - q["arrival"]) * 1e3 for d, q in zip(done_at, reqs))
+
+    def pct(x):
+        return lat[min(len(lat) - 1, int(math.ceil(x * len(lat))) - 1)]
+
+    ok = sum(1 for x, r in zip(status, res) if x == 0 and r <= 1e-8)
+    out = {
+        "metric": "served interval-SVD requests/sec (c4, Poisson arrivals) at rel. residual <=1e-8; p50/p99 latency",
+        "value": ok / t_end, "unit": "requests/s", "n_gpus": 1, "steps": len(reqs), "warmup": 0,
+        "ms_per_step": t_end / len(reqs) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"c4_pool_{len(pool)}_random_sparse_n1e4-3e5_m=1.5n_12nnz_per_col",
+                   "arrival_rate": args.rate, "requests": len(reqs), "N": 16, "M": 4, "ell": args.ell},
+        "p50_ms": pct(0.5), "p99_ms": pct(0.99), "max_rel_residual": max(res),
+        "meeting_target": ok, "all_requests_per_s": len(reqs) / t_end,
+        "status": status, "makespan_s": t_end,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +300,11 @@ def main():
     ap.add_argument("--max-iters", type=int, default=0)
     ap.add_argument("--window", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pool", type=int, default=0, help="c3: problems in the pool (64); c4: matrices (8)")
+    ap.add_argument("--requests", type=int, default=24, help="c4: requests")
+    ap.add_argument("--rate", type=float, default=2.0, help="c4: arrival rate (requests/s)")
+    ap.add_argument("--ell", type=int, default=1,
+                    help="c3 / c4: rounds of the moment iteration (the configs' value is 1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (a kernel of known traffic for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
@@ -168,6 +329,12 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 1 GiB read + 1 GiB written")
         del src, dst
+    if args.config == "c3":
+        args.pool = args.pool or 64
+        return bench_c3(args, cs, torch)
+    if args.config == "c4":
+        args.pool = args.pool or 8
+        return bench_c4(args, cs, torch)
     W = workload(args.config)
     I = W["I"]
     log("workload", W["desc"], "nnz", I.nnz, "interval", W["a"], W["b"])

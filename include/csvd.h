@@ -201,9 +201,10 @@ const char *csvd_last_error(const csvd_ctx *ctx);
 /* Frees everything the context owns.  NULL is accepted. */
 void csvd_destroy(csvd_ctx *ctx);
 
-/* Frees the device memory a context keeps between solves: the chunks of a
- * stored block basis (csvd_params.keep_basis), which the next solve of the
- * same block width would reuse.  Waits for the context's stream first.
+/* Frees the device memory kept between solves on the context's device: the
+ * idle chunks of stored block bases (csvd_params.keep_basis), which the next
+ * solve of the same size would reuse (a solve that needs room frees idle
+ * chunks of other sizes by itself).  Waits for the context's stream first.
  * Returns CSVD_OK, CSVD_EINVAL (NULL) or CSVD_EDEVICE. */
 int csvd_trim(csvd_ctx *ctx);
 

@@ -4,8 +4,37 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 namespace csvd {
+
+// Chunks of stored bases that no solve is using, per device, kept for the
+// next solve: freeing and re-allocating tens of GB per solve stalls the
+// device while the driver clears the memory.  Idle chunks are freed when a
+// new allocation would not leave kStoreReserve free, and by csvd_trim.  The
+// pool lives until the process ends (never destroyed: it may hold device
+// memory past the runtime's own teardown).
+namespace {
+struct ChunkPool {
+  std::mutex mu;
+  std::map<int, std::vector<std::unique_ptr<DevBuf>>> idle;  // device -> idle chunks
+};
+ChunkPool &chunk_pool() {
+  static ChunkPool *p = new ChunkPool();
+  return *p;
+}
+int current_device() {
+  int d = 0;
+  return hipGetDevice(&d) == hipSuccess ? d : 0;
+}
+}  // namespace
+
+void release_idle_chunks() {
+  ChunkPool &p = chunk_pool();
+  std::lock_guard<std::mutex> g(p.mu);
+  p.idle[current_device()].clear();
+}
 
 static int lp_bit(int Lp) { return Lp == 16 ? 1 : (Lp == 32 ? 2 : 4); }
 
@@ -170,15 +199,27 @@ bool BlockJob::grow_store(int kneed, hipStream_t st) {
   while ((int64_t)chunks.size() * kStoreChunk <= kneed) {
     if (chunks.size() + 1 >= qtab.size()) return false;
     std::unique_ptr<DevBuf> c;
-    if (cache && !cache->empty() && cache->back()->bytes == bytes) {
-      c = std::move(cache->back());
-      cache->pop_back();
-    } else {
-      if (cache) cache->clear();  // chunks of another block width
-      size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) != hipSuccess || fr < bytes + kStoreReserve) return false;
-      c.reset(new DevBuf());
-      if (c->alloc(bytes) != hipSuccess) return false;
+    {
+      ChunkPool &p = chunk_pool();
+      std::lock_guard<std::mutex> g(p.mu);
+      auto &idle = p.idle[current_device()];
+      for (size_t i = idle.size(); i-- > 0;)
+        if (idle[i]->bytes == bytes) {
+          c = std::move(idle[i]);
+          idle.erase(idle.begin() + (std::ptrdiff_t)i);
+          break;
+        }
+      if (!c) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+        if (fr < bytes + kStoreReserve && !idle.empty()) {
+          idle.clear();  // idle chunks of other widths make room
+          if (hipMemGetInfo(&fr, &tot) != hipSuccess) return false;
+        }
+        if (fr < bytes + kStoreReserve) return false;
+        c.reset(new DevBuf());
+        if (c->alloc(bytes) != hipSuccess) return false;
+      }
     }
     qtab[chunks.size()] = c->as<double>();
     chunks.push_back(std::move(c));
@@ -194,8 +235,12 @@ bool BlockJob::grow_store(int kneed, hipStream_t st) {
 }
 
 void BlockJob::free_store(bool keep) {
-  if (keep && cache)
-    for (auto &c : chunks) cache->push_back(std::move(c));
+  if (keep && !chunks.empty()) {
+    ChunkPool &p = chunk_pool();
+    std::lock_guard<std::mutex> g(p.mu);
+    auto &idle = p.idle[current_device()];
+    for (auto &c : chunks) idle.push_back(std::move(c));
+  }
   chunks.clear();
 }
 
@@ -265,18 +310,62 @@ hipError_t BEngine::start(BlockJob *j) {
   if (e != hipSuccess) return e;
   e = j->sync_desc(st_);
   if (e != hipSuccess) return e;
+  // one-pass flag, counter and robust-step mark of this round start at zero
+  if ((e = hipMemsetAsync(J.flags + 1, 0, 3 * sizeof(int), st_)) != hipSuccess) return e;
+  if ((e = start_block(j, true)) != hipSuccess) return e;
   BBatch b = j->solo;
   b.clock = d_clock_.as<int64_t>();
-  if ((e = launch_bs_tall(b, 1, 1, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_small1(b, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_tall(b, 2, 1, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_reduce(b, 1, 1, 3, 0, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_small2(b, 1, st_)) != hipSuccess) return e;
-  if ((e = launch_bs_gamma(b, 1, st_)) != hipSuccess) return e;
   if ((e = launch_shift(b, 1)) != hipSuccess) return e;
   p1_.push_back(j);
   dirty1_ = true;
+  return hipSuccess;
+}
+
+// Householder QR of a row-major n x Lp block: stays orthonormal also when
+// the block is numerically rank deficient (a Cholesky QR of such a block
+// loses orthogonality).  Deterministic, so a second pass reproduces it bit
+// for bit.
+hipError_t BEngine::orth_block(BlockJob *j, const double *src, double *dst, double *R, double *norms) {
+  BJobDesc &J = j->h;
+  const int64_t n = J.n;
+  const int Lp = J.Lp;
+  DevBuf X, Z, tau, ws, ws2;
+  hipError_t e;
+  if ((e = X.alloc(sizeof(double) * n * Lp)) != hipSuccess) return e;
+  if ((e = Z.alloc(sizeof(double) * n * Lp)) != hipSuccess) return e;
+  if ((e = tau.alloc(sizeof(double) * Lp)) != hipSuccess) return e;
+  if ((e = ws.alloc(sizeof(double) * hh_blocked_ws_doubles(Lp))) != hipSuccess) return e;
+  if ((e = ws2.alloc(sizeof(double) * hh_blocked_ws_doubles(Lp))) != hipSuccess) return e;
+  double *x = X.as<double>(), *z = Z.as<double>();
+  if ((e = launch_row_to_col((int)n, Lp, src, Lp, x, n, st_)) != hipSuccess) return e;
+  if (norms && (e = launch_col_norms(x, n, (int)n, Lp, norms, st_)) != hipSuccess) return e;
+  if ((e = hh_qr_blocked(x, n, (int)n, Lp, tau.as<double>(), ws.as<double>(), st_)) != hipSuccess) return e;
+  if (R && (e = launch_b_r0(x, n, Lp, R, st_)) != hipSuccess) return e;
+  if ((e = launch_b_eye(z, n, n, Lp, st_)) != hipSuccess) return e;
+  if ((e = hh_apply_blocked(x, n, (int)n, Lp, ws.as<double>(), z, n, Lp, ws2.as<double>(), st_)) != hipSuccess)
+    return e;
+  if ((e = launch_col_to_row((int)n, Lp, z, n, dst, Lp, st_)) != hipSuccess) return e;
+  return hipStreamSynchronize(st_);  // the work buffers are freed on return
+}
+
+// Q_0 (block 0 of the basis) and, on the first pass, B_0 and the column norms
+// of the starting block, by Householder QR.
+hipError_t BEngine::start_block(BlockJob *j, bool first) {
+  BJobDesc &J = j->h;
+  return orth_block(j, J.Vpad, j->block_ptr(0), first ? J.Bh : nullptr, first ? J.beta0 : nullptr);
+}
+
+// After gamma wrote W3 = W' - Q_k (P + C) into block k + 1 of a robust step:
+// Q_{k+1} and (first pass) B_{k+1} = R by Householder QR.
+hipError_t BEngine::robust_finish(std::vector<BlockJob *> &v, bool first_pass) {
+  for (BlockJob *j : v) {
+    const int k = (int)(clock_ - j->h.start_clock);
+    if (k >= j->robust_steps || k >= j->h.Kstop) continue;
+    double *blk = j->block_ptr(k + 1);
+    const size_t L2 = (size_t)j->h.Lp * j->h.Lp;
+    hipError_t e = orth_block(j, blk, blk, first_pass ? j->h.Bh + (size_t)(k + 1) * L2 : nullptr, nullptr);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 
@@ -316,9 +405,7 @@ hipError_t BEngine::enter_pass2(BlockJob *j) {
   j->pass = 2;
   j->mflushed = 0;
   if ((e = j->sync_desc(st_)) != hipSuccess) return e;
-  BBatch b = j->solo;
-  b.clock = d_clock_.as<int64_t>();
-  if ((e = launch_bs_gamma(b, 1, st_)) != hipSuccess) return e;
+  if ((e = start_block(j, false)) != hipSuccess) return e;
   p2_.push_back(j);
   dirty2_ = true;
   return hipSuccess;
@@ -390,11 +477,19 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = launch_bs_reduce(b, 0, 1, 0, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_tall(b, 1, 1, 0, st_)) != hipSuccess) return e;   // C, G2
     if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
+    for (BlockJob *j : p1_) {  // mark the robust steps for small1
+      const int k = (int)(clock_ - j->h.start_clock);
+      if (j->robust_steps > 0 && (k == 0 || k == j->robust_steps) &&
+          (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(j->h.flags + 3), k == 0 ? 1 : 0, 1, st_)) !=
+              hipSuccess)
+        return e;
+    }
     if ((e = launch_bs_small1(b, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_tall(b, 2, 1, 0, st_)) != hipSuccess) return e;   // G3
     if ((e = launch_bs_reduce(b, 1, 1, 3, 1, st_)) != hipSuccess) return e;
     if ((e = launch_bs_small2(b, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_gamma(b, 0, st_)) != hipSuccess) return e;
+    if ((e = robust_finish(p1_, true)) != hipSuccess) return e;
     if ((e = launch_shift(b, 0)) != hipSuccess) return e;
     if (timer && sample) timer->end(st_);
   }
@@ -417,6 +512,7 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
     if ((e = launch_bs_tall(b, 0, 0, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_gamma(b, 0, st_)) != hipSuccess) return e;
+    if ((e = robust_finish(p2_, false)) != hipSuccess) return e;
   }
   if (p1_.empty() && p2_.empty()) return hipSuccess;
   if ((e = launch_b_tick(d_clock_.as<int64_t>(), st_)) != hipSuccess) return e;

@@ -13,6 +13,9 @@ constexpr int kStoreChunk = 64;
 // device memory left free when the stored basis grows (bytes)
 constexpr size_t kStoreReserve = (size_t)8 << 30;
 
+// Frees the idle stored-basis chunks of the current device.
+void release_idle_chunks();
+
 // One block Lanczos problem: device histories, work blocks and the pass
 // state.  Pass 1 builds the block tridiagonal matrix and monitors every
 // (shift, column) residual.  If the whole basis fits in device memory it is
@@ -25,7 +28,6 @@ struct BlockJob {
   BBatch solo{};
   std::vector<double *> qtab;                  // host copy of the basis table
   std::vector<std::unique_ptr<DevBuf>> chunks;  // stored basis, kStoreChunk blocks each
-  std::vector<std::unique_ptr<DevBuf>> *cache = nullptr;  // chunks kept between solves (owner's)
   bool want_store = true;  // try store mode (the server keeps the ring: its budget covers the job only)
   bool store = false;      // store mode active for the current pass 1
   bool stored_last = false;  // the last round's moments came from a stored basis
@@ -36,6 +38,12 @@ struct BlockJob {
   int64_t steps_total = 0; // over all passes and rounds
   int64_t steps_last = 0;  // pass-1 steps of the last round
   int mflushed = 0;        // second-pass steps whose moments are already in Sout
+  int robust_steps = 0;    // steps 0 .. robust_steps - 1 of each pass orthonormalise the new block by
+                           // Householder QR (rounds after the first start from a filtered block
+                           // whose first Krylov block is numerically rank deficient)
+  double *block_ptr(int k) const {  // Q_k in the basis storage (host view of the basis table)
+    return qtab[(k / h.qC) % h.qT] + (size_t)(k % h.qC) * h.n * h.Lp;
+  }
   static size_t bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, int Kcap, int L, int Kmom);
   hipError_t create(const int *rp, const int *ci, const double *va, const int *rpT, const int *ciT,
                     const double *vaT, int64_t m, int64_t n, int64_t nnz, int L, int Lp, int S, int Kcap, int Kmom,
@@ -47,7 +55,7 @@ struct BlockJob {
   // 0 .. kneed (false: memory did not allow it)
   hipError_t set_ring(hipStream_t st);
   bool grow_store(int kneed, hipStream_t st);
-  // keep: the chunks go to the cache for the next solve; else they are freed
+  // keep: the chunks go to the device's pool of idle chunks; else they are freed
   void free_store(bool keep);
 };
 
@@ -76,6 +84,12 @@ class BEngine {
   hipError_t rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &dt, BBatch &b);
   hipError_t enter_pass2(BlockJob *j);
   hipError_t finish_stored(BlockJob *j);
+  hipError_t start_block(BlockJob *j, bool first);
+  // Householder QR of the row-major n x Lp block src: Q into dst (may be src),
+  // optionally R (row-major Lp x Lp, zero below) and the column norms of src
+  hipError_t orth_block(BlockJob *j, const double *src, double *dst, double *R, double *norms);
+  // robust steps of the jobs in v after their gamma (Q_{k+1} from W3)
+  hipError_t robust_finish(std::vector<BlockJob *> &v, bool first_pass);
   hipError_t launch_shift(const BBatch &b, int init);
   KernelTimer *timer_ = nullptr;  // the timer of the last step() call (moment launches are sampled)
   hipStream_t st_;

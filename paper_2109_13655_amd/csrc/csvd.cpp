@@ -371,7 +371,6 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
     R.bjob->h.Kmom = Kmom;
     R.bjob->want_store = (p->keep_basis != 0);
     R.bjob->h.onepass_rho = (p->cholqr_passes == 2) ? 0.0 : kOnePassRho;
-    R.bjob->cache = &ctx->basis_cache;
     // the deflation test of the basis is relative to ||A^T A||
     double na = p->norm_a;
     if (!(na > 0)) {
@@ -468,6 +467,7 @@ static int run_after_round_block(SolveRun &R, bool *more) {
     HIPCHK(ctx, hipMemcpyAsync(R.d_rhs.p, Vc.data(), 8 * Vc.size(), hipMemcpyHostToDevice, ctx->st));
     HIPCHK(ctx, hipStreamSynchronize(ctx->st));
     R.round += 1;
+    B.robust_steps = kRobustSteps;  // the filtered block: first Krylov blocks by Householder QR
     if (R.round + 1 == p.ell) {
       B.h.Kmom = p.M + 1;
       B.h.Sout = ctx->d_S.as<double>();
@@ -926,7 +926,7 @@ int csvd_trim(csvd_ctx *ctx) {
   if (!ctx) return CSVD_EINVAL;
   ctx->err.clear();
   if (hipStreamSynchronize(ctx->st) != hipSuccess) return set_err(ctx, CSVD_EDEVICE, "stream synchronize failed");
-  ctx->basis_cache.clear();
+  csvd::release_idle_chunks();
   return CSVD_OK;
 }
 

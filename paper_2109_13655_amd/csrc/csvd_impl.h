@@ -155,6 +155,7 @@ constexpr int kBlockMaxVB = 256;  // workgroups per job in the tall kernels
 constexpr int kBlockPollSteps = 4;  // block steps between convergence polls
 constexpr int kMomWindow = 16;   // second-pass steps per moment accumulation (basis ring = window + 2)
 constexpr double kDeflTol = 1e-10;  // relative size below which a new basis direction is deflated
+constexpr int kRobustSteps = 2;      // Householder-orthonormalised steps at the start of rounds after the first
 constexpr double kOnePassRho = 1.5;  // one Cholesky pass when ||R1||_F ||R1^-1||_F <= 1.5 Lp
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);
@@ -179,6 +180,8 @@ hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st);
 hipError_t launch_b_backsolve(const BJobDesc &hj, int K, hipStream_t st);
 hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st);
 hipError_t launch_b_tick(int64_t *clock, hipStream_t st);
+hipError_t launch_b_r0(const double *X, int64_t ld, int Lp, double *B, hipStream_t st);
+hipError_t launch_b_eye(double *Z, int64_t ld, int64_t rows, int cols, hipStream_t st);
 
 struct Ctx;  // defined in csvd.cpp
 

@@ -178,10 +178,6 @@ struct csvd_ctx {
   std::unique_ptr<csvd::Job> job;    // last round's job (solutions), single-vector solver
   double norm_est = 0.0;             // cached ||A||_2 estimate
   csvd::SolveSpec spec;
-  // chunks of a stored block basis kept for the next solve (freeing and
-  // re-allocating tens of GB per solve stalls the device while the memory is
-  // cleared); csvd_trim releases them
-  std::vector<std::unique_ptr<csvd::DevBuf>> basis_cache;
 };
 
 struct csvd_server;

@@ -619,6 +619,37 @@ hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------ starting block
+// B[r * Lp + c] = R(r, c) for r <= c, 0 below: the triangle of a Householder
+// QR stored column-major (ld) in X.
+__global__ void b_r0(const double *__restrict__ X, int64_t ld, int Lp, double *__restrict__ B) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= Lp * Lp) return;
+  const int r = e / Lp, c = e - r * Lp;
+  B[e] = (r <= c) ? X[(int64_t)c * ld + r] : 0.0;
+}
+
+hipError_t launch_b_r0(const double *X, int64_t ld, int Lp, double *B, hipStream_t st) {
+  hipLaunchKernelGGL(b_r0, dim3((Lp * Lp + 255) / 256), dim3(256), 0, st, X, ld, Lp, B);
+  return hipGetLastError();
+}
+
+// Z = the first cols columns of the rows x rows identity, column-major (ld)
+__global__ void b_eye(double *__restrict__ Z, int64_t ld, int64_t rows, int cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = e / rows, r = e - c * rows;
+    Z[c * ld + r] = (r == c) ? 1.0 : 0.0;
+  }
+}
+
+hipError_t launch_b_eye(double *Z, int64_t ld, int64_t rows, int cols, hipStream_t st) {
+  int64_t g = (rows * cols + 255) / 256;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(b_eye, dim3((unsigned)g), dim3(256), 0, st, Z, ld, rows, cols);
+  return hipGetLastError();
+}
+
 __global__ void b_tick(int64_t *clock) { *clock += 1; }
 
 hipError_t launch_b_tick(int64_t *clock, hipStream_t st) {

@@ -855,6 +855,9 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   regs_to_lds<LP>(D, As);
   __syncthreads();
   chol_inv_blocked<LP>(As, Xs, thr, dead, Tmp);
+  // a step marked robust (flags[3], set by the host) leaves the new block to a
+  // Householder QR after gamma: M = I, N = P + C make gamma write W3
+  const bool robust = !init && gp(J.flags)[3] != 0;
   // one-pass test: rho = ||R1||_F ||R1^-1||_F / Lp, sums in a fixed order
   __shared__ int one_pass;
   {
@@ -880,7 +883,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
       }
       const bool anydead = __any(l < LP && dead[l] != 0);
       if (l == 0) {
-        const int op = (!init && !anydead && sqrt(a * x) <= J.onepass_rho * LP) ? 1 : 0;
+        const int op = (!init && (robust || (!anydead && sqrt(a * x) <= J.onepass_rho * LP))) ? 1 : 0;
         one_pass = op;
         gp(J.flags)[1] = op;
         if (op) gp(J.flags)[0] = 0;
@@ -898,19 +901,23 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
     R1[e] = rv;
     R1i[e] = Xs[r * SS + c];
     if (op) {
-      Bn[e] = rv;
-      Mk[e] = Xs[r * SS + c];
+      if (!robust) Bn[e] = rv;
+      Mk[e] = robust ? (r == c ? 1.0 : 0.0) : Xs[r * SS + c];
     }
     Pm[r * SS + c] += Cm[r * SS + c];  // P + C
   }
   __syncthreads();
+  if (robust) {
+    GLB double *Nk = gp(J.Nh) + (int64_t)k * L2;
+    for (int e = t; e < L2; e += kThreads) Nk[e] = Pm[(e / LP) * SS + (e % LP)];
+  }
   if (act) {
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) D[tj] = v4d{0.0, 0.0, 0.0, 0.0};
     if (!init) mm_lds<LP, false>(Pm, Xs, 1.0, D);
   }
   regs_to_glb<LP>(D, T);
-  if (op) regs_to_glb<LP>(D, gp(J.Nh) + (int64_t)k * L2);
+  if (op && !robust) regs_to_glb<LP>(D, gp(J.Nh) + (int64_t)k * L2);
 }
 
 template <int LP>

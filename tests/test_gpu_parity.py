@@ -176,7 +176,7 @@ def test_block_stored_basis_equals_regenerated():
             info = cs.csvd_get_info(ctx)
             say("keep_basis", keep, "status", st, "steps", info.iterations, "stored", info.basis_stored)
             assert st == cs.CSVD_OK and info.basis_stored == keep
-            assert info.iterations > 128
+            assert info.iterations > 64  # the last round's basis spans two storage chunks
             out.append(cs.csvd_get_triplets(ctx, I.m, I.n) + (cs.csvd_get_moment(ctx, 0, I.n, 8),))
         # the kept chunks are reused by the next solve, and freed on request
         st = cs.csvd_solve_interval(ctx, I.a, I.b, cs.csvd_params_default(
@@ -382,6 +382,37 @@ def test_block_one_and_two_cholqr_passes_agree():
         with pytest.raises(cs.CsvdError) as e:
             cs.csvd_solve_interval(ctx, a, b, cs.csvd_params_default(L=16, cholqr_passes=1), V)
         assert e.value.code == cs.CSVD_EINVAL
+    finally:
+        cs.csvd_destroy(ctx)
+
+
+def test_block_ell2_with_more_columns_than_values():
+    """Two rounds with L = 32 columns and 16 values in the interval: the
+    second round starts from a filtered block that is numerically rank
+    deficient, whose first Krylov blocks are orthonormalised by Householder
+    QR.  Matches dense truth and the per-column solver."""
+    I = synth.random_sparse(5200, 2600, 9, config=86)
+    A = I.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    a, b = synth.interval_by_count(ev, 1300, 16)
+    s_o, U_o, V_o, sall = truth.dense_truth(I, a, b)
+    V = synth.v_in(I.n, 32, 9)
+    ctx = make_ctx(I)
+    try:
+        out = []
+        for solver in (cs.CSVD_SOLVER_BLOCK, cs.CSVD_SOLVER_SINGLE):
+            p = cs.csvd_params_default(L=32, M=4, N=16, ell=2, solver=solver)
+            st = cs.csvd_solve_interval(ctx, a, b, p, V)
+            info = cs.csvd_get_info(ctx)
+            say("ell2 solver", solver, "status", st, "steps", info.iterations, "total", info.iterations_total)
+            assert st == cs.CSVD_OK
+            sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+            np.testing.assert_allclose(sig, s_o, rtol=1e-10)
+            r_host = truth.triplet_residuals(I, sig, U, Vv, normA=sall[0])
+            assert r_host.max() <= 1e-10
+            assert truth.subspace_gap(Vv, V_o) <= 1e-7
+            out.append(sig)
+        np.testing.assert_allclose(out[0], out[1], rtol=1e-11)
     finally:
         cs.csvd_destroy(ctx)
 
