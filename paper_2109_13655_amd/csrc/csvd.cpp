@@ -563,11 +563,15 @@ int run_finalize(SolveRun &R) {
   HIPCHK(ctx, dnorm.alloc(sizeof(double) * (LMe + 1)));
   HIPCHK(ctx, hipMemcpyAsync(dRt.p, Rt.data(), sizeof(double) * Rt.size(), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(dJ.p, Jm.data(), sizeof(double) * Jm.size(), hipMemcpyHostToDevice, st));
+  // one-sided Jacobi; a pair is rotated while |a_p^T a_q| > sqrt(rows) eps
+  // ||a_p|| ||a_q|| (the rounding level of the dot product itself, as in
+  // LAPACK's one-sided Jacobi): below it a rotation only moves noise
   auto jacobi = [&](double *A, int rows, int ncol_even, double *V, int vrows) -> int {
+    const double tol = std::sqrt((double)rows) * 2.220446049250313e-16;
     for (int sweep = 0; sweep < 60; ++sweep) {
       HIPCHK(ctx, hipMemsetAsync(dcnt.p, 0, sizeof(int), st));
       for (int s2 = 0; s2 + 1 < ncol_even; ++s2)
-        HIPCHK(ctx, launch_jacobi_step(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, 1e-15,
+        HIPCHK(ctx, launch_jacobi_step(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol,
                                        dcnt.as<int>(), st));
       int cnt = 0;
       HIPCHK(ctx, hipMemcpyAsync(&cnt, dcnt.p, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -17,15 +17,22 @@
 
 namespace csvd {
 
+// Sum over a wave by a butterfly; lane 0's result (a fixed order of additions)
+__device__ __forceinline__ double wave_sum0(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Sum over the kThreads threads of a block in a fixed order: butterflies in
+// each wave, then the waves' sums (lane 0) in order.  Every thread gets it.
 __device__ __forceinline__ double block_reduce(double v, double *red) {
+  static_assert(kThreads == 256, "four waves");
   const int t = threadIdx.x;
-  red[t] = v;
+  v = wave_sum0(v);
+  if ((t & 63) == 0) red[t >> 6] = v;
   __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if (t < off) red[t] += red[t + off];
-    __syncthreads();
-  }
-  const double r = red[0];
+  const double r = (red[0] + red[1]) + (red[2] + red[3]);
   __syncthreads();
   return r;
 }
@@ -124,7 +131,7 @@ hipError_t launch_hh_apply(const double *Xr, int64_t ldr, int rows, int nref_dir
 // rotate; step s pairs (n-1, s) and ((s+b) mod (n-1), (s-b) mod (n-1)).
 __global__ __launch_bounds__(kThreads) void k_jacobi(double *A, int64_t lda, int rows, int ncol, double *V,
                                                      int64_t ldv, int vrows, int step, double tol, int *counter) {
-  __shared__ double r0[kThreads], r1[kThreads], r2[kThreads];
+  __shared__ double r0[4], r1[4], r2[4];
   const int b = blockIdx.x;
   const int n1 = ncol - 1;
   int p, q;
@@ -149,19 +156,18 @@ __global__ __launch_bounds__(kThreads) void k_jacobi(double *A, int64_t lda, int
     spq = fma(x, y, spq);
   }
   const int t = threadIdx.x;
-  r0[t] = spp;
-  r1[t] = sqq;
-  r2[t] = spq;
-  __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if (t < off) {
-      r0[t] += r0[t + off];
-      r1[t] += r1[t + off];
-      r2[t] += r2[t + off];
-    }
-    __syncthreads();
+  spp = wave_sum0(spp);
+  sqq = wave_sum0(sqq);
+  spq = wave_sum0(spq);
+  if ((t & 63) == 0) {
+    r0[t >> 6] = spp;
+    r1[t >> 6] = sqq;
+    r2[t >> 6] = spq;
   }
-  const double app = r0[0], aqq = r1[0], apq = r2[0];
+  __syncthreads();
+  const double app = (r0[0] + r0[1]) + (r0[2] + r0[3]);
+  const double aqq = (r1[0] + r1[1]) + (r1[2] + r1[3]);
+  const double apq = (r2[0] + r2[1]) + (r2[2] + r2[3]);
   if (apq == 0.0 || !(fabs(apq) > tol * sqrt(app * aqq))) return;
   const double zeta = (aqq - app) / (2.0 * apq);
   const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -399,6 +405,7 @@ __global__ __launch_bounds__(256) void k_tg_reduce(const double *__restrict__ pa
   const int o = blockIdx.x * 32 + (t & 31);
   double s = 0.0;
   if (o < total)
+#pragma unroll 8
     for (int vb = grp; vb < nvb; vb += 8) s += part[(int64_t)vb * total + o];
   sp[grp][t & 31] = s;
   __syncthreads();
@@ -527,6 +534,8 @@ __global__ __launch_bounds__(64) void k_pf_coef(const double *__restrict__ part,
   const int t = threadIdx.x, nc = jend - j;
   if (t < nc) {
     double s = 0.0;
+    // eight partial sums in flight, added in order
+#pragma unroll 8
     for (int b = 0; b < nb; ++b) s += part[(int64_t)b * kHB + t];
     T[t] = s;
   }
