@@ -281,7 +281,7 @@ hipError_t BEngine::launch_shift(const BBatch &b, int init) {
   return launch_b_shift(bs, init, side_);
 }
 
-// CholeskyQR2 of Vpad gives Q_0 and R_0 = B_0; Z_0 = R_0 for every shift.
+// Householder QR of Vpad gives Q_0 and R_0 = B_0; Z_0 = R_0 for every shift.
 hipError_t BEngine::start(BlockJob *j) {
   BJobDesc &J = j->h;
   J.start_clock = (int)clock_;
@@ -473,9 +473,9 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
     if (timer && sample) timer->end(st_);
     if (timer && sample) timer->begin(2, st_);
-    if ((e = launch_bs_tall(b, 0, 1, 0, st_)) != hipSuccess) return e;   // W', P
+    if ((e = launch_bs_tall(b, 0, 1, st_)) != hipSuccess) return e;   // W', P
     if ((e = launch_bs_reduce(b, 0, 1, 0, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_tall(b, 1, 1, 0, st_)) != hipSuccess) return e;   // C, G2
+    if ((e = launch_bs_tall(b, 1, 1, st_)) != hipSuccess) return e;   // C, G2
     if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
     for (BlockJob *j : p1_) {  // mark the robust steps for small1
       const int k = (int)(clock_ - j->h.start_clock);
@@ -484,11 +484,11 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
               hipSuccess)
         return e;
     }
-    if ((e = launch_bs_small1(b, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_tall(b, 2, 1, 0, st_)) != hipSuccess) return e;   // G3
+    if ((e = launch_bs_small1(b, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_tall(b, 2, 1, st_)) != hipSuccess) return e;   // G3
     if ((e = launch_bs_reduce(b, 1, 1, 3, 1, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_small2(b, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_gamma(b, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_small2(b, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
     if ((e = robust_finish(p1_, true)) != hipSuccess) return e;
     if ((e = launch_shift(b, 0)) != hipSuccess) return e;
     if (timer && sample) timer->end(st_);
@@ -510,8 +510,8 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     }
     if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_tall(b, 0, 0, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_gamma(b, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_tall(b, 0, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
     if ((e = robust_finish(p2_, false)) != hipSuccess) return e;
   }
   if (p1_.empty() && p2_.empty()) return hipSuccess;

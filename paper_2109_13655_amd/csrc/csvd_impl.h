@@ -166,16 +166,16 @@ hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st);
 // Tall kernels of one block step (see k_bstep.hip).  mode 0 (alpha): W' =
 // W - Q_{k-1} B_k^T and (grams = 1) the partial Gram matrix Q_k^T W'; mode 1
 // (beta): partial Gram matrices of W2 = W' - Q_k P; mode 2 (gamma0): partial
-// Gram matrix of Y = W' R1^-1 - Q_k T; init = 1 takes Vpad for W' and no Q_k.
-// gamma: Q_{k+1} = W' M_k - Q_k N_k (init = 1: Q_0 = Vpad M_init).
-hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st);
-hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st);
+// Gram matrix of Y = W' R1^-1 - Q_k T (skipped on one-pass steps).
+// gamma: Q_{k+1} = W' M_k - Q_k N_k.
+hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, hipStream_t st);
+hipError_t launch_bs_gamma(const BBatch &b, hipStream_t st);
 // reduction of nm partial Gram matrices from slot m0 into red slots d0.. (fixed order)
 hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, int second, hipStream_t st);
-// small1: A_k, first Cholesky, R1^-1, T.  small2: second Cholesky, M_k, N_k,
-// B_{k+1} (init = 1: M_init and B_0)
-hipError_t launch_bs_small1(const BBatch &b, int init, hipStream_t st);
-hipError_t launch_bs_small2(const BBatch &b, int init, hipStream_t st);
+// small1: A_k, first Cholesky, R1^-1, T (and M_k, N_k, B_{k+1} on one-pass
+// steps).  small2: second Cholesky, M_k, N_k, B_{k+1}
+hipError_t launch_bs_small1(const BBatch &b, hipStream_t st);
+hipError_t launch_bs_small2(const BBatch &b, hipStream_t st);
 hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st);
 hipError_t launch_b_backsolve(const BJobDesc &hj, int K, hipStream_t st);
 hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st);

@@ -222,19 +222,21 @@ __device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, bo
 }
 
 // ---------------------------------------------------------- tall passes
-// mode kTallAlpha: W' = W - Q_{k-1} B_k^T stored in place; Gram Q_k^T W'
-//   (when grams = 1).
-// mode kTallBeta:  W2 = X - Q_k P with X = W' (init: Vpad, no Q term);
-//   Grams Q_k^T W2 and W2^T W2.
-// mode kTallGamma0: Y = X R1^-1 - Q_k T (init: no Q term); Gram Y^T Y.
+// kTallAlpha: W' = W - Q_{k-1} B_k^T stored in place; Gram Q_k^T W' (when
+//   grams = 1).
+// kTallBeta:  W2 = W' - Q_k P (not stored); Grams Q_k^T W2 and W2^T W2.
+// kTallGamma0: Y = W' R1^-1 - Q_k T (not stored); Gram Y^T Y.
 enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
 
+// gamma0 (the second Cholesky QR pass); its Gram tiles are staged through
+// LDS (ten tiles per panel do not fit the registers of two waves per SIMD
+// next to the two panel products)
 template <int LP>
-__global__ __launch_bounds__(kTallThreads) void bs_tall(const BJobDesc *__restrict__ jobs, int njob,
-                                                    const int *__restrict__ toff, const int64_t *__restrict__ clock,
-                                                    int mode, int grams, int init) {
+__global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__restrict__ jobs, int njob,
+                                                      const int *__restrict__ toff,
+                                                      const int64_t *__restrict__ clock) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
-  __shared__ double Xs[kPanel * kPSMax], Ys[kPanel * kPSMax];
+  __shared__ double Ys[kPanel * kPSMax];
   constexpr int L2 = LP * LP, NT = LP / 16;
   const int g = blockIdx.x;
   const int j = bfind2(toff, njob, g);
@@ -242,56 +244,38 @@ __global__ __launch_bounds__(kTallThreads) void bs_tall(const BJobDesc *__restri
   if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
-  if (mode == kTallGamma0 && !init && gp(J.flags)[1]) return;  // one-pass step
+  if (gp(J.flags)[1]) return;  // one-pass step
   const int vb = g - toff[j];
-  const int t = threadIdx.x, w = t >> 6;
-  const int64_t n = J.n, nL = n * LP;
-  GLB double *X = init ? gp(J.Vpad) : gp(J.W);
+  const int w = threadIdx.x >> 6;
+  const int64_t n = J.n;
+  const GLB double *X = gp(J.W);
   const GLB double *Qc = qblock(J, k);
-  const GLB double *Pv = qblock(J, k > 0 ? k - 1 : k);
-  const bool useQ = !init && (mode != kTallAlpha || k > 0);
-  if (mode == kTallAlpha) {
-    if (useQ) stage_mat<LP, kTallThreads>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
-  } else if (mode == kTallBeta) {
-    if (useQ) stage_mat<LP, kTallThreads>(gp(J.red), false, true, S2);  // -P
-  } else {
-    stage_mat<LP, kTallThreads>(gp(J.scr) + L2, false, false, S1);           // R1^-1
-    if (useQ) stage_mat<LP, kTallThreads>(gp(J.scr) + 2 * L2, false, true, S2);  // -T
-  }
+  stage_mat<LP, kTallThreads>(gp(J.scr) + L2, false, false, S1);      // R1^-1
+  stage_mat<LP, kTallThreads>(gp(J.scr) + 2 * L2, false, true, S2);  // -T
   __syncthreads();
-  const int nfull = (mode == kTallGamma0) ? 0 : NT * NT;
-  const int ntile = nfull + ((mode == kTallAlpha) ? 0 : NT * (NT + 1) / 2);
+  constexpr int ntile = NT * (NT + 1) / 2;
   v4d acc[kMaxTiles];
 #pragma unroll
   for (int i = 0; i < kMaxTiles; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
   const int nch = (int)((n + kTallRows - 1) / kTallRows);
   for (int ch = vb; ch < nch; ch += J.nvb) {
     const int64_t r0 = (int64_t)ch * kTallRows + 16 * w;
-    v4d D[4];
-    if (mode == kTallGamma0) {
-      zero4(D);
-      panel_mm<LP>(X, r0, n, S1, D);
-    } else {
-      load_dl<LP>(X, r0, n, D);
-    }
-    if (useQ) panel_mm<LP>(mode == kTallAlpha ? Pv : Qc, r0, n, S2, D);
-    if (mode == kTallAlpha && useQ) store_dl<LP>(X, r0, n, D);
-    if (grams) {
-      v4d Qd[4];
-      zero4(Qd);
-      if (nfull && !init) load_dl<LP>(Qc, r0, n, Qd);
-      gram_chunk<LP>(Qd, D, nfull, ntile, Xs, Ys, acc);
-    }
+    v4d D[4], Qd[4];
+    zero4(D);
+    zero4(Qd);
+    panel_mm<LP>(X, r0, n, S1, D);
+    panel_mm<LP>(Qc, r0, n, S2, D);
+    gram_chunk<LP>(Qd, D, 0, ntile, Ys, Ys, acc);
   }
-  if (grams) store_gram(J, vb, nfull, ntile, acc);
+  store_gram(J, vb, 0, ntile, acc);
 }
 
 // ------------------------------------------------------------------ gamma
-// Q_{k+1} = W' M_k - Q_k N_k; init = 1: Q_0 = Vpad M_init.
+// Q_{k+1} = W' M_k - Q_k N_k
 template <int LP>
 __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
-                                                     const int *__restrict__ toff, const int64_t *__restrict__ clock,
-                                                     int init) {
+                                                     const int *__restrict__ toff,
+                                                     const int64_t *__restrict__ clock) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
   constexpr int L2 = LP * LP;
   const int g = blockIdx.x;
@@ -302,12 +286,12 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
   if (k >= J.Kstop) return;
   const int vb = g - toff[j];
   const int w = threadIdx.x >> 6;
-  const int64_t n = J.n, nL = n * LP;
-  const GLB double *X = init ? gp(J.Vpad) : gp(J.W);
+  const int64_t n = J.n;
+  const GLB double *X = gp(J.W);
   const GLB double *Qc = qblock(J, k);
-  GLB double *Qn = qblock(J, init ? k : k + 1);
-  stage_mat<LP, kTallThreads>(gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2, false, false, S1);
-  if (!init) stage_mat<LP, kTallThreads>(gp(J.Nh) + (int64_t)k * L2, false, true, S2);
+  GLB double *Qn = qblock(J, k + 1);
+  stage_mat<LP, kTallThreads>(gp(J.Mh) + (int64_t)k * L2, false, false, S1);
+  stage_mat<LP, kTallThreads>(gp(J.Nh) + (int64_t)k * L2, false, true, S2);
   __syncthreads();
   const int nch = (int)((n + kTallRows - 1) / kTallRows);
   for (int ch = vb; ch < nch; ch += J.nvb) {
@@ -315,7 +299,10 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
     v4d D[4];
     zero4(D);
     panel_mm<LP>(X, r0, n, S1, D);
-    if (!init) panel_mm<LP>(Qc, r0, n, S2, D);
+    // keeps the second panel's loads after the first product (hoisted, they
+    // exceed the register file at Lp = 64)
+    __builtin_amdgcn_sched_barrier(0);
+    panel_mm<LP>(Qc, r0, n, S2, D);
     store_dl<LP>(Qn, r0, n, D);
   }
 }
@@ -332,7 +319,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
 template <int LP, int MODE, int NTH>
 __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void bs_tall_rg(
     const BJobDesc *__restrict__ jobs, int njob, const int *__restrict__ toff, const int64_t *__restrict__ clock,
-    int grams, int init) {
+    int grams) {
   constexpr int NT = LP / 16, L2 = LP * LP, NW = NTH / 64;
   constexpr int NF = (MODE == kTallGamma0) ? 0 : NT * NT;       // tiles of Q_k^T X
   constexpr int NS = (MODE == kTallAlpha) ? 0 : NT * (NT + 1) / 2;  // upper tiles of X^T X
@@ -345,21 +332,18 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
   if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
-  if (MODE == kTallGamma0 && !init && gp(J.flags)[1]) return;  // one-pass step
+  static_assert(MODE == kTallAlpha || MODE == kTallBeta, "alpha and beta passes");
   const int vb = g - toff[j];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const int64_t n = J.n;
-  GLB double *X = init ? gp(J.Vpad) : gp(J.W);
+  GLB double *X = gp(J.W);
   const GLB double *Qc = qblock(J, k);
   const GLB double *Pv = qblock(J, k > 0 ? k - 1 : k);
-  const bool useQ = !init && (MODE != kTallAlpha || k > 0);
+  const bool useQ = (MODE != kTallAlpha || k > 0);
   if (MODE == kTallAlpha) {
     if (useQ) stage_mat<LP, NTH>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
-  } else if (MODE == kTallBeta) {
-    if (useQ) stage_mat<LP, NTH>(gp(J.red), false, true, S2);  // -P
   } else {
-    stage_mat<LP, NTH>(gp(J.scr) + L2, false, false, S1);           // R1^-1
-    if (useQ) stage_mat<LP, NTH>(gp(J.scr) + 2 * L2, false, true, S2);  // -T
+    stage_mat<LP, NTH>(gp(J.red), false, true, S2);  // -P
   }
   __syncthreads();
   v4d acc[NA];
@@ -369,19 +353,14 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
   for (int pn = vb * NW + w; pn < npanel; pn += J.nvb * NW) {
     const int64_t r0 = (int64_t)pn * 16;
     v4d D[4];
-    if (MODE == kTallGamma0) {
-      zero4(D);
-      panel_mm<LP>(X, r0, n, S1, D);
-    } else {
-      load_dl<LP>(X, r0, n, D);
-    }
+    load_dl<LP>(X, r0, n, D);
     if (useQ) panel_mm<LP>(MODE == kTallAlpha ? Pv : Qc, r0, n, S2, D);
     if (MODE == kTallAlpha && useQ) store_dl<LP>(X, r0, n, D);
     if (grams) {
+      __builtin_amdgcn_sched_barrier(0);  // Q_k panel loads after the update (register pressure)
       if (NF) {
         v4d Qd[4];
-        zero4(Qd);
-        if (!init) load_dl<LP>(Qc, r0, n, Qd);
+        load_dl<LP>(Qc, r0, n, Qd);
 #pragma unroll
         for (int ti = 0; ti < NT; ++ti)
 #pragma unroll
@@ -808,7 +787,7 @@ __device__ void chol_inv_blocked(double *A, double *X, const double *thr, int *d
 // G3 (upper tiles); scr = R1, R1^-1, T
 template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict__ jobs,
-                                                      const int64_t *__restrict__ clock, int init) {
+                                                      const int64_t *__restrict__ clock) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
   __shared__ double Pm[LP * SS], Cm[LP * SS], As[LP * SS], Xs[LP * SS];
   __shared__ double Tmp[4 * 16 * 17];
@@ -821,12 +800,8 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const bool act = w < NT;
   const GLB double *red = gp(J.red);
-  if (init) {
-    for (int e = t; e < L2; e += kThreads) Pm[(e / LP) * SS + (e % LP)] = Cm[(e / LP) * SS + (e % LP)] = 0.0;
-  } else {
-    glb_to_lds<LP>(red, Pm, false);
-    glb_to_lds<LP>(red + L2, Cm, false);
-  }
+  glb_to_lds<LP>(red, Pm, false);
+  glb_to_lds<LP>(red + L2, Cm, false);
   v4d D[4];
   if (act)
 #pragma unroll
@@ -840,11 +815,10 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   if (t < LP) {
     double own = gram_sym(red + 2 * L2, LP, t, t);
     for (int i = 0; i < LP; ++i) own = fma(Pm[i * SS + t], Pm[i * SS + t], own);
-    const double flo = init ? 0.0 : (1e-14 * J.dscale) * (1e-14 * J.dscale);
+    const double flo = (1e-14 * J.dscale) * (1e-14 * J.dscale);
     thr[t] = fmax(kDeflTol * kDeflTol * own, flo);
-    if (init) gp(J.beta0)[t] = sqrt(fmax(gram_sym(red + 2 * L2, LP, t, t), 0.0));
   }
-  if (!init) {
+  {
     GLB double *Ak = gp(J.Ah) + (int64_t)k * L2;
     for (int e = t; e < L2; e += kThreads) {
       const int r = e / LP, c = e - r * LP;
@@ -857,7 +831,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   chol_inv_blocked<LP>(As, Xs, thr, dead, Tmp);
   // a step marked robust (flags[3], set by the host) leaves the new block to a
   // Householder QR after gamma: M = I, N = P + C make gamma write W3
-  const bool robust = !init && gp(J.flags)[3] != 0;
+  const bool robust = gp(J.flags)[3] != 0;
   // one-pass test: rho = ||R1||_F ||R1^-1||_F / Lp, sums in a fixed order
   __shared__ int one_pass;
   {
@@ -883,11 +857,11 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
       }
       const bool anydead = __any(l < LP && dead[l] != 0);
       if (l == 0) {
-        const int op = (!init && (robust || (!anydead && sqrt(a * x) <= J.onepass_rho * LP))) ? 1 : 0;
+        const int op = (robust || (!anydead && sqrt(a * x) <= J.onepass_rho * LP)) ? 1 : 0;
         one_pass = op;
         gp(J.flags)[1] = op;
         if (op) gp(J.flags)[0] = 0;
-        gp(J.flags)[2] = init ? 0 : gp(J.flags)[2] + op;  // one-pass steps of this round
+        gp(J.flags)[2] += op;  // one-pass steps of this round
       }
     }
     __syncthreads();
@@ -914,7 +888,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   if (act) {
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) D[tj] = v4d{0.0, 0.0, 0.0, 0.0};
-    if (!init) mm_lds<LP, false>(Pm, Xs, 1.0, D);
+    mm_lds<LP, false>(Pm, Xs, 1.0, D);
   }
   regs_to_glb<LP>(D, T);
   if (op && !robust) regs_to_glb<LP>(D, gp(J.Nh) + (int64_t)k * L2);
@@ -922,7 +896,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
 
 template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict__ jobs,
-                                                      const int64_t *__restrict__ clock, int init) {
+                                                      const int64_t *__restrict__ clock) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
   __shared__ double As[LP * SS], Xs[LP * SS], Os[LP * SS];
   __shared__ double Tmp[4 * 16 * 17];
@@ -932,7 +906,7 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
   if (J.Lp != LP) return;
   const int k = (int)(*clock - J.start_clock);
   if (k >= J.Kstop) return;
-  if (!init && gp(J.flags)[1]) return;  // one-pass step: small1 wrote M, N and B
+  if (gp(J.flags)[1]) return;  // one-pass step: small1 wrote M, N and B
   const int t = threadIdx.x, w = t >> 6;
   const bool act = w < NT;
   const GLB double *red = gp(J.red);
@@ -973,9 +947,9 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
     for (int tj = 0; tj < NT; ++tj) E[tj] = v4d{0.0, 0.0, 0.0, 0.0};
     mm_lds<LP, false>(Os, Xs, 1.0, E);
   }
-  regs_to_glb<LP>(E, gp(J.Mh) + (int64_t)(init ? J.Kcap : k) * L2);
+  regs_to_glb<LP>(E, gp(J.Mh) + (int64_t)k * L2);
   __syncthreads();
-  if (!init) {
+  {
     // N = T R2^-1
     glb_to_lds<LP>(T, Os, false);
     __syncthreads();
@@ -995,25 +969,25 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
     for (int tj = 0; tj < NT; ++tj) E[tj] = v4d{0.0, 0.0, 0.0, 0.0};
     mm_lds<LP, false>(As, Os, 1.0, E);
   }
-  regs_to_glb<LP>(E, gp(J.Bh) + (int64_t)(init ? 0 : k + 1) * L2);
+  regs_to_glb<LP>(E, gp(J.Bh) + (int64_t)(k + 1) * L2);
 }
 
 // ---------------------------------------------------------------- launchers
 // one launch per block width present in the batch (blocks of jobs of another
 // width return at once)
-hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStream_t st) {
+hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, hipStream_t st) {
   // alpha and beta: wave-local Gram products (beta at Lp = 64 holds 26 Gram
   // tiles per wave: one wave per SIMD); gamma0: panels staged through LDS
 #define CSVD_TALL(LPV)                                                                                           \
   if (mode == kTallAlpha)                                                                                        \
     hipLaunchKernelGGL((bs_tall_rg<LPV, kTallAlpha, 512>), dim3(b.totalr), dim3(512), 0, st, b.jobs, b.njob,     \
-                       b.toffr, b.clock, grams, init);                                                           \
+                       b.toffr, b.clock, grams);                                                                 \
   else if (mode == kTallBeta)                                                                                    \
     hipLaunchKernelGGL((bs_tall_rg<LPV, kTallBeta, (LPV == 64 ? 256 : 512)>), dim3(b.totalr),                    \
-                       dim3(LPV == 64 ? 256 : 512), 0, st, b.jobs, b.njob, b.toffr, b.clock, grams, init);       \
+                       dim3(LPV == 64 ? 256 : 512), 0, st, b.jobs, b.njob, b.toffr, b.clock, grams);             \
   else                                                                                                           \
-    hipLaunchKernelGGL(bs_tall<LPV>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, \
-                       mode, grams, init);
+    hipLaunchKernelGGL(bs_gamma0<LPV>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr,       \
+                       b.clock);
   if (b.lpmask & 1) CSVD_TALL(16)
   if (b.lpmask & 2) CSVD_TALL(32)
   if (b.lpmask & 4) CSVD_TALL(64)
@@ -1021,13 +995,13 @@ hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, int init, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_bs_gamma(const BBatch &b, int init, hipStream_t st) {
+hipError_t launch_bs_gamma(const BBatch &b, hipStream_t st) {
   if (b.lpmask & 1)
-    hipLaunchKernelGGL(bs_gamma<16>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+    hipLaunchKernelGGL(bs_gamma<16>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock);
   if (b.lpmask & 2)
-    hipLaunchKernelGGL(bs_gamma<32>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+    hipLaunchKernelGGL(bs_gamma<32>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock);
   if (b.lpmask & 4)
-    hipLaunchKernelGGL(bs_gamma<64>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock, init);
+    hipLaunchKernelGGL(bs_gamma<64>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock);
   return hipGetLastError();
 }
 
@@ -1037,17 +1011,17 @@ hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, int second,
   return hipGetLastError();
 }
 
-hipError_t launch_bs_small1(const BBatch &b, int init, hipStream_t st) {
-  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small1<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
-  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small1<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
-  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small1<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+hipError_t launch_bs_small1(const BBatch &b, hipStream_t st) {
+  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small1<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
+  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small1<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
+  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small1<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
   return hipGetLastError();
 }
 
-hipError_t launch_bs_small2(const BBatch &b, int init, hipStream_t st) {
-  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small2<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
-  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small2<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
-  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small2<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock, init);
+hipError_t launch_bs_small2(const BBatch &b, hipStream_t st) {
+  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small2<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
+  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small2<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
+  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small2<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
   return hipGetLastError();
 }
 
