@@ -257,6 +257,8 @@ hipError_t BEngine::init() {
   if ((e = d_sclock_.alloc(sizeof(int64_t))) != hipSuccess) return e;
   if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&snap_main_, hipEventDisableTiming)) != hipSuccess) return e;
+  if ((e = hipEventCreateWithFlags(&snap_side_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(d_clock_.p, 0, sizeof(int64_t), st_)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(d_sclock_.p, 0, sizeof(int64_t), st_)) != hipSuccess) return e;
   return hipStreamSynchronize(st_);
@@ -267,7 +269,11 @@ BEngine::~BEngine() {
     (void)hipStreamSynchronize(side_);
     (void)hipStreamDestroy(side_);
   }
+  (void)hipStreamSynchronize(st_);
   if (ev_) (void)hipEventDestroy(ev_);
+  if (snap_main_) (void)hipEventDestroy(snap_main_);
+  if (snap_side_) (void)hipEventDestroy(snap_side_);
+  if (snap_host_) (void)hipHostFree(snap_host_);
 }
 
 // the shift recurrences of the current step on the side stream, after the
@@ -523,30 +529,68 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
   return hipSuccess;
 }
 
+hipError_t BEngine::take_snapshot() {
+  snap_.clear();
+  if (p1_.empty()) return hipSuccess;
+  hipError_t e;
+  if (p1_.size() > snap_cap_) {
+    // no copy into the old buffer is pending: its events were waited for
+    if (snap_host_) (void)hipHostFree(snap_host_);
+    snap_host_ = nullptr;
+    snap_cap_ = 0;
+    const size_t cap = std::max<size_t>(16, 2 * p1_.size());
+    if ((e = hipHostMalloc((void **)&snap_host_, 4 * sizeof(int) * cap, hipHostMallocDefault)) != hipSuccess)
+      return e;
+    snap_cap_ = cap;
+  }
+  for (BlockJob *j : p1_) {
+    const BJobDesc &J = j->h;
+    const int steps = (int)(clock_ - J.start_clock);
+    if (steps <= 0) continue;
+    // the newest step whose recurrences ran (none run past Kstop); its
+    // active count is written on the side stream, the flags on the main one
+    const int klast = std::min(steps - 1, J.Kstop - 1);
+    int *h = snap_host_ + 4 * snap_.size();
+    if ((e = hipMemcpyAsync(h, J.active + (klast & 1), sizeof(int), hipMemcpyDeviceToHost, side_)) != hipSuccess)
+      return e;
+    if ((e = hipMemcpyAsync(h + 1, J.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st_)) != hipSuccess) return e;
+    snap_.push_back({j, steps});
+  }
+  if (snap_.empty()) return hipSuccess;
+  if ((e = hipEventRecord(snap_main_, st_)) != hipSuccess) return e;
+  return hipEventRecord(snap_side_, side_);
+}
+
 hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
   hipError_t e;
-  // pass-1 jobs: unconverged pairs after their last step
-  const int n1 = (int)p1_.size();
-  std::vector<int> act(n1, 1);
-  // the active counts are written on the side stream
-  if ((e = hipStreamSynchronize(side_)) != hipSuccess) return e;
-  for (int i = 0; i < n1; ++i) {
-    const BJobDesc &J = p1_[i]->h;
-    // the newest step whose recurrences ran (none run past Kstop)
-    const int klast = std::min((int)(clock_ - 1 - J.start_clock), J.Kstop - 1);
-    if (klast < 0) continue;
-    e = hipMemcpyAsync(&act[i], J.active + (klast & 1), sizeof(int), hipMemcpyDeviceToHost, st_);
-    if (e != hipSuccess) return e;
+  // pass-1 jobs that were unconverged after their last step at the previous poll
+  std::vector<BlockJob *> ending;
+  if (!snap_.empty()) {
+    if ((e = hipEventSynchronize(snap_main_)) != hipSuccess) return e;
+    if ((e = hipEventSynchronize(snap_side_)) != hipSuccess) return e;
+    for (size_t i = 0; i < snap_.size(); ++i) {
+      BlockJob *j = snap_[i].j;
+      if (!j || j->pass != 1) continue;
+      const int *h = snap_host_ + 4 * i;
+      const int steps = snap_[i].steps;
+      if (h[0] == 0 || steps >= j->Kcap) {
+        j->K = std::min(steps, j->Kcap);
+        j->steps_last = j->K;
+        j->converged = (h[0] == 0);
+        j->deflated_last = h[1];
+        j->one_pass_last = h[3];
+        ending.push_back(j);
+      }
+    }
+    snap_.clear();
   }
-  if ((e = hipStreamSynchronize(st_)) != hipSuccess) return e;
+  // the shift recurrences of the steps past K may still run on the side
+  // stream: they end before the backward solution and a new round's set-up
+  if (!ending.empty() && (e = hipStreamSynchronize(side_)) != hipSuccess) return e;
   std::vector<BlockJob *> keep1;
-  for (int i = 0; i < n1; ++i) {
-    BlockJob *j = p1_[i];
+  for (BlockJob *j : p1_) {
     const int steps = (int)(clock_ - j->h.start_clock);
-    if (steps > 0 && (act[i] == 0 || steps >= j->Kcap)) {
-      j->K = std::min(steps, j->Kcap);
-      j->steps_last = j->K;
-      j->converged = (act[i] == 0);
+    if (std::find(ending.begin(), ending.end(), j) != ending.end()) {
       dirty1_ = true;
       if (j->store) {
         if ((e = finish_stored(j)) != hipSuccess) return e;
@@ -576,6 +620,7 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
     }
   }
   p1_.swap(keep1);
+  if ((e = take_snapshot()) != hipSuccess) return e;
   std::vector<BlockJob *> keep2;
   for (BlockJob *j : p2_) {
     const int steps = (int)(clock_ - j->h.start_clock);
@@ -610,6 +655,8 @@ void BEngine::remove(BlockJob *j) {
   };
   r(p1_, dirty1_);
   r(p2_, dirty2_);
+  for (Snap &x : snap_)
+    if (x.j == j) x.j = nullptr;
 }
 
 }  // namespace csvd

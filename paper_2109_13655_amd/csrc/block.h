@@ -38,6 +38,8 @@ struct BlockJob {
   int64_t steps_total = 0; // over all passes and rounds
   int64_t steps_last = 0;  // pass-1 steps of the last round
   int mflushed = 0;        // second-pass steps whose moments are already in Sout
+  int deflated_last = 0;   // deflated columns and one-pass steps at step K - 1 of the last pass 1
+  int one_pass_last = 0;
   int robust_steps = 0;    // steps 0 .. robust_steps - 1 of each pass orthonormalise the new block by
                            // Householder QR (rounds after the first start from a filtered block
                            // whose first Krylov block is numerically rank deficient)
@@ -91,6 +93,22 @@ class BEngine {
   // robust steps of the jobs in v after their gamma (Q_{k+1} from W3)
   hipError_t robust_finish(std::vector<BlockJob *> &v, bool first_pass);
   hipError_t launch_shift(const BBatch &b, int init);
+  // Convergence snapshot: each poll copies the counters of every pass-1 job
+  // (after its last enqueued step) into pinned host memory without waiting,
+  // and decides from the snapshot of the poll before, so the device always
+  // has the steps of one poll interval queued.  A job whose snapshot shows
+  // convergence after `steps` steps ends with K = steps, as if it had been
+  // polled at once; the steps it ran meanwhile only wrote history entries
+  // and basis blocks past K.
+  struct Snap {
+    BlockJob *j;
+    int steps;
+  };
+  hipError_t take_snapshot();
+  std::vector<Snap> snap_;
+  int *snap_host_ = nullptr;  // pinned, 4 ints per entry: active count, flags[0..2]
+  size_t snap_cap_ = 0;
+  hipEvent_t snap_main_ = nullptr, snap_side_ = nullptr;
   KernelTimer *timer_ = nullptr;  // the timer of the last step() call (moment launches are sampled)
   hipStream_t st_;
   hipStream_t side_ = nullptr;

@@ -768,12 +768,8 @@ int run_finalize(SolveRun &R) {
     // A^T, u gather (m x Lp), w write (n x Lp)
     info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
     info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + n);
-    int fl = 0;
-    HIPCHK(ctx, hipMemcpy(&fl, R.bjob->h.flags, sizeof(int), hipMemcpyDeviceToHost));
-    info.deflated = fl;
-    int ops = 0;
-    HIPCHK(ctx, hipMemcpy(&ops, R.bjob->h.flags + 2, sizeof(int), hipMemcpyDeviceToHost));
-    info.one_pass_steps = ops;
+    info.deflated = R.bjob->deflated_last;
+    info.one_pass_steps = R.bjob->one_pass_last;
     info.basis_stored = R.bjob->stored_last ? 1 : 0;
   } else {
     info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
