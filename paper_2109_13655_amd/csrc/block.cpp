@@ -252,16 +252,12 @@ hipError_t BlockJob::sync_desc(hipStream_t st) {
 
 // ------------------------------------------------------------------ engine
 hipError_t BEngine::init() {
-  hipError_t e = d_clock_.alloc(sizeof(int64_t));
+  hipError_t e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
-  if ((e = d_sclock_.alloc(sizeof(int64_t))) != hipSuccess) return e;
-  if ((e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&snap_main_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&snap_side_, hipEventDisableTiming)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(d_clock_.p, 0, sizeof(int64_t), st_)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(d_sclock_.p, 0, sizeof(int64_t), st_)) != hipSuccess) return e;
-  return hipStreamSynchronize(st_);
+  return hipSuccess;
 }
 
 BEngine::~BEngine() {
@@ -282,9 +278,7 @@ hipError_t BEngine::launch_shift(const BBatch &b, int init) {
   hipError_t e = hipEventRecord(ev_, st_);
   if (e != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(side_, ev_, 0)) != hipSuccess) return e;
-  BBatch bs = b;
-  bs.clock = d_sclock_.as<int64_t>();
-  return launch_b_shift(bs, init, side_);
+  return launch_b_shift(b, init, side_);
 }
 
 // Householder QR of Vpad gives Q_0 and R_0 = B_0; Z_0 = R_0 for every shift.
@@ -320,7 +314,7 @@ hipError_t BEngine::start(BlockJob *j) {
   if ((e = hipMemsetAsync(J.flags + 1, 0, 3 * sizeof(int), st_)) != hipSuccess) return e;
   if ((e = start_block(j, true)) != hipSuccess) return e;
   BBatch b = j->solo;
-  b.clock = d_clock_.as<int64_t>();
+  b.clock = clock_;
   if ((e = launch_shift(b, 1)) != hipSuccess) return e;
   p1_.push_back(j);
   dirty1_ = true;
@@ -459,7 +453,6 @@ hipError_t BEngine::rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &d
   b.totals = ts[nj];
   b.lpmask = 0;
   for (int i = 0; i < nj; ++i) b.lpmask |= lp_bit(descs[i].Lp);
-  b.clock = d_clock_.as<int64_t>();
   return hipSuccess;
 }
 
@@ -468,9 +461,11 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
   hipError_t e;
   if (!p1_.empty()) {
     if (dirty1_) {
+      if ((e = flush_shifts()) != hipSuccess) return e;  // with the tables of their steps
       if ((e = rebuild(p1_, dj1_, dt1_, b1_)) != hipSuccess) return e;
       dirty1_ = false;
     }
+    b1_.clock = clock_;
     const BBatch &b = b1_;
     if (timer && sample) timer->begin(0, st_);
     if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
@@ -496,7 +491,7 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = launch_bs_small2(b, st_)) != hipSuccess) return e;
     if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
     if ((e = robust_finish(p1_, true)) != hipSuccess) return e;
-    if ((e = launch_shift(b, 0)) != hipSuccess) return e;
+    ++npend_;  // its shift recurrences run at the next poll
     if (timer && sample) timer->end(st_);
   }
   if (!p2_.empty()) {
@@ -504,6 +499,7 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
       if ((e = rebuild(p2_, dj2_, dt2_, b2_)) != hipSuccess) return e;
       dirty2_ = false;
     }
+    b2_.clock = clock_;
     const BBatch &b = b2_;
     // moments of the last window: S += sum Q_k F_k over kMomWindow steps,
     // before the ring slots of that window are reused
@@ -521,11 +517,23 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = robust_finish(p2_, false)) != hipSuccess) return e;
   }
   if (p1_.empty() && p2_.empty()) return hipSuccess;
-  if ((e = launch_b_tick(d_clock_.as<int64_t>(), st_)) != hipSuccess) return e;
-  if ((e = launch_b_tick(d_sclock_.as<int64_t>(), side_)) != hipSuccess) return e;
   ++clock_;
   for (BlockJob *j : p1_) j->steps_total++;
   for (BlockJob *j : p2_) j->steps_total++;
+  return hipSuccess;
+}
+
+hipError_t BEngine::flush_shifts() {
+  if (npend_ == 0) return hipSuccess;
+  hipError_t e = hipEventRecord(ev_, st_);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(side_, ev_, 0)) != hipSuccess) return e;
+  BBatch b = b1_;
+  for (int i = npend_; i > 0; --i) {
+    b.clock = clock_ - i;
+    if ((e = launch_b_shift(b, 0, side_)) != hipSuccess) return e;
+  }
+  npend_ = 0;
   return hipSuccess;
 }
 
@@ -533,8 +541,13 @@ hipError_t BEngine::take_snapshot() {
   snap_.clear();
   if (p1_.empty()) return hipSuccess;
   hipError_t e;
+  if (dirty1_) {  // the batch tables list the jobs in the order of p1_
+    if ((e = rebuild(p1_, dj1_, dt1_, b1_)) != hipSuccess) return e;
+    dirty1_ = false;
+  }
   if (p1_.size() > snap_cap_) {
-    // no copy into the old buffer is pending: its events were waited for
+    // nothing writes to the old buffer any more: the events of its last
+    // snapshot were waited for
     if (snap_host_) (void)hipHostFree(snap_host_);
     snap_host_ = nullptr;
     snap_cap_ = 0;
@@ -543,26 +556,21 @@ hipError_t BEngine::take_snapshot() {
       return e;
     snap_cap_ = cap;
   }
-  for (BlockJob *j : p1_) {
-    const BJobDesc &J = j->h;
-    const int steps = (int)(clock_ - J.start_clock);
-    if (steps <= 0) continue;
-    // the newest step whose recurrences ran (none run past Kstop); its
-    // active count is written on the side stream, the flags on the main one
-    const int klast = std::min(steps - 1, J.Kstop - 1);
-    int *h = snap_host_ + 4 * snap_.size();
-    if ((e = hipMemcpyAsync(h, J.active + (klast & 1), sizeof(int), hipMemcpyDeviceToHost, side_)) != hipSuccess)
-      return e;
-    if ((e = hipMemcpyAsync(h + 1, J.flags, 3 * sizeof(int), hipMemcpyDeviceToHost, st_)) != hipSuccess) return e;
-    snap_.push_back({j, steps});
-  }
-  if (snap_.empty()) return hipSuccess;
+  b1_.clock = clock_;
+  if ((e = launch_b_snap(b1_, 0, snap_host_, side_)) != hipSuccess) return e;
+  if ((e = launch_b_snap(b1_, 1, snap_host_, st_)) != hipSuccess) return e;
   if ((e = hipEventRecord(snap_main_, st_)) != hipSuccess) return e;
-  return hipEventRecord(snap_side_, side_);
+  if ((e = hipEventRecord(snap_side_, side_)) != hipSuccess) return e;
+  for (BlockJob *j : p1_) {
+    const int steps = (int)(clock_ - j->h.start_clock);
+    snap_.push_back({steps > 0 ? j : nullptr, steps});
+  }
+  return hipSuccess;
 }
 
 hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
   hipError_t e;
+  if ((e = flush_shifts()) != hipSuccess) return e;
   // pass-1 jobs that were unconverged after their last step at the previous poll
   std::vector<BlockJob *> ending;
   if (!snap_.empty()) {
@@ -584,6 +592,10 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
     }
     snap_.clear();
   }
+  // the next snapshot, of the jobs that go on
+  if ((e = take_snapshot()) != hipSuccess) return e;
+  for (Snap &x : snap_)
+    if (std::find(ending.begin(), ending.end(), x.j) != ending.end()) x.j = nullptr;
   // the shift recurrences of the steps past K may still run on the side
   // stream: they end before the backward solution and a new round's set-up
   if (!ending.empty() && (e = hipStreamSynchronize(side_)) != hipSuccess) return e;
@@ -620,7 +632,6 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
     }
   }
   p1_.swap(keep1);
-  if ((e = take_snapshot()) != hipSuccess) return e;
   std::vector<BlockJob *> keep2;
   for (BlockJob *j : p2_) {
     const int steps = (int)(clock_ - j->h.start_clock);
@@ -644,6 +655,7 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
 
 void BEngine::remove(BlockJob *j) {
   // the caller frees the job next: no launch may still use it
+  (void)flush_shifts();
   (void)hipStreamSynchronize(side_);
   (void)hipStreamSynchronize(st_);
   auto r = [&](std::vector<BlockJob *> &v, bool &dirty) {

@@ -62,8 +62,8 @@ struct BlockJob {
 };
 
 // The per-shift recurrences (b_shift) of step k depend only on A_k, B_k and
-// B_{k+1}, so they run on a second stream and overlap the next steps; that
-// stream has its own copy of the step clock.
+// B_{k+1}, so they run on a second stream and overlap the next steps.  The
+// step clock is the host's: every launch of a step takes it by value.
 class BEngine {
  public:
   explicit BEngine(hipStream_t st) : st_(st) {}
@@ -93,7 +93,11 @@ class BEngine {
   // robust steps of the jobs in v after their gamma (Q_{k+1} from W3)
   hipError_t robust_finish(std::vector<BlockJob *> &v, bool first_pass);
   hipError_t launch_shift(const BBatch &b, int init);
-  // Convergence snapshot: each poll copies the counters of every pass-1 job
+  // The shift recurrences of the steps since the last poll, launched together
+  // behind one event (they read only history entries of their own steps).
+  hipError_t flush_shifts();
+  int npend_ = 0;
+  // Convergence snapshot: each poll writes the counters of every pass-1 job
   // (after its last enqueued step) into pinned host memory without waiting,
   // and decides from the snapshot of the poll before, so the device always
   // has the steps of one poll interval queued.  A job whose snapshot shows
@@ -114,7 +118,6 @@ class BEngine {
   hipStream_t side_ = nullptr;
   hipEvent_t ev_ = nullptr;
   int64_t clock_ = 0;
-  DevBuf d_clock_, d_sclock_;
   std::vector<BlockJob *> p1_, p2_;
   DevBuf dj1_, dt1_, dj2_, dt2_;
   BBatch b1_{}, b2_{};

@@ -145,7 +145,7 @@ struct BBatch {
   const int *toff1, *toff2, *toffr, *toffs;  // tiles of A, A^T, row chunks, shifts
   int total1, total2, totalr, totals;
   int lpmask;  // block widths present: bit 0 -> 16, bit 1 -> 32, bit 2 -> 64
-  const int64_t *clock;
+  int64_t clock;  // engine step clock of the launches (step k of a job: clock - start_clock)
 };
 
 constexpr int kBlockMaxLp = 64;   // widest block of the block Lanczos engine
@@ -179,7 +179,10 @@ hipError_t launch_bs_small2(const BBatch &b, hipStream_t st);
 hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st);
 hipError_t launch_b_backsolve(const BJobDesc &hj, int K, hipStream_t st);
 hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st);
-hipError_t launch_b_tick(int64_t *clock, hipStream_t st);
+// counters of every job of the batch after its newest step into pinned host
+// memory (part 0: active count, on the stream of the shift recurrences;
+// part 1: flags[0..2], on the step stream)
+hipError_t launch_b_snap(const BBatch &b, int part, int *host, hipStream_t st);
 hipError_t launch_b_r0(const double *X, int64_t ld, int Lp, double *B, hipStream_t st);
 hipError_t launch_b_eye(double *Z, int64_t ld, int64_t rows, int cols, hipStream_t st);
 

@@ -74,7 +74,7 @@ __device__ __forceinline__ double pick_tile(const v4d (&x)[4], int tj, int v) {
 
 template <int LP>
 __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__ jobs, int njob,
-                                                    const int *__restrict__ toffs, const int64_t *__restrict__ clock,
+                                                    const int *__restrict__ toffs, int64_t clock,
                                                     int init) {
   constexpr int NT = LP / 16, KS = LP / 4, L2 = LP * LP, SS = LP + 1;
   __shared__ double LB[LP * SS];
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kThreads) void b_shift(const BJobDesc *__restrict__
   const int s = g - toffs[j];
   const int L = J.L;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
-  const int k = (int)(*clock - J.start_clock);
+  const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
   const int64_t hbase = (int64_t)s * (J.Kcap + 1) * L2;
   GLB double2 *__restrict__ Hinv = gp(J.Hinv) + hbase;
@@ -650,10 +650,32 @@ hipError_t launch_b_eye(double *Z, int64_t ld, int64_t rows, int cols, hipStream
   return hipGetLastError();
 }
 
-__global__ void b_tick(int64_t *clock) { *clock += 1; }
+// Convergence snapshot of every job of a batch into host memory (4 ints per
+// job): part 0 the active count after the job's newest step (written by the
+// shift recurrences), part 1 its flags[0..2] (written by the step kernels).
+// Jobs whose first step has not run get -1.
+__global__ void b_snap(const BJobDesc *__restrict__ jobs, int njob, int64_t clock, int part, int *host) {
+  for (int i = threadIdx.x; i < njob; i += blockDim.x) {
+    const BJobDesc &J = jobs[i];
+    const int steps = (int)(clock - J.start_clock);
+    int *h = host + 4 * i;
+    if (steps <= 0) {
+      h[part == 0 ? 0 : 1] = -1;
+      continue;
+    }
+    const int klast = min(steps - 1, J.Kstop - 1);
+    if (part == 0) {
+      h[0] = J.active[klast & 1];
+    } else {
+      h[1] = J.flags[0];
+      h[2] = J.flags[1];
+      h[3] = J.flags[2];
+    }
+  }
+}
 
-hipError_t launch_b_tick(int64_t *clock, hipStream_t st) {
-  hipLaunchKernelGGL(b_tick, dim3(1), dim3(1), 0, st, clock);
+hipError_t launch_b_snap(const BBatch &b, int part, int *host, hipStream_t st) {
+  hipLaunchKernelGGL(b_snap, dim3(1), dim3(64), 0, st, b.jobs, b.njob, b.clock, part, host);
   return hipGetLastError();
 }
 

@@ -123,9 +123,9 @@ __device__ __forceinline__ void tile_any(const GLB int *__restrict__ rp, const G
 
 __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff, int total,
-                                                     const int64_t *__restrict__ clock) {
+                                                     int64_t clock) {
   __shared__ double gsum[kThreads];
-  const int64_t ck = *clock;
+  const int64_t ck = clock;
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const int j = bfind_sp(toff, njob, g);
     const BJobDesc &J = jobs[j];
@@ -139,9 +139,9 @@ __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict_
 
 __global__ __launch_bounds__(kThreads) void b_spmm_at(const BJobDesc *__restrict__ jobs, int njob,
                                                       const int *__restrict__ toff, int total,
-                                                      const int64_t *__restrict__ clock) {
+                                                      int64_t clock) {
   __shared__ double gsum[kThreads];
-  const int64_t ck = *clock;
+  const int64_t ck = clock;
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const int j = bfind_sp(toff, njob, g);
     const BJobDesc &J = jobs[j];

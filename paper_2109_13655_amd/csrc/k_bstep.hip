@@ -234,7 +234,7 @@ enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
 template <int LP>
 __global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__restrict__ jobs, int njob,
                                                       const int *__restrict__ toff,
-                                                      const int64_t *__restrict__ clock) {
+                                                      int64_t clock) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
   __shared__ double Ys[kPanel * kPSMax];
   constexpr int L2 = LP * LP, NT = LP / 16;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__rest
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
   if (J.Lp != LP) return;
-  const int k = (int)(*clock - J.start_clock);
+  const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
   if (gp(J.flags)[1]) return;  // one-pass step
   const int vb = g - toff[j];
@@ -275,14 +275,14 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__rest
 template <int LP>
 __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff,
-                                                     const int64_t *__restrict__ clock) {
+                                                     int64_t clock) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
   constexpr int L2 = LP * LP;
   const int g = blockIdx.x;
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
   if (J.Lp != LP) return;
-  const int k = (int)(*clock - J.start_clock);
+  const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
   const int vb = g - toff[j];
   const int w = threadIdx.x >> 6;
@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
 // 1, ...) through LDS and stored as the workgroup's partial sums.
 template <int LP, int MODE, int NTH>
 __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void bs_tall_rg(
-    const BJobDesc *__restrict__ jobs, int njob, const int *__restrict__ toff, const int64_t *__restrict__ clock,
+    const BJobDesc *__restrict__ jobs, int njob, const int *__restrict__ toff, int64_t clock,
     int grams) {
   constexpr int NT = LP / 16, L2 = LP * LP, NW = NTH / 64;
   constexpr int NF = (MODE == kTallGamma0) ? 0 : NT * NT;       // tiles of Q_k^T X
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
   if (J.Lp != LP) return;
-  const int k = (int)(*clock - J.start_clock);
+  const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
   static_assert(MODE == kTallAlpha || MODE == kTallBeta, "alpha and beta passes");
   const int vb = g - toff[j];
@@ -424,11 +424,11 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
 // m) L2 + e], m < nm, in a fixed order: 8 interleaved partial sums combined
 // in order.  Grid (njob, 2 * 64 * 64 / 32); block = 32 outputs x 8 groups.
 __global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict__ jobs,
-                                                      const int64_t *__restrict__ clock, int m0, int nm, int d0,
+                                                      int64_t clock, int m0, int nm, int d0,
                                                       int second) {
   __shared__ double part[8][32];
   const BJobDesc &J = jobs[blockIdx.x];
-  const int k = (int)(*clock - J.start_clock);
+  const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
   if (second && gp(J.flags)[1]) return;  // one-pass step: no second Gram
   const int L2 = J.Lp * J.Lp;
@@ -787,7 +787,7 @@ __device__ void chol_inv_blocked(double *A, double *X, const double *thr, int *d
 // G3 (upper tiles); scr = R1, R1^-1, T
 template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict__ jobs,
-                                                      const int64_t *__restrict__ clock) {
+                                                      int64_t clock) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
   __shared__ double Pm[LP * SS], Cm[LP * SS], As[LP * SS], Xs[LP * SS];
   __shared__ double Tmp[4 * 16 * 17];
@@ -795,7 +795,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
   if (J.Lp != LP) return;
-  const int k = (int)(*clock - J.start_clock);
+  const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const bool act = w < NT;
@@ -896,7 +896,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
 
 template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict__ jobs,
-                                                      const int64_t *__restrict__ clock) {
+                                                      int64_t clock) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
   __shared__ double As[LP * SS], Xs[LP * SS], Os[LP * SS];
   __shared__ double Tmp[4 * 16 * 17];
@@ -904,7 +904,7 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
   if (J.Lp != LP) return;
-  const int k = (int)(*clock - J.start_clock);
+  const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
   if (gp(J.flags)[1]) return;  // one-pass step: small1 wrote M, N and B
   const int t = threadIdx.x, w = t >> 6;
