@@ -549,7 +549,7 @@ int run_finalize(SolveRun &R) {
   HIPCHK(ctx, ws1.alloc(sizeof(double) * hh_blocked_ws_doubles(LM)));
   HIPCHK(ctx, hh_qr_blocked(Xq.as<double>(), npad, (int)n, LM, tau1.as<double>(), ws1.as<double>(), st));
   // R (LM x LM upper) to the host, R^T back as a column-major LMe x LMe block
-  const int LMe = LM + (LM & 1);
+  const int LMe = jacobi_padded_cols(LM);  // zero columns to a whole number of Jacobi block pairs
   std::vector<double> Rh((size_t)LM * LM);
   XFER(d2h_cols(ctx, Rh.data(), Xq.as<double>(), npad, LM, LM, st));
   std::vector<double> Rt((size_t)LMe * LMe, 0.0), Jm((size_t)LMe * LMe, 0.0);
@@ -566,13 +566,22 @@ int run_finalize(SolveRun &R) {
   // one-sided Jacobi; a pair is rotated while |a_p^T a_q| > sqrt(rows) eps
   // ||a_p|| ||a_q|| (the rounding level of the dot product itself, as in
   // LAPACK's one-sided Jacobi): below it a rotation only moves noise
+  // (square A and V of jacobi_padded_cols columns: pairs of column blocks
+  // in LDS where the size allows, else one launch per column pairing)
   auto jacobi = [&](double *A, int rows, int ncol_even, double *V, int vrows) -> int {
     const double tol = std::sqrt((double)rows) * 2.220446049250313e-16;
+    const int w = jacobi_block_width(ncol_even);
+    const int nsteps = w ? ncol_even / w - 1 : ncol_even - 1;
     for (int sweep = 0; sweep < 60; ++sweep) {
       HIPCHK(ctx, hipMemsetAsync(dcnt.p, 0, sizeof(int), st));
-      for (int s2 = 0; s2 + 1 < ncol_even; ++s2)
-        HIPCHK(ctx, launch_jacobi_step(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol,
-                                       dcnt.as<int>(), st));
+      for (int s2 = 0; s2 < nsteps; ++s2) {
+        if (w)
+          HIPCHK(ctx, launch_jacobi_blk(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol, dcnt.as<int>(),
+                                        st));
+        else
+          HIPCHK(ctx, launch_jacobi_step(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol,
+                                         dcnt.as<int>(), st));
+      }
       int cnt = 0;
       HIPCHK(ctx, hipMemcpyAsync(&cnt, dcnt.p, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPCHK(ctx, hipStreamSynchronize(st));
@@ -614,7 +623,7 @@ int run_finalize(SolveRun &R) {
   }
   double t1 = now_ms();
   // ---- step 4: X = A V~, [U~, B] = qr(X)
-  const int re = r + (r & 1);
+  const int re = jacobi_padded_cols(r);
   DevBuf Vrow, Xrow, Xa, tau2, ws2;
   std::vector<double> Bh;
   if (r > 0) {

@@ -194,6 +194,133 @@ hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, d
   return hipGetLastError();
 }
 
+// Block-pair one-sided Jacobi.  The ncol columns form nb = ncol / W blocks;
+// launch `step` of a sweep pairs the blocks by the same round-robin as the
+// per-column kernel pairs columns, and each workgroup copies its two blocks
+// of A (rows) and V (vrows) to LDS and rotates pairs among their 2W columns
+// there: on step 0 every pair (each block is in exactly one block pair, so
+// every pair within a block is checked once per sweep), on the other steps
+// the W x W pairs across the two blocks.  Each round has W disjoint pairs,
+// one per wave; the wave's sums are butterflies in lane 0's order,
+// broadcast, so every lane takes the same decision.  The rotation and its
+// test are those of k_jacobi.
+template <int W, int RMAX>
+__global__ __launch_bounds__(W * 64) void k_jacobi_blk(double *A, int64_t lda, int rows, int ncol, double *V,
+                                                       int64_t ldv, int vrows, int step, double tol, int *counter) {
+  __shared__ double As[2 * W * RMAX], Vs[2 * W * RMAX];
+  const int nb = ncol / W, n1 = nb - 1;
+  const int b = blockIdx.x;
+  int p, q;
+  if (b == 0) {
+    p = step;
+    q = n1;
+  } else {
+    p = (step + b) % n1;
+    q = (step - b + n1) % n1;
+  }
+  if (p > q) {
+    const int tmp = p;
+    p = q;
+    q = tmp;
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  // local column c: block p for c < W, block q for c >= W
+  auto gcol = [&](int c) { return c < W ? p * W + c : q * W + (c - W); };
+  for (int c = w; c < 2 * W; c += W) {
+    const double *a = A + (int64_t)gcol(c) * lda;
+    const double *v = V + (int64_t)gcol(c) * ldv;
+    for (int i = l; i < rows; i += 64) As[c * RMAX + i] = a[i];
+    for (int i = l; i < vrows; i += 64) Vs[c * RMAX + i] = v[i];
+  }
+  __syncthreads();
+  int rot = 0;
+  const int nrounds = (step == 0) ? 2 * W - 1 : W;
+  for (int r = 0; r < nrounds; ++r) {
+    int x, y;
+    if (step == 0) {  // round-robin over the 2W local columns, 2W - 1 fixed
+      constexpr int m1 = 2 * W - 1;
+      if (w == 0) {
+        x = r;
+        y = m1;
+      } else {
+        x = (r + w) % m1;
+        y = (r - w + m1) % m1;
+      }
+      if (x > y) {
+        const int tmp = x;
+        x = y;
+        y = tmp;
+      }
+    } else {
+      x = w;
+      y = W + (w + r) % W;
+    }
+    double *ax = As + x * RMAX, *ay = As + y * RMAX;
+    double spp = 0.0, sqq = 0.0, spq = 0.0;
+    for (int i = l; i < rows; i += 64) {
+      const double u = ax[i], v = ay[i];
+      spp = fma(u, u, spp);
+      sqq = fma(v, v, sqq);
+      spq = fma(u, v, spq);
+    }
+    const double app = __shfl(wave_sum0(spp), 0);
+    const double aqq = __shfl(wave_sum0(sqq), 0);
+    const double apq = __shfl(wave_sum0(spq), 0);
+    if (apq != 0.0 && fabs(apq) > tol * sqrt(app * aqq)) {
+      const double zeta = (aqq - app) / (2.0 * apq);
+      const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + tt * tt);
+      const double s = c * tt;
+      for (int i = l; i < rows; i += 64) {
+        const double u = ax[i], v = ay[i];
+        ax[i] = c * u - s * v;
+        ay[i] = s * u + c * v;
+      }
+      double *vx = Vs + x * RMAX, *vy = Vs + y * RMAX;
+      for (int i = l; i < vrows; i += 64) {
+        const double u = vx[i], v = vy[i];
+        vx[i] = c * u - s * v;
+        vy[i] = s * u + c * v;
+      }
+      ++rot;
+    }
+    __syncthreads();
+  }
+  for (int c = w; c < 2 * W; c += W) {
+    double *a = A + (int64_t)gcol(c) * lda;
+    double *v = V + (int64_t)gcol(c) * ldv;
+    for (int i = l; i < rows; i += 64) a[i] = As[c * RMAX + i];
+    for (int i = l; i < vrows; i += 64) v[i] = Vs[c * RMAX + i];
+  }
+  if (l == 0 && rot > 0) atomicAdd(counter, rot);
+}
+
+int jacobi_block_width(int n) {
+  if (n <= 256) return 16;
+  if (n <= 512) return 8;
+  return 0;
+}
+
+int jacobi_padded_cols(int n) {
+  const int w = jacobi_block_width(n);
+  if (w == 0) return n + (n & 1);
+  return (n + 2 * w - 1) / (2 * w) * (2 * w);
+}
+
+hipError_t launch_jacobi_blk(double *A, int64_t lda, int rows, int ncol, double *V, int64_t ldv, int vrows, int step,
+                             double tol, int *counter, hipStream_t st) {
+  const int w = jacobi_block_width(ncol);  // the width the columns were padded for
+  if (w == 0 || ncol % (2 * w) != 0 || rows > 4096 / w || vrows > 4096 / w || step < 0 || step >= ncol / w - 1)
+    return hipErrorInvalidValue;
+  if (w == 16)
+    hipLaunchKernelGGL((k_jacobi_blk<16, 256>), dim3(ncol / 32), dim3(1024), 0, st, A, lda, rows, ncol, V, ldv, vrows,
+                       step, tol, counter);
+  else
+    hipLaunchKernelGGL((k_jacobi_blk<8, 512>), dim3(ncol / 16), dim3(512), 0, st, A, lda, rows, ncol, V, ldv, vrows,
+                       step, tol, counter);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------ small helpers
 // dst[c * ldd + r] = src[c * lds + r] for r < rows, c < cols (column-major
 // blocks with different leading dimensions; replaces strided 2-D copies)
