@@ -30,8 +30,8 @@ HBM_PEAK_GBS = 8000.0
 # c2, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy
 # (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 of csrc/k_bspmm.hip) and for the c2 workload.
-SPMM_TRAFFIC_C2 = {"sha256": "a11d536573565865a171af39433ca82881a04271bcda9830f6b99ada4ad50863",
-                   "bytes": (244868.0 * 2.0 + 100000.9 + 250765.6 * 2.0 + 50011.1) * 1024.0}
+SPMM_TRAFFIC_C2 = {"sha256": "a0fe56dfeda4fea741dc0993e30f69eb7540bbb44c2c8d634decb2970d8c5642",
+                   "bytes": (244866.6 * 2.0 + 100001.0 + 250738.6 * 2.0 + 50011.0) * 1024.0}
 
 
 def log(*a):
