@@ -6,11 +6,15 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "block.h"
@@ -513,10 +517,11 @@ int run_after_round(SolveRun &R, bool *more) {
   return CSVD_OK;
 }
 
-// Steps 1-2 (moments) and 3-5 (dense) after the last round.
-int run_finalize(SolveRun &R) {
+// Steps 1-2 (moments) and 3-5 (dense) after the last round, on `stream`
+// (default: the context's stream).
+int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   csvd_ctx *ctx = R.ctx;
-  hipStream_t st = ctx->st;
+  hipStream_t st = stream ? stream : ctx->st;
   const csvd_params &p = R.spec.p;
   const int L = p.L, M = p.M, S = R.spec.S;
   const int64_t m = ctx->m, n = ctx->n;
@@ -1138,6 +1143,69 @@ int csvd_get_transpose(csvd_ctx *ctx, int32_t *rowptr, int32_t *colidx, double *
 // Batched solves and the serving loop.
 extern "C" {
 
+// Worker threads, each with its own stream, that run the epilogues (steps
+// 3-5) of finished batch jobs while the calling thread keeps stepping the
+// others.  An epilogue touches only its own context, and its kernels reduce
+// in a fixed order, so the results do not depend on the stream or thread.
+class FinishPool {
+ public:
+  using Fn = std::function<void(int, hipStream_t)>;
+  FinishPool(int nthreads, Fn fn) : fn_(std::move(fn)) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (int i = 0; i < nthreads; ++i) th_.emplace_back([this, dev] { run(dev); });
+  }
+  ~FinishPool() { finish(); }
+  FinishPool(const FinishPool &) = delete;
+  FinishPool &operator=(const FinishPool &) = delete;
+  void push(int i) {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      q_.push_back(i);
+    }
+    cv_.notify_one();
+  }
+  // runs what is queued, then ends the threads
+  void finish() {
+    {
+      std::lock_guard<std::mutex> g(mu_);
+      done_ = true;
+    }
+    cv_.notify_all();
+    for (std::thread &t : th_)
+      if (t.joinable()) t.join();
+  }
+
+ private:
+  void run(int dev) {
+    (void)hipSetDevice(dev);
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) st = nullptr;
+    for (;;) {
+      int i;
+      {
+        std::unique_lock<std::mutex> g(mu_);
+        cv_.wait(g, [&] { return done_ || !q_.empty(); });
+        if (q_.empty()) break;
+        i = q_.front();
+        q_.pop_front();
+      }
+      fn_(i, st);
+    }
+    if (st) {
+      (void)hipStreamSynchronize(st);
+      (void)hipStreamDestroy(st);
+    }
+  }
+  Fn fn_;
+  std::vector<std::thread> th_;
+  std::mutex mu_;
+  std::condition_variable cv_;
+  std::deque<int> q_;
+  bool done_ = false;
+};
+constexpr int kFinishThreads = 8;
+
 int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, const double *b,
                      const csvd_params *params, const double *const *V_in, int32_t *status) {
   if (count < 1 || !ctxs || !a || !b || !params || !status) return CSVD_EINVAL;
@@ -1149,6 +1217,25 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
   if (use_block(&params[0], ctxs[0]->n)) {
     std::vector<std::unique_ptr<SolveRun>> runs(count);
     std::map<BlockJob *, int> owner;
+    auto finish_job = [&](int i, hipStream_t fst) {
+      SolveRun &R = *runs[i];
+      csvd_ctx *ctx = ctxs[i];
+      int rc;
+      try {
+        rc = run_finalize(R, fst);
+      } catch (...) {
+        rc = set_err(ctx, CSVD_ENOMEM, "host allocation failed in the epilogue");
+      }
+      if (rc) {
+        status[i] = rc;
+      } else {
+        ctx->spec = R.spec;
+        ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
+        status[i] = ctx->last_status;
+      }
+      R.bjob.reset();  // free the basis histories
+    };
+    FinishPool pool(std::min<int>(count, kFinishThreads), finish_job);
     BEngine eng(st);
     if (eng.init() != hipSuccess) return CSVD_EDEVICE;
     for (int i = 0; i < count; ++i) {
@@ -1187,18 +1274,10 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
           if (eng.start(j) != hipSuccess) return CSVD_EDEVICE;
           continue;
         }
-        rc = run_finalize(R);
-        if (rc) {
-          status[i] = rc;
-          continue;
-        }
-        csvd_ctx *ctx = ctxs[i];
-        ctx->spec = R.spec;
-        ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
-        status[i] = ctx->last_status;
-        R.bjob.reset();  // free the basis histories early
+        pool.push(i);  // steps 3-5 on a worker while the others go on
       }
     }
+    pool.finish();
     return CSVD_OK;
   }
   std::vector<std::unique_ptr<SolveRun>> runs(count);
