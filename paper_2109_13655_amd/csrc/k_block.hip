@@ -350,29 +350,35 @@ hipError_t launch_b_shift(const BBatch &b, int init, hipStream_t st) {
 // ------------------------------------------------------ backward solution
 // Y_k = H_k^{-1} (Z_k + B_{k+1}^T Y_{k+1}), k = K-1 .. 0; Y_k overwrites Z_k
 // (columns < L).  The columns are independent: one workgroup per (shift,
-// group of 16 columns).  The recurrence is sequential in k, so the operands
-// of step k - 1 (H^{-1}, B, the Z rows) are loaded into registers while step
-// k computes, and staged in LDS at the start of the next step.
+// group of 16 columns).  Both products of a step are FP64 MFMA tiles: wave w
+// owns rows 16 w .. 16 w + 15 of T = Z_k + B_{k+1}^T Y_{k+1} and of
+// Y_k = H_k^{-1} T, real and imaginary part (A operand from LDS in rows, B
+// operand from the column tiles, accumulator in the MFMA output layout).
+// The recurrence is sequential in k, so the operands of step k - 1 (H^{-1},
+// B, the wave's Z tile) are loaded into registers while step k computes and
+// staged in LDS at the start of the next step.
 constexpr int kBsCols = 16;
 
+template <int LP>
 __global__ __launch_bounds__(kThreads) void b_backsolve(BJobDesc J, int K) {
-  constexpr int IT = kBlockMaxLp * kBlockMaxLp / kThreads, RI = kBlockMaxLp / (kThreads / kBsCols);
-  __shared__ double2 Hs[kBlockMaxLp * kBlockMaxLp];
-  __shared__ double Bs[kBlockMaxLp * kBlockMaxLp];
-  __shared__ double2 Ts[kBlockMaxLp * kBsCols], Yn[kBlockMaxLp * kBsCols];
-  const int ng = (J.L + kBsCols - 1) / kBsCols;
+  constexpr int L2 = LP * LP, SS = LP + 1, TS = kBsCols + 1, KS = LP / 4;
+  constexpr int IT = (L2 + kThreads - 1) / kThreads;
+  __shared__ double Hr[LP * SS], Hi[LP * SS], Bs[LP * SS];
+  __shared__ double Tr[LP * TS], Ti[LP * TS], Yr[LP * TS], Yi[LP * TS];
+  const int L = J.L, ng = (L + kBsCols - 1) / kBsCols;
   const int s = blockIdx.x / ng, cg = blockIdx.x - s * ng;
-  const int Lp = J.Lp, L2 = Lp * Lp, L = J.L;
-  const int t = threadIdx.x, i0 = t >> 4;
-  const int jj = t & (kBsCols - 1), col = cg * kBsCols + jj;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
+  const bool act = w < LP / 16;
+  const int col = cg * kBsCols + rl;  // this lane's column in the MFMA output layout
   const bool live = col < L;
   const int64_t hbase = (int64_t)s * (J.Kcap + 1) * L2;
   const GLB double2 *__restrict__ Hinv = gp(J.Hinv) + hbase;
   GLB double2 *__restrict__ Zh = gp(J.Zh) + hbase;
-  double2 hv[IT], zv[RI], zn[RI];
+  double2 hv[IT], zv[4], zn[4];
   double bv[IT];
-  // operands of step k: H_k^{-1}, B_{k+1} (none for the last step), rows of Z_k
-  auto fetch = [&](int k, double2 (&z)[RI]) {
+  // operands of step k: H_k^{-1}, B_{k+1} (none for the last step) and the
+  // wave's tile of Z_k (rows 16 w + q + 4 v, column col)
+  auto fetch = [&](int k, double2 (&z)[4]) {
     const GLB double2 *__restrict__ Hk = Hinv + (int64_t)k * L2;
     const GLB double *__restrict__ Bk1 = gp(J.Bh) + (int64_t)(k + 1) * L2;
 #pragma unroll
@@ -383,95 +389,148 @@ __global__ __launch_bounds__(kThreads) void b_backsolve(BJobDesc J, int K) {
       bv[it] = (e < L2 && k < K - 1) ? Bk1[e] : 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < RI; ++r) {
-      const int i = i0 + r * (kThreads / kBsCols);
-      z[r] = make_double2(0.0, 0.0);
-      if (i < Lp && live) z[r] = Zh[(int64_t)k * L2 + i * Lp + col];
+    for (int v = 0; v < 4; ++v) {
+      z[v] = make_double2(0.0, 0.0);
+      if (act && live) z[v] = Zh[(int64_t)k * L2 + (16 * w + q + 4 * v) * LP + col];
     }
   };
   if (K > 0) fetch(K - 1, zv);
   for (int k = K - 1; k >= 0; --k) {
-    __syncthreads();  // the previous step is done with Hs, Bs and Ts
+    __syncthreads();  // the previous step is done with Hr, Hi, Bs, Tr, Ti and wrote Yr, Yi
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
       const int e = t + it * kThreads;
       if (e < L2) {
-        Hs[e] = hv[it];
-        Bs[e] = bv[it];
+        const int r = e / LP, c = e - r * LP;
+        Hr[r * SS + c] = hv[it].x;
+        Hi[r * SS + c] = hv[it].y;
+        Bs[r * SS + c] = bv[it];
       }
     }
     __syncthreads();
     if (k > 0) fetch(k - 1, zn);
-    // T = Z_k + B_{k+1}^T Y_{k+1} for this thread's rows; (B^T)[i][c] = B[c][i], B upper
+    if (act) {
+      // T = Z_k + B_{k+1}^T Y_{k+1}; (B^T)(i, c) = B(c, i)
+      v4d Dr = v4d{zv[0].x, zv[1].x, zv[2].x, zv[3].x};
+      v4d Di = v4d{zv[0].y, zv[1].y, zv[2].y, zv[3].y};
+      if (k < K - 1) {
 #pragma unroll
-    for (int r = 0; r < RI; ++r) {
-      const int i = i0 + r * (kThreads / kBsCols);
-      if (i < Lp) {
-        double2 acc = zv[r];
-        if (k < K - 1) {
-          for (int c = 0; c <= i; ++c) {
-            const double b = Bs[c * Lp + i];
-            const double2 y = Yn[c * kBsCols + jj];
-            acc.x = fma(b, y.x, acc.x);
-            acc.y = fma(b, y.y, acc.y);
-          }
+        for (int ks = 0; ks < KS; ++ks) {
+          const int c = 4 * ks + q;
+          const double a = Bs[c * SS + 16 * w + rl];
+          Dr = mfma4b(a, Yr[c * TS + rl], Dr);
+          Di = mfma4b(a, Yi[c * TS + rl], Di);
         }
-        Ts[i * kBsCols + jj] = acc;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        Tr[(16 * w + q + 4 * v) * TS + rl] = Dr[v];
+        Ti[(16 * w + q + 4 * v) * TS + rl] = Di[v];
       }
     }
     __syncthreads();
+    if (act) {
+      // Y_k = H_k^{-1} T: real part Hr Tr - Hi Ti, imaginary part Hr Ti + Hi Tr
+      v4d Dr = v4d{0.0, 0.0, 0.0, 0.0}, Di = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int r = 0; r < RI; ++r) {
-      const int i = i0 + r * (kThreads / kBsCols);
-      if (i < Lp) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int c = 0; c < Lp; ++c) {
-          const double2 p = cmulb(Hs[i * Lp + c], Ts[c * kBsCols + jj]);
-          acc.x += p.x;
-          acc.y += p.y;
-        }
-        Yn[i * kBsCols + jj] = acc;
-        if (live) Zh[(int64_t)k * L2 + i * Lp + col] = acc;
+      for (int ks = 0; ks < KS; ++ks) {
+        const int c = 4 * ks + q;
+        const double ar = Hr[(16 * w + rl) * SS + c], ai = Hi[(16 * w + rl) * SS + c];
+        const double br = Tr[c * TS + rl], bi = Ti[c * TS + rl];
+        Dr = mfma4b(ar, br, Dr);
+        Dr = mfma4b(-ai, bi, Dr);
+        Di = mfma4b(ar, bi, Di);
+        Di = mfma4b(ai, br, Di);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * w + q + 4 * v;
+        Yr[i * TS + rl] = Dr[v];
+        Yi[i * TS + rl] = Di[v];
+        if (live) Zh[(int64_t)k * L2 + i * LP + col] = make_double2(Dr[v], Di[v]);
       }
     }
 #pragma unroll
-    for (int r = 0; r < RI; ++r) zv[r] = zn[r];
+    for (int v = 0; v < 4; ++v) zv[v] = zn[v];
   }
 }
 
 hipError_t launch_b_backsolve(const BJobDesc &hj, int K, hipStream_t st) {
   const int ng = (hj.L + kBsCols - 1) / kBsCols;
-  hipLaunchKernelGGL(b_backsolve, dim3(hj.S * ng), dim3(kThreads), 0, st, hj, K);
+  if (K <= 0) return hipSuccess;
+  switch (hj.Lp) {
+    case 16: hipLaunchKernelGGL(b_backsolve<16>, dim3(hj.S * ng), dim3(kThreads), 0, st, hj, K); break;
+    case 32: hipLaunchKernelGGL(b_backsolve<32>, dim3(hj.S * ng), dim3(kThreads), 0, st, hj, K); break;
+    case 64: hipLaunchKernelGGL(b_backsolve<64>, dim3(hj.S * ng), dim3(kThreads), 0, st, hj, K); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 // F_k(c, kk*L + l) = sum_s 2 Re(c_{s,kk} Y_{s,k}(c, l)), stored column-major
-// per step: F[k][(kk*L + l) * Lp + c].
-__global__ void b_fcoef(BJobDesc J, int K) {
+// per step: F[k][(kk*L + l) * Lp + c].  One workgroup per (step k, group of
+// 16 rows c): each thread reads the entries (c, l) of its kFcPairs pairs for
+// every shift once (consecutive l, coalesced) and keeps up to kFcMom moment
+// sums per pair, summed over the shifts in order; the sums of one kk go out
+// through LDS so that the stores run along c.
+constexpr int kFcPairs = 4, kFcMom = 9;
+
+__global__ __launch_bounds__(kThreads) void b_fcoef(BJobDesc J, int K) {
+  static_assert(16 * kBlockMaxLp <= kThreads * kFcPairs, "pairs per workgroup");
+  __shared__ double Fs[16 * kBlockMaxLp];
   const int Lp = J.Lp, L2 = Lp * Lp, L = J.L, KL = J.Kmom * L;
-  const int64_t total = (int64_t)K * KL * Lp;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e % Lp);
-    const int64_t r = e / Lp;
-    const int oc = (int)(r % KL);
-    const int k = (int)(r / KL);
-    const int kk = oc / L, l = oc - kk * L;
-    double acc = 0.0;
+  const int ncg = Lp / 16;
+  const int k = blockIdx.x / ncg, g = blockIdx.x - k * ncg;
+  const int t = threadIdx.x, np = 16 * L;
+  GLB double *Fk = gp(J.F) + (int64_t)k * KL * Lp;
+  for (int kk0 = 0; kk0 < J.Kmom; kk0 += kFcMom) {
+    const int nk = min(kFcMom, J.Kmom - kk0);
+    double acc[kFcPairs][kFcMom];
+#pragma unroll
+    for (int u = 0; u < kFcPairs; ++u)
+#pragma unroll
+      for (int q = 0; q < kFcMom; ++q) acc[u][q] = 0.0;
     for (int s = 0; s < J.S; ++s) {
-      const double2 y = gp(J.Zh)[((int64_t)s * (J.Kcap + 1) + k) * L2 + c * Lp + l];
-      const double2 cm = gp(J.cmom)[s * J.cstride + kk];
-      acc += 2.0 * (cm.x * y.x - cm.y * y.y);
+      const GLB double2 *__restrict__ Y = gp(J.Zh) + ((int64_t)s * (J.Kcap + 1) + k) * L2;
+      double2 y[kFcPairs];
+#pragma unroll
+      for (int u = 0; u < kFcPairs; ++u) {
+        const int p = t + u * kThreads;
+        y[u] = make_double2(0.0, 0.0);
+        if (p < np) y[u] = Y[(16 * g + p / L) * Lp + p % L];
+      }
+#pragma unroll
+      for (int q = 0; q < kFcMom; ++q) {
+        if (q < nk) {
+          const double2 cm = gp(J.cmom)[s * J.cstride + kk0 + q];
+#pragma unroll
+          for (int u = 0; u < kFcPairs; ++u) acc[u][q] += 2.0 * (cm.x * y[u].x - cm.y * y[u].y);
+        }
+      }
     }
-    gp(J.F)[e] = acc;
+#pragma unroll
+    for (int q = 0; q < kFcMom; ++q) {
+      if (q < nk) {
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kFcPairs; ++u) {
+          const int p = t + u * kThreads;
+          if (p < np) Fs[(p % L) * 16 + p / L] = acc[u][q];
+        }
+        __syncthreads();
+        for (int e = t; e < np; e += kThreads) {
+          const int l = e >> 4, cl = e & 15;
+          Fk[((int64_t)(kk0 + q) * L + l) * Lp + 16 * g + cl] = Fs[e];
+        }
+      }
+    }
   }
 }
 
 hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st) {
-  const int64_t total = (int64_t)K * hj.Kmom * hj.L * hj.Lp;
-  int64_t g = (total + 255) / 256;
-  if (g > 16384) g = 16384;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(b_fcoef, dim3((unsigned)g), dim3(256), 0, st, hj, K);
+  if (K <= 0) return hipSuccess;
+  if (hj.L > hj.Lp || hj.Lp % 16 != 0 || hj.Lp > kBlockMaxLp) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(b_fcoef, dim3((unsigned)(K * (hj.Lp / 16))), dim3(kThreads), 0, st, hj, K);
   return hipGetLastError();
 }
 
