@@ -66,12 +66,11 @@ __device__ __forceinline__ v4d mfma4(double a, double b, v4d c) {
 // c = q * KS + ks (q = l / 16), so each lane reads KS consecutive entries of
 // its row with wide loads.
 template <int LP>
-__device__ __forceinline__ void panel_mm(const GLB double *__restrict__ X, int64_t row0, int64_t n,
-                                         const double *S, v4d (&D)[4]) {
-  constexpr int KS = LP / 4, NT = LP / 16;
+__device__ __forceinline__ void load_rows(const GLB double *__restrict__ X, int64_t row0, int64_t n,
+                                          double (&a)[LP / 4]) {
+  constexpr int KS = LP / 4;
   const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
   const int64_t row = row0 + rl;
-  double a[KS];
 #pragma unroll
   for (int i = 0; i < KS; ++i) a[i] = 0.0;
   if (row < n) {
@@ -83,12 +82,26 @@ __device__ __forceinline__ void panel_mm(const GLB double *__restrict__ X, int64
       a[2 * i + 1] = v.y;
     }
   }
+}
+
+template <int LP>
+__device__ __forceinline__ void rows_mm(const double (&a)[LP / 4], const double *S, v4d (&D)[4]) {
+  constexpr int KS = LP / 4, NT = LP / 16;
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
     const double *sr = S + (q * KS + ks) * kSS + rl;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) D[nt] = mfma4(a[ks], sr[16 * nt], D[nt]);
   }
+}
+
+template <int LP>
+__device__ __forceinline__ void panel_mm(const GLB double *__restrict__ X, int64_t row0, int64_t n,
+                                         const double *S, v4d (&D)[4]) {
+  double a[LP / 4];
+  load_rows<LP>(X, row0, n, a);
+  rows_mm<LP>(a, S, D);
 }
 
 // element (row0 + l/16 + 4v, 16 nt + l%16) of a row-major n x Lp block
