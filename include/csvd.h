@@ -92,7 +92,7 @@ typedef struct {
 enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
 
 /* Fills *p with the paper's defaults: L=16, M=8, N=32, ell=1, delta=1e-20,
- * alpha=0.1, PLAIN, FP64, solve_rtol=1e-11, max_iters=1000000,
+ * alpha=0.1, PLAIN, FP64, solve_rtol=1e-10, max_iters=1000000,
  * spurious_eps=1e-12, seed=2109, norm_a=0, window=0, check_solves=0,
  * solver=CSVD_SOLVER_AUTO, keep_basis=1, cholqr_passes=0. */
 int csvd_params_default(csvd_params *p);

@@ -867,7 +867,7 @@ int csvd_params_default(csvd_params *p) {
   p->alpha = 0.1;
   p->transform = CSVD_PLAIN;
   p->precision = CSVD_FP64;
-  p->solve_rtol = 1e-11;
+  p->solve_rtol = 1e-10;
   p->max_iters = 1000000;
   p->spurious_eps = 1e-12;
   p->seed = 2109;

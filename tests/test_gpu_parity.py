@@ -474,7 +474,9 @@ def test_seeded_vin_uses_counter_generator():
     I = _small_problem()
     ctx = make_ctx(I)
     try:
-        p = cs.csvd_params_default(L=4, M=2, N=16, seed=12345)
+        # the two starting blocks may differ in the last bit, so the moments
+        # agree to about the solve tolerance: fix it well below the bound
+        p = cs.csvd_params_default(L=4, M=2, N=16, seed=12345, solve_rtol=1e-13)
         cs.csvd_solve_interval(ctx, I.a, I.b, p, None)
         S_a = cs.csvd_get_moment(ctx, 0, I.n, 4)
         V = synth.splitmix_normal(12345, I.n, 4)
