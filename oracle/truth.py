@@ -45,6 +45,32 @@ def triplet_residuals(A, sigma, U, V, normA=None):
     return np.maximum(r1, r2) / normA
 
 
+def sparse_triplet_residuals(rowptr, colidx, vals, m, n, sigma, U, V, normA):
+    """The residuals of ``triplet_residuals`` where no dense copy of A fits:
+    A V and A^T U are taken with a CSR library product (scipy.sparse)."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.asarray(vals, dtype=np.float64), np.asarray(colidx), np.asarray(rowptr)), shape=(m, n))
+    r1 = np.linalg.norm(A @ V - U * sigma[None, :], axis=0)
+    r2 = np.linalg.norm(A.T @ U - V * sigma[None, :], axis=0)
+    return np.maximum(r1, r2) / normA
+
+
+def sparse_norm2_lower(rowptr, colidx, vals, m, n, iters=100, seed=0):
+    """A lower bound of ||A||_2 from the power method on A^T A (seeded start):
+    the Rayleigh quotient x^T A^T A x / x^T x never exceeds ||A||_2^2, so a
+    residual divided by this bound is not understated."""
+    import scipy.sparse as sp
+    A = sp.csr_matrix((np.asarray(vals, dtype=np.float64), np.asarray(colidx), np.asarray(rowptr)), shape=(m, n))
+    x = np.random.default_rng(seed).standard_normal(n)
+    lam = 0.0
+    for _ in range(iters):
+        x /= np.linalg.norm(x)
+        y = A.T @ (A @ x)
+        lam = max(lam, float(x @ y))
+        x = y
+    return float(np.sqrt(lam))
+
+
 def strict_count(s, a, b, band):
     """Number of sigma strictly inside (a + band, b - band) and the number in
     the edge bands [a - band, a + band] and [b - band, b + band]."""

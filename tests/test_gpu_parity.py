@@ -584,3 +584,40 @@ def test_dense_gemm_mfma(R, N, K):
         B = np.zeros((K, N)); B[k, j] = 3.0
         Cm = cs.csvd_dense_gemm(A, B)
         assert Cm[i, j] == 6.0 and np.count_nonzero(Cm) == 1
+
+
+# ------------------------------------------------------------ full size
+
+def test_c2_full_size_certificate():
+    """The headline workload at full size (2e5 x 1e5, 10^6 nonzeros, L = 64,
+    M = 8, N = 32, the bench's parameters and starting block).  No oracle
+    solve fits here, so the oracle certifies the GPU's triplets: residuals
+    from host sparse products (checked on sampled rows against the row-by-row
+    definition) over a lower bound of ||A||_2, orthonormal U and V, every
+    value in [a, b]."""
+    import bench
+    W = bench.workload("c2")
+    I = W["I"]
+    say("c2 full size: m", I.m, "n", I.n, "nnz", I.nnz, "interval", W["a"], W["b"])
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=W["L"], M=W["M"], N=W["N"], ell=W["ell"], norm_a=W["norm_a"])
+        st = cs.csvd_solve_interval(ctx, W["a"], W["b"], p, synth.v_in(I.n, W["L"], 2, 0))
+        info = cs.csvd_get_info(ctx)
+        say("status", st, "block steps", info.iterations, "t_hat", info.t_hat)
+        assert st == cs.CSVD_OK and info.converged
+        sig, U, V, r = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    t = sig.size
+    assert t >= 32
+    assert np.all(np.diff(sig) >= 0) and sig[0] >= W["a"] and sig[-1] <= W["b"]
+    nA = truth.sparse_norm2_lower(I.rowptr, I.colidx, I.vals, I.m, I.n, iters=60)
+    res = truth.sparse_triplet_residuals(I.rowptr, I.colidx, I.vals, I.m, I.n, sig, U, V, nA)
+    say("oracle certificate: max residual", res.max(), "reported", r.max())
+    assert res.max() <= 1e-8
+    rows = np.random.default_rng(5).choice(I.m, 64, replace=False)
+    AV = sparse.product_rows(I.rowptr, I.colidx, I.vals, V, rows)
+    np.testing.assert_allclose(AV, U[rows] * sig[None, :], rtol=0, atol=1e-8 * nA)
+    assert np.abs(U.T @ U - np.eye(t)).max() <= 1e-10
+    assert np.abs(V.T @ V - np.eye(t)).max() <= 1e-10

@@ -311,3 +311,37 @@ def test_model_counts_match_paper():
     assert strict == 39 and edge == 2   # 41 in the closed interval; paper says 40
     assert abs(I1.sigma.min() - g1["sigma_first"]) < 1e-15
     assert abs(np.log10(I2.sigma.min()) - g2["log10_first"]) < 1e-12
+
+
+def test_sparse_residual_certificate_matches_dense_definition():
+    """The sparse certificate against the dense residuals on exact SVD
+    triplets (both at rounding level), and a known answer: scaling v_i by
+    (1 + e) makes both residuals of triplet i exactly e sigma_i ||v_i|| = e
+    sigma_i, divided by ||A||_2 (a dropped term, a sign or a transposed
+    operand breaks one of these)."""
+    I = synth.random_sparse(300, 200, 5, config=91)
+    Ad = I.dense()
+    Uf, s, Vt = np.linalg.svd(Ad, full_matrices=False)
+    sel = np.arange(40, 52)
+    sig, U, V = s[sel], Uf[:, sel], Vt.T[:, sel].copy()
+    nA = truth.norm2(Ad)
+    rs = truth.sparse_triplet_residuals(I.rowptr, I.colidx, I.vals, I.m, I.n, sig, U, V, nA)
+    rd = truth.triplet_residuals(Ad, sig, U, V, nA)
+    assert rs.max() <= 1e-13 and rd.max() <= 1e-13
+    eps = 1e-6
+    V[:, 3] *= 1.0 + eps
+    rs = truth.sparse_triplet_residuals(I.rowptr, I.colidx, I.vals, I.m, I.n, sig, U, V, nA)
+    rd = truth.triplet_residuals(Ad, sig, U, V, nA)
+    np.testing.assert_allclose(rs[3], eps * sig[3] / nA, rtol=1e-6)
+    np.testing.assert_allclose(rs, rd, rtol=1e-9, atol=1e-15)
+    assert np.delete(rs, 3).max() <= 1e-13
+
+
+def test_sparse_norm_is_a_lower_bound():
+    """The power-method estimate never exceeds ||A||_2 (LAPACK's SVD) and is
+    close to it after enough steps."""
+    I = synth.random_sparse(300, 200, 5, config=92)
+    nA = truth.norm2(I.dense())
+    est = truth.sparse_norm2_lower(I.rowptr, I.colidx, I.vals, I.m, I.n, iters=400)
+    assert est <= nA * (1 + 1e-14)
+    assert est >= nA * (1 - 1e-4)
