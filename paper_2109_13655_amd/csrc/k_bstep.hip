@@ -436,6 +436,7 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
 // red[(d0 + m) L2 + e] = sum over the workgroups vb of gpart[(vb * 2 + m0 +
 // m) L2 + e], m < nm, in a fixed order: 8 interleaved partial sums combined
 // in order.  Grid (njob, 2 * 64 * 64 / 32); block = 32 outputs x 8 groups.
+// The workgroup count of the tall kernels is at most kBlockMaxVB.
 __global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict__ jobs,
                                                       int64_t clock, int m0, int nm, int d0,
                                                       int second) {
@@ -449,10 +450,18 @@ __global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict
   const int t = threadIdx.x, grp = t >> 5;
   const int o = blockIdx.y * 32 + (t & 31);
   const GLB double *__restrict__ P = gp(J.gpart) + (int64_t)m0 * L2;
+  // all of this thread's partials (workgroups grp, grp + 8, ...) are loaded
+  // at once, then added in that order (past nvb they are zeros)
+  constexpr int kPer = kBlockMaxVB / 8;
+  double v[kPer];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    const int vb = grp + 8 * i;
+    v[i] = (vb < J.nvb) ? P[(int64_t)vb * 2 * L2 + o] : 0.0;
+  }
   double s = 0.0;
-  // loads of eight partials in flight, added in order
-#pragma unroll 8
-  for (int vb = grp; vb < J.nvb; vb += 8) s += P[(int64_t)vb * 2 * L2 + o];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) s += v[i];
   part[grp][t & 31] = s;
   __syncthreads();
   if (grp == 0) {
