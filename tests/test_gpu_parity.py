@@ -604,8 +604,12 @@ def test_c2_full_size_certificate():
         p = cs.csvd_params_default(L=W["L"], M=W["M"], N=W["N"], ell=W["ell"], norm_a=W["norm_a"])
         st = cs.csvd_solve_interval(ctx, W["a"], W["b"], p, synth.v_in(I.n, W["L"], 2, 0))
         info = cs.csvd_get_info(ctx)
-        say("status", st, "block steps", info.iterations, "t_hat", info.t_hat)
+        say("status", st, "block steps", info.iterations, "t_hat", info.t_hat, "one-pass steps",
+            info.one_pass_steps, "basis stored", info.basis_stored)
         assert st == cs.CSVD_OK and info.converged
+        # counters of the steps the solution uses (the convergence poll lags
+        # by one interval; the steps run meanwhile are not counted)
+        assert 0 <= info.one_pass_steps <= info.iterations and info.deflated == 0
         sig, U, V, r = cs.csvd_get_triplets(ctx, I.m, I.n)
     finally:
         cs.csvd_destroy(ctx)
