@@ -333,10 +333,11 @@ template <int LP, int MODE, int NTH>
 __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void bs_tall_rg(
     const BJobDesc *__restrict__ jobs, int njob, const int *__restrict__ toff, int64_t clock,
     int grams) {
+  static_assert(MODE == kTallAlpha || MODE == kTallBeta, "alpha and beta passes");
   constexpr int NT = LP / 16, L2 = LP * LP, NW = NTH / 64;
-  constexpr int NF = (MODE == kTallGamma0) ? 0 : NT * NT;       // tiles of Q_k^T X
+  constexpr int NF = NT * NT;                                       // tiles of Q_k^T X
   constexpr int NS = (MODE == kTallAlpha) ? 0 : NT * (NT + 1) / 2;  // upper tiles of X^T X
-  constexpr int NA = (NF + NS) > 0 ? NF + NS : 1;
+  constexpr int NA = NF + NS;
   __shared__ double SM[2 * LP * kSS];
   double *S1 = SM, *S2 = SM + LP * kSS;
   const int g = blockIdx.x;
@@ -345,7 +346,6 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
   if (J.Lp != LP) return;
   const int k = (int)(clock - J.start_clock);
   if (k >= J.Kstop) return;
-  static_assert(MODE == kTallAlpha || MODE == kTallBeta, "alpha and beta passes");
   const int vb = g - toff[j];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const int64_t n = J.n;
