@@ -135,6 +135,30 @@ def test_block_moments_match_oracle(transform, L, small):
         cs.csvd_destroy(ctx)
 
 
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_SINGLE, cs.CSVD_SOLVER_BLOCK])
+def test_interval_from_zero(solver):
+    """a = 0 (allowed for the plain form): the 34 smallest singular values of
+    a Givens-wrapped diagonal (exact values known), against the exact values
+    and the oracle's dense residuals.  The shifts then lie within 2.5e-3 of
+    the origin with imaginary parts near 1.3e-4."""
+    sig = np.linspace(0.02, 1.0, 1100)
+    I = synth.givens_known(1300, 1100, sigma=sig, nrot=3000, config=93, a=0.0, b=0.05)
+    exact = np.sort(I.sigma[(I.sigma >= 0.0) & (I.sigma <= 0.05)])
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=16, M=8, N=32, solve_rtol=1e-12, solver=solver)
+        st = cs.csvd_solve_interval(ctx, 0.0, 0.05, p, synth.v_in(I.n, 16, 93))
+        info = cs.csvd_get_info(ctx)
+        s, U, V, r = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    say("interval [0, 0.05]: solver", info.solver, "steps", info.iterations, "t_hat", s.size, "exact", exact.size)
+    assert st == cs.CSVD_OK and s.size == exact.size == 34
+    np.testing.assert_allclose(s, exact, rtol=1e-9)
+    res = truth.triplet_residuals(I, s, U, V, normA=1.0)
+    assert res.max() <= 1e-8
+
+
 def test_block_and_single_solvers_agree():
     """Both solvers give the same triplets on the same problem."""
     I = _mid_problem()
