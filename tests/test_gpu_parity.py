@@ -159,6 +159,43 @@ def test_interval_from_zero(solver):
     assert res.max() <= 1e-8
 
 
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_SINGLE, cs.CSVD_SOLVER_BLOCK])
+def test_top_of_spectrum_and_multiple_value(solver):
+    """Two degenerate intervals on a Givens-wrapped diagonal with exact
+    values, ends at midpoints between neighbouring values: one ends half a
+    spacing past sigma_max = 1 (the 10 largest values), the other holds 0.5 with
+    multiplicity 4 and one neighbour on each side.  A multiple value has no
+    unique vectors, so its four triplets are compared by the principal angles
+    between the computed and the exact subspaces."""
+    sig = np.linspace(0.02, 1.0, 1100)
+    sig[540:544] = 0.5  # multiplicity 4
+    sig = np.sort(sig)[::-1]
+    I = synth.givens_known(1300, 1100, sigma=sig, nrot=3000, config=94, a=0.98, b=1.5)
+    so = np.sort(I.sigma)
+    i5 = int(np.searchsorted(so, 0.5))  # first copy of 0.5
+    top = (0.5 * (so[-11] + so[-10]), so[-1] + 0.5 * (so[-1] - so[-2]))
+    mult = (0.5 * (so[i5 - 2] + so[i5 - 1]), 0.5 * (so[i5 + 4] + so[i5 + 5]))
+    for (a, b), want in ((top, 10), (mult, 6)):
+        exact = np.sort(I.sigma[(I.sigma >= a) & (I.sigma <= b)])
+        ctx = make_ctx(I)
+        try:
+            p = cs.csvd_params_default(L=16, M=8, N=32, solve_rtol=1e-12, solver=solver)
+            st = cs.csvd_solve_interval(ctx, a, b, p, synth.v_in(I.n, 16, 94))
+            s, U, V, r = cs.csvd_get_triplets(ctx, I.m, I.n)
+        finally:
+            cs.csvd_destroy(ctx)
+        say("interval", a, b, "solver", solver, "t_hat", s.size, "exact", exact.size)
+        assert st == cs.CSVD_OK and s.size == exact.size == want
+        np.testing.assert_allclose(s, exact, rtol=1e-9)
+        assert truth.triplet_residuals(I, s, U, V, normA=1.0).max() <= 1e-8
+        if want == 6:
+            sel = np.nonzero(np.abs(I.sigma - 0.5) < 1e-12)[0]
+            mine = np.nonzero(np.abs(s - 0.5) < 1e-9)[0]
+            assert sel.size == mine.size == 4
+            assert truth.subspace_gap(V[:, mine], I.V[:, sel]) <= 1e-7
+            assert truth.subspace_gap(U[:, mine], I.U[:, sel]) <= 1e-7
+
+
 def test_block_and_single_solvers_agree():
     """Both solvers give the same triplets on the same problem."""
     I = _mid_problem()
