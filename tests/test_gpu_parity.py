@@ -589,6 +589,39 @@ def test_batch_equals_solo_bitwise(solver):
             cs.csvd_destroy(c)
 
 
+def test_batch_mixed_block_widths_bitwise():
+    """A block batch of widths 16, 32 and 64 (L = 8, 24, 40): every step runs
+    each width's kernels on its jobs, and the epilogues of finished jobs run
+    on worker threads; each result equals the job's solo solve bit for bit."""
+    specs = [(2200, 1100, 8), (4200, 2100, 24), (8400, 4200, 40)]
+    probs = []
+    for i, (m, n, L) in enumerate(specs):
+        I = synth.random_sparse(m, n, 8, config=95, instance=i)
+        a, b, _, _ = synth.interval_from_sample(m, n, 8, 6, scale=max(1, n // 1000), config=95)
+        probs.append((I, a, b, L))
+    params = [cs.csvd_params_default(L=L, M=4, N=16, solver=cs.CSVD_SOLVER_BLOCK) for _, _, _, L in probs]
+    vins = [synth.v_in(I.n, L, 12, i) for i, (I, _, _, L) in enumerate(probs)]
+    ctxs = [make_ctx(I) for I, _, _, _ in probs]
+    try:
+        solo = []
+        for (I, a, b, L), c, p, V in zip(probs, ctxs, params, vins):
+            st = cs.csvd_solve_interval(c, a, b, p, V)
+            info = cs.csvd_get_info(c)
+            say("solo n", I.n, "L", L, "Lp", info.L_padded, "steps", info.iterations, "t_hat", info.t_hat)
+            assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK
+            solo.append(cs.csvd_get_triplets(c, I.m, I.n))
+        st = cs.csvd_solve_batch(ctxs, [a for _, a, _, _ in probs], [b for _, _, b, _ in probs], params, vins)
+        assert all(s == cs.CSVD_OK for s in st)
+        for (I, _, _, _), c, ref in zip(probs, ctxs, solo):
+            got = cs.csvd_get_triplets(c, I.m, I.n)
+            assert got[0].size >= 1
+            for x, y in zip(got, ref):
+                assert np.array_equal(x, y)
+    finally:
+        for c in ctxs:
+            cs.csvd_destroy(c)
+
+
 @pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_SINGLE, cs.CSVD_SOLVER_BLOCK])
 def test_server_results_match_solo_and_cancel(solver):
     probs = _three_problems()
