@@ -194,6 +194,7 @@ hipError_t BlockJob::set_ring(hipStream_t st) {
 }
 
 bool BlockJob::grow_store(int kneed, hipStream_t st) {
+  if (store_cap > 0 && kneed >= store_cap) return false;  // blocks 0 .. kneed would pass the cap
   const size_t bytes = sizeof(double) * (size_t)kStoreChunk * h.n * h.Lp;
   bool changed = false;
   while ((int64_t)chunks.size() * kStoreChunk <= kneed) {

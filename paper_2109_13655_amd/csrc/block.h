@@ -29,6 +29,7 @@ struct BlockJob {
   std::vector<double *> qtab;                  // host copy of the basis table
   std::vector<std::unique_ptr<DevBuf>> chunks;  // stored basis, kStoreChunk blocks each
   bool want_store = true;  // try store mode (the server keeps the ring: its budget covers the job only)
+  int store_cap = 0;       // most basis blocks to store (0: as device memory allows)
   bool store = false;      // store mode active for the current pass 1
   bool stored_last = false;  // the last round's moments came from a stored basis
   int pass = 0;            // 0 idle, 1 building the basis, 2 accumulating moments, 3 done

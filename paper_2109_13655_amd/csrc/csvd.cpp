@@ -208,7 +208,7 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
     return set_err(ctx, CSVD_EINVAL, "solver must be CSVD_SOLVER_AUTO, CSVD_SOLVER_BLOCK or CSVD_SOLVER_SINGLE");
   if (p->solver == CSVD_SOLVER_BLOCK && (pad_L(p->L) > kBlockMaxLp || p->precision != CSVD_FP64))
     return set_err(ctx, CSVD_EINVAL, "the block solver needs L <= 64 and CSVD_FP64");
-  if (p->keep_basis != 0 && p->keep_basis != 1) return set_err(ctx, CSVD_EINVAL, "keep_basis must be 0 or 1");
+  if (p->keep_basis < 0) return set_err(ctx, CSVD_EINVAL, "keep_basis must be >= 0");
   if (p->cholqr_passes != 0 && p->cholqr_passes != 2)
     return set_err(ctx, CSVD_EINVAL, "cholqr_passes must be 0 or 2");
   return CSVD_OK;
@@ -374,6 +374,7 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
                                M + 1, ctx->st));
     R.bjob->h.Kmom = Kmom;
     R.bjob->want_store = (p->keep_basis != 0);
+    R.bjob->store_cap = (p->keep_basis >= 2) ? p->keep_basis : 0;
     R.bjob->h.onepass_rho = (p->cholqr_passes == 2) ? 0.0 : kOnePassRho;
     // the deflation test of the basis is relative to ||A^T A||
     double na = p->norm_a;
