@@ -201,12 +201,13 @@ hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, d
 // there: on step 0 every pair (each block is in exactly one block pair, so
 // every pair within a block is checked once per sweep), on the other steps
 // the W x W pairs across the two blocks.  Each round has W disjoint pairs,
-// one per wave; the wave's sums are butterflies in lane 0's order,
-// broadcast, so every lane takes the same decision.  The rotation and its
+// one per wave; the wave's sums are xor butterflies.  The rotation and its
 // test are those of k_jacobi.
 template <int W, int RMAX>
 __global__ __launch_bounds__(W * 64) void k_jacobi_blk(double *A, int64_t lda, int rows, int ncol, double *V,
                                                        int64_t ldv, int vrows, int step, double tol, int *counter) {
+  static_assert(RMAX % 64 == 0, "whole rows per lane");
+  constexpr int KR = RMAX / 64;  // rows per lane
   __shared__ double As[2 * W * RMAX], Vs[2 * W * RMAX];
   const int nb = ncol / W, n1 = nb - 1;
   const int b = blockIdx.x;
@@ -226,11 +227,29 @@ __global__ __launch_bounds__(W * 64) void k_jacobi_blk(double *A, int64_t lda, i
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   // local column c: block p for c < W, block q for c >= W
   auto gcol = [&](int c) { return c < W ? p * W + c : q * W + (c - W); };
-  for (int c = w; c < 2 * W; c += W) {
-    const double *a = A + (int64_t)gcol(c) * lda;
-    const double *v = V + (int64_t)gcol(c) * ldv;
-    for (int i = l; i < rows; i += 64) As[c * RMAX + i] = a[i];
-    for (int i = l; i < vrows; i += 64) Vs[c * RMAX + i] = v[i];
+  // each wave copies columns w and w + W of A and V: every load of the wave
+  // is issued before the first LDS store
+  {
+    double ta[2][KR], tv[2][KR];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double *a = A + (int64_t)gcol(w + h * W) * lda;
+      const double *v = V + (int64_t)gcol(w + h * W) * ldv;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = l + 64 * k;
+        ta[h][k] = i < rows ? a[i] : 0.0;
+        tv[h][k] = i < vrows ? v[i] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = l + 64 * k;
+        if (i < rows) As[(w + h * W) * RMAX + i] = ta[h][k];
+        if (i < vrows) Vs[(w + h * W) * RMAX + i] = tv[h][k];
+      }
   }
   __syncthreads();
   int rot = 0;
@@ -255,42 +274,65 @@ __global__ __launch_bounds__(W * 64) void k_jacobi_blk(double *A, int64_t lda, i
       x = w;
       y = W + (w + r) % W;
     }
+    // the pair's rows stay in registers from the sums to the rotation; rows
+    // past `rows` read as zero and add nothing (the sums never hold -0)
     double *ax = As + x * RMAX, *ay = As + y * RMAX;
-    double spp = 0.0, sqq = 0.0, spq = 0.0;
-    for (int i = l; i < rows; i += 64) {
-      const double u = ax[i], v = ay[i];
-      spp = fma(u, u, spp);
-      sqq = fma(v, v, sqq);
-      spq = fma(u, v, spq);
+    double u[KR], v[KR];
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = l + 64 * k;
+      u[k] = i < rows ? ax[i] : 0.0;
+      v[k] = i < rows ? ay[i] : 0.0;
     }
-    const double app = __shfl(wave_sum0(spp), 0);
-    const double aqq = __shfl(wave_sum0(sqq), 0);
-    const double apq = __shfl(wave_sum0(spq), 0);
+    double spp = 0.0, sqq = 0.0, spq = 0.0;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      spp = fma(u[k], u[k], spp);
+      sqq = fma(v[k], v[k], sqq);
+      spq = fma(u[k], v[k], spq);
+    }
+    // after the xor butterflies every lane holds the same sums (addition
+    // commutes), so all lanes take the same decision
+    const double app = wave_sum0(spp);
+    const double aqq = wave_sum0(sqq);
+    const double apq = wave_sum0(spq);
     if (apq != 0.0 && fabs(apq) > tol * sqrt(app * aqq)) {
       const double zeta = (aqq - app) / (2.0 * apq);
       const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double c = 1.0 / sqrt(1.0 + tt * tt);
       const double s = c * tt;
-      for (int i = l; i < rows; i += 64) {
-        const double u = ax[i], v = ay[i];
-        ax[i] = c * u - s * v;
-        ay[i] = s * u + c * v;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = l + 64 * k;
+        if (i < rows) {
+          ax[i] = c * u[k] - s * v[k];
+          ay[i] = s * u[k] + c * v[k];
+        }
       }
       double *vx = Vs + x * RMAX, *vy = Vs + y * RMAX;
-      for (int i = l; i < vrows; i += 64) {
-        const double u = vx[i], v = vy[i];
-        vx[i] = c * u - s * v;
-        vy[i] = s * u + c * v;
+#pragma unroll
+      for (int k = 0; k < KR; ++k) {
+        const int i = l + 64 * k;
+        if (i < vrows) {
+          const double a = vx[i], b = vy[i];
+          vx[i] = c * a - s * b;
+          vy[i] = s * a + c * b;
+        }
       }
       ++rot;
     }
     __syncthreads();
   }
-  for (int c = w; c < 2 * W; c += W) {
-    double *a = A + (int64_t)gcol(c) * lda;
-    double *v = V + (int64_t)gcol(c) * ldv;
-    for (int i = l; i < rows; i += 64) a[i] = As[c * RMAX + i];
-    for (int i = l; i < vrows; i += 64) v[i] = Vs[c * RMAX + i];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    double *a = A + (int64_t)gcol(w + h * W) * lda;
+    double *v = V + (int64_t)gcol(w + h * W) * ldv;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int i = l + 64 * k;
+      if (i < rows) a[i] = As[(w + h * W) * RMAX + i];
+      if (i < vrows) v[i] = Vs[(w + h * W) * RMAX + i];
+    }
   }
   if (l == 0 && rot > 0) atomicAdd(counter, rot);
 }
