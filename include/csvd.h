@@ -82,9 +82,10 @@ typedef struct {
   int32_t keep_basis;     /* block solver: 1 keeps the whole basis in device memory while */
                           /* it fits (leaving 8 GB free), so the moments need no second   */
                           /* pass; 0 always regenerates it in a second pass; k >= 2 keeps */
-                          /* at most k blocks (in chunks of 64) and, past them, goes on   */
-                          /* with the ring and a second pass.  All give the same          */
-                          /* bits.  Jobs of csvd_server never keep it                     */
+                          /* at most k blocks and, past them, goes on with the ring and a */
+                          /* second pass (memory is taken in chunks of 64 blocks, so up   */
+                          /* to k rounded up to 64).  All give the same bits.  Jobs of    */
+                          /* csvd_server never keep it                                    */
   int32_t cholqr_passes;  /* block solver: 0 (default) orthonormalises a new basis block  */
                           /* with one Cholesky QR pass when the first factor R1 is well   */
                           /* conditioned (||R1||_F ||R1^-1||_F <= 1.5 Lp, no deflated    */

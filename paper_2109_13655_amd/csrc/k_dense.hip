@@ -694,20 +694,37 @@ __global__ __launch_bounds__(256) void k_pf_dots(const double *__restrict__ X, i
   if (t < nc) part[(int64_t)blockIdx.x * kHB + t] = red[t][0] + red[t][1] + red[t][2] + red[t][3];
 }
 
-__global__ __launch_bounds__(64) void k_pf_coef(const double *__restrict__ part, int nb, double *__restrict__ X,
-                                                 int64_t ld, int j, int jend, double *__restrict__ tau,
-                                                 double *__restrict__ coef) {
+constexpr int kPFTile = 64;  // partial rows per LDS tile of pf_coef
+
+__global__ __launch_bounds__(256) void k_pf_coef(const double *__restrict__ part, int nb, double *__restrict__ X,
+                                                  int64_t ld, int j, int jend, double *__restrict__ tau,
+                                                  double *__restrict__ coef) {
   // coef[0] = scale, coef[1] = beta, coef[2 + c] = w for column j + c (c >= 1)
+  constexpr int kPer = kPFTile * kHB / 256;  // partials each thread stages per tile
+  __shared__ double P[kPFTile * kHB];
   __shared__ double T[kHB];
   __shared__ double sh[2];
   const int t = threadIdx.x, nc = jend - j;
-  if (t < nc) {
-    double s = 0.0;
-    // eight partial sums in flight, added in order
-#pragma unroll 8
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * kHB + t];
-    T[t] = s;
+  // the partials of a tile are staged with all loads in flight, then added
+  // in block order (entries of columns >= nc were not written: never read)
+  double s = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += kPFTile) {
+    double v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = t + 256 * u, b = b0 + e / kHB, c = e % kHB;
+      v[u] = (b < nb && c < nc) ? part[(int64_t)b * kHB + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) P[t + 256 * u] = v[u];
+    __syncthreads();
+    if (t < nc) {
+      const int nbt = min(kPFTile, nb - b0);
+      for (int b = 0; b < nbt; ++b) s += P[b * kHB + t];
+    }
+    __syncthreads();
   }
+  if (t < nc) T[t] = s;
   __syncthreads();
   if (t == 0) {
     const double x0 = X[(int64_t)j * ld + j], xn2 = T[0];
@@ -741,7 +758,13 @@ __global__ __launch_bounds__(256) void k_pf_update(double *__restrict__ X, int64
     v = X[(int64_t)j * ld + r] * scale;
     X[(int64_t)j * ld + r] = v;
   }
-  for (int c = 1; c < nc; ++c) X[(int64_t)(j + c) * ld + r] -= coef[2 + c] * v;
+  // the row's entries of columns j+1 .. jend-1 are loaded before the first store
+  double xv[kHB];
+#pragma unroll
+  for (int c = 1; c < kHB; ++c) xv[c] = c < nc ? X[(int64_t)(j + c) * ld + r] : 0.0;
+#pragma unroll
+  for (int c = 1; c < kHB; ++c)
+    if (c < nc) X[(int64_t)(j + c) * ld + r] = xv[c] - coef[2 + c] * v;
 }
 
 static hipError_t panel_factor(double *X, int64_t ld, int rows, int j0, int jend, double *tau, double *part,
@@ -750,7 +773,7 @@ static hipError_t panel_factor(double *X, int64_t ld, int rows, int j0, int jend
     const int64_t below = (int64_t)rows - j - 1;
     const int nb = (int)std::max<int64_t>(1, (below + kPFRows - 1) / kPFRows);
     hipLaunchKernelGGL(k_pf_dots, dim3(nb), dim3(256), 0, st, X, ld, rows, j, jend, part);
-    hipLaunchKernelGGL(k_pf_coef, dim3(1), dim3(64), 0, st, part, nb, X, ld, j, jend, tau, coef);
+    hipLaunchKernelGGL(k_pf_coef, dim3(1), dim3(256), 0, st, part, nb, X, ld, j, jend, tau, coef);
     const int nu = (int)((rows - j + 255) / 256);
     hipLaunchKernelGGL(k_pf_update, dim3(nu), dim3(256), 0, st, X, ld, rows, j, jend, coef);
     hipError_t e = hipGetLastError();
