@@ -30,8 +30,13 @@ HBM_PEAK_GBS = 8000.0
 # c2, from rocprofv3 FETCH_SIZE and WRITE_SIZE runs scaled by a 1 GiB copy
 # (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 of csrc/k_bspmm.hip) and for the c2 workload.
-SPMM_TRAFFIC_C2 = {"sha256": "a0fe56dfeda4fea741dc0993e30f69eb7540bbb44c2c8d634decb2970d8c5642",
+SPMM_TRAFFIC_C2 = {"source": "k_bspmm.hip",
+                   "sha256": "a0fe56dfeda4fea741dc0993e30f69eb7540bbb44c2c8d634decb2970d8c5642",
                    "bytes": (244866.6 * 2.0 + 100001.0 + 250738.6 * 2.0 + 50011.0) * 1024.0}
+# the same for one full 16-block launch of b_moments (sha256 of csrc/k_block.hip)
+MOMENTS_TRAFFIC_C2 = {"source": "k_block.hip",
+                      "sha256": "c1f4a3a2ee20fa400a1a2dd8495f3da2f193a70e94fd3cb323fa7533e59a8837",
+                      "bytes": (2750987.7 * 2.0 + 450000.0) * 1024.0}
 
 
 def log(*a):
@@ -86,16 +91,18 @@ def cpu_baseline(W, iters_gpu, seconds=15.0):
                        f"{W.get('ell', 1)} (extrapolated); OMP_NUM_THREADS={threads}")}
 
 
-def spmm_traffic(config):
+def profiled_traffic(config, entry):
+    """Counter-measured HBM bytes per launch, or None when the workload is not
+    c2 or the kernel source differs from the one the counters were taken on."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2109_13655_amd", "csrc", "k_bspmm.hip")
+    src = os.path.join(ROOT, "paper_2109_13655_amd", "csrc", entry["source"])
     try:
         h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except OSError:
         return None
-    if config != "c2" or h != SPMM_TRAFFIC_C2["sha256"]:
+    if config != "c2" or h != entry["sha256"]:
         return None
-    return SPMM_TRAFFIC_C2["bytes"]
+    return entry["bytes"]
 
 
 def roofline(info, config):
@@ -112,13 +119,13 @@ def roofline(info, config):
         b, t = info.spmm_at_bytes, info.spmm_at_ms
         name = "k2_spmm_lanczos (A^T product + Lanczos update + window store)"
     ach = b / (t * 1e-3) / 1e9 if t > 0 else None
-    traffic = spmm_traffic(config) if info.solver == 1 else None
+    traffic = profiled_traffic(config, SPMM_TRAFFIC_C2) if info.solver == 1 else None
     return {"bound": "hbm", "kernel": name, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (ach / HBM_PEAK_GBS) if ach else None, "traffic": traffic,
             "bytes_per_launch": b, "avg_launch_ms": t, "samples": int(info.spmm_samples)}
 
 
-def roofline_moments(info, W):
+def roofline_moments(info, W, config):
     """The moment accumulation of the block solver, S += [Q_k0 .. Q_k0+15]
     [F_k0; ..; F_k0+15] on FP64 MFMA: 2 n Lp (M + 1) L flops per basis block,
     16 blocks per launch, timed with HIP events around every full launch."""
@@ -130,7 +137,8 @@ def roofline_moments(info, W):
     flops = 2.0 * I.n * Lp * kmom * W["L"] * 16
     ach = flops / (info.moments_ms * 1e-3) / 1e12
     return {"bound": "mfma", "kernel": "b_moments (S += Q F over 16 basis blocks)", "achieved": ach,
-            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFS, "traffic": None,
+            "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": ach / FP64_MFMA_PEAK_TFS,
+            "traffic": profiled_traffic(config, MOMENTS_TRAFFIC_C2),
             "flops_per_launch": flops, "avg_launch_ms": info.moments_ms}
 
 
@@ -408,7 +416,7 @@ def main():
         "phase_ms": {"solve": info.t_solve_ms, "lowrank": info.t_lowrank_ms, "qr": info.t_qr_ms,
                      "extract": info.t_extract_ms},
         "roofline": roofline(info, args.config),
-        "roofline_moments": roofline_moments(info, W),
+        "roofline_moments": roofline_moments(info, W, args.config),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle COCG sample)")
