@@ -35,8 +35,8 @@ SPMM_TRAFFIC_C2 = {"source": "k_bspmm.hip",
                    "bytes": (244866.6 * 2.0 + 100001.0 + 250738.6 * 2.0 + 50011.0) * 1024.0}
 # the same for one full 16-block launch of b_moments (sha256 of csrc/k_block.hip)
 MOMENTS_TRAFFIC_C2 = {"source": "k_block.hip",
-                      "sha256": "c1f4a3a2ee20fa400a1a2dd8495f3da2f193a70e94fd3cb323fa7533e59a8837",
-                      "bytes": (2750987.7 * 2.0 + 450000.0) * 1024.0}
+                      "sha256": "752f71d8b47b4e831f937d6a1ced1706bf75cb438683d5e95ef2f4cc5cd7daee",
+                      "bytes": (1325056.1 * 2.0 + 450000.0) * 1024.0}
 
 
 def log(*a):

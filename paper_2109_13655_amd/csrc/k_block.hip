@@ -567,8 +567,14 @@ __global__ __launch_bounds__(kThreads, OCC) void b_moments(BJobDesc J, int k0, i
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const int64_t n = J.n;
   const int KL = J.Kmom * J.L;
-  const int64_t rb = (int64_t)blockIdx.x * ROWS;
-  const int col0 = blockIdx.y * COLS;
+  // workgroups go to the 8 XCDs round-robin by id: the column groups of a
+  // row tile are consecutive workgroups of one XCD, so they share its L2
+  // for the basis rows (row tiles padded to a multiple of 8)
+  const int ngrp = (KL + COLS - 1) / COLS;
+  const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+  const int64_t rb = ((int64_t)(j / ngrp) * 8 + xcd) * ROWS;
+  const int col0 = (j % ngrp) * COLS;
+  if (rb >= n) return;
   v4d acc[WR][NTL];
 #pragma unroll
   for (int r = 0; r < WR; ++r)
@@ -669,7 +675,8 @@ hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st) {
   if (T <= 0) return hipSuccess;
   const int KL = hj.Kmom * hj.L;
   constexpr int ROWS = 64 * kMomWR, C = kMomCols;
-  const dim3 g((unsigned)((hj.n + ROWS - 1) / ROWS), (unsigned)((KL + C - 1) / C));
+  const int64_t tiles8 = (hj.n + 8 * ROWS - 1) / (8 * ROWS) * 8;  // row tiles padded to a multiple of 8
+  const dim3 g((unsigned)(tiles8 * ((KL + C - 1) / C)));
   switch (hj.Lp) {
     case 16: hipLaunchKernelGGL((b_moments<16, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
     case 32: hipLaunchKernelGGL((b_moments<32, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
