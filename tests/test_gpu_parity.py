@@ -527,6 +527,12 @@ def test_not_converged_status_and_errors():
         big = cs.csvd_params_default(L=200, M=2)
         with pytest.raises(cs.CsvdError):
             cs.csvd_solve_interval(ctx, I.a, I.b, big)
+        with pytest.raises(cs.CsvdError) as e:
+            cs.csvd_solve_interval(ctx, I.a, I.b, cs.csvd_params_default(L=4, M=2, N=16, keep_basis=-1))
+        assert e.value.code == cs.CSVD_EINVAL
+        # the context stays usable after the rejected calls
+        assert cs.csvd_solve_interval(ctx, I.a, I.b, cs.csvd_params_default(L=4, M=2, N=16, keep_basis=3)) in (
+            cs.CSVD_OK, cs.CSVD_ENOTCONV)
     finally:
         cs.csvd_destroy(ctx)
 
