@@ -677,12 +677,24 @@ __global__ __launch_bounds__(256) void k_pf_dots(const double *__restrict__ X, i
   double acc[kHB];
 #pragma unroll
   for (int c = 0; c < kHB; ++c) acc[c] = 0.0;
-  for (int64_t r = rb + t; r < rb + kPFRows && r < rows; r += 256) {
-    const double x = X[(int64_t)j * ld + r];
+  // both rows of a thread are loaded before the first product (same order
+  // of the products as a row-by-row loop)
+  static_assert(kPFRows == 2 * 256, "two rows per thread");
+  double xr[2], xc[2][kHB];
 #pragma unroll
-    for (int c = 0; c < kHB; ++c)
-      if (c < nc) acc[c] = fma(x, X[(int64_t)(j + c) * ld + r], acc[c]);
+  for (int h = 0; h < 2; ++h) {
+    const int64_t r = rb + t + 256 * h;
+    const bool ok = r < rows;
+    xr[h] = ok ? X[(int64_t)j * ld + r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < kHB; ++c) xc[h][c] = (ok && c < nc) ? X[(int64_t)(j + c) * ld + r] : 0.0;
   }
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    if (rb + t + 256 * h < rows)
+#pragma unroll
+      for (int c = 0; c < kHB; ++c)
+        if (c < nc) acc[c] = fma(xr[h], xc[h][c], acc[c]);
   // fixed-order reduction: within the wave by xor-shuffles, then over waves
 #pragma unroll
   for (int c = 0; c < kHB; ++c) {
