@@ -609,30 +609,29 @@ __global__ __launch_bounds__(256) void k_tmat(const double *__restrict__ G, cons
 // C(r, c) -= sum_i V(r, i) W2(i, c), r >= j0, with W2 = T^T W (trans = 1) or
 // T W; 64 rows x 64 columns per workgroup, C written back in column segments
 // through LDS.
+// W2 = op(T) W (kHB x p2, row-major; op(T) = T^T when trans): the product
+// every row tile of the trailing update applies, formed once per panel
+__global__ __launch_bounds__(256) void k_tw(const double *__restrict__ T, int trans, const double *__restrict__ W,
+                                             int p2, double *__restrict__ W2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)kHB * p2) return;
+  const int i = (int)(e / p2), c = (int)(e - (int64_t)i * p2);
+  double s = 0.0;
+  for (int k = 0; k < kHB; ++k) s = fma(trans ? T[k * kHB + i] : T[i * kHB + k], W[(int64_t)k * p2 + c], s);
+  W2[e] = s;
+}
+
 __global__ __launch_bounds__(256) void k_tu(const double *__restrict__ X, int64_t ld, int j0, int jb, int64_t rows,
-                                             const double *__restrict__ T, int trans, const double *__restrict__ W,
-                                             int p2, double *__restrict__ C, int64_t ldc) {
-  __shared__ double Ts[kHB][kHB + 1];
-  __shared__ double Ws[kHB][64 + 1];
+                                             const double *__restrict__ W2g, int p2, double *__restrict__ C,
+                                             int64_t ldc) {
   __shared__ double W2[kHB][64 + 1];
   __shared__ double Cs[64][65];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const int64_t rb = (int64_t)j0 + (int64_t)blockIdx.x * 64;
   const int col0 = blockIdx.y * 64;
-  for (int e = t; e < kHB * kHB; e += 256) {
-    const int i = e / kHB, k = e % kHB;
-    Ts[i][k] = trans ? T[k * kHB + i] : T[e];
-  }
   for (int e = t; e < kHB * 64; e += 256) {
     const int i = e / 64, c = e % 64;
-    Ws[i][c] = (col0 + c < p2) ? W[(int64_t)i * p2 + col0 + c] : 0.0;
-  }
-  __syncthreads();
-  for (int e = t; e < kHB * 64; e += 256) {
-    const int i = e / 64, c = e % 64;
-    double s = 0.0;
-    for (int k = 0; k < kHB; ++k) s = fma(Ts[i][k], Ws[k][c], s);
-    W2[i][c] = s;
+    W2[i][c] = (col0 + c < p2) ? W2g[(int64_t)i * p2 + col0 + c] : 0.0;
   }
   __syncthreads();
   v4dd acc[4];
@@ -651,10 +650,20 @@ __global__ __launch_bounds__(256) void k_tu(const double *__restrict__ X, int64_
 #pragma unroll
     for (int v = 0; v < 4; ++v) Cs[16 * tj + rl][16 * w + q + 4 * v] = acc[tj][v];
   __syncthreads();
-  for (int e = t; e < 64 * 64; e += 256) {
-    const int c = e >> 6, rr = e & 63;
+  // every load of the tile's C entries is issued before the first store
+  constexpr int NE = 64 * 64 / 256;
+  double cv[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = t + 256 * u, c = e >> 6, rr = e & 63;
     const int64_t row = rb + rr;
-    if (col0 + c < p2 && row < rows) C[(int64_t)(col0 + c) * ldc + row] -= Cs[c][rr];
+    cv[u] = (col0 + c < p2 && row < rows) ? C[(int64_t)(col0 + c) * ldc + row] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = t + 256 * u, c = e >> 6, rr = e & 63;
+    const int64_t row = rb + rr;
+    if (col0 + c < p2 && row < rows) C[(int64_t)(col0 + c) * ldc + row] = cv[u] - Cs[c][rr];
   }
 }
 
@@ -836,8 +845,10 @@ hipError_t hh_qr_blocked(double *X, int64_t ld, int rows, int cols, double *tau,
     if (p2 <= 0) continue;
     double *C = X + (int64_t)c0 * ld;
     if ((e = tall_vtc(X, ld, j0, jb, rows, C, ld, 0, p2, part, W, st)) != hipSuccess) return e;
+    // part is free again after the reduction into W: it holds T^T W
+    hipLaunchKernelGGL(k_tw, dim3((unsigned)(((int64_t)kHB * p2 + 255) / 256)), dim3(256), 0, st, T, 1, W, p2, part);
     const dim3 g((unsigned)((rows - j0 + 63) / 64), (unsigned)((p2 + 63) / 64));
-    hipLaunchKernelGGL(k_tu, g, dim3(256), 0, st, X, ld, j0, jb, (int64_t)rows, T, 1, W, p2, C, ld);
+    hipLaunchKernelGGL(k_tu, g, dim3(256), 0, st, X, ld, j0, jb, (int64_t)rows, part, p2, C, ld);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -857,8 +868,10 @@ hipError_t hh_apply_blocked(const double *X, int64_t ld, int rows, int nref, con
     const int j0 = pi * kHB, jb = std::min(kHB, nref - j0);
     const double *T = Tall + (size_t)pi * kHB * kHB;
     if ((e = tall_vtc(X, ld, j0, jb, rows, Z, ldz, 0, ncols, part, W, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tw, dim3((unsigned)(((int64_t)kHB * ncols + 255) / 256)), dim3(256), 0, st, T, 0, W, ncols,
+                       part);
     const dim3 g((unsigned)((rows - j0 + 63) / 64), (unsigned)((ncols + 63) / 64));
-    hipLaunchKernelGGL(k_tu, g, dim3(256), 0, st, X, ld, j0, jb, (int64_t)rows, T, 0, W, ncols, Z, ldz);
+    hipLaunchKernelGGL(k_tu, g, dim3(256), 0, st, X, ld, j0, jb, (int64_t)rows, part, ncols, Z, ldz);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
