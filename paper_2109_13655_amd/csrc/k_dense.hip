@@ -527,21 +527,30 @@ __global__ __launch_bounds__(256) void k_tg_part(const double *__restrict__ X, i
   // wave w: output tiles (ti, tj) = (w >> 2 ... ): 2 x 4 tiles of 16 x 16 over 4 waves
   v4dd acc[2];
   acc[0] = acc[1] = v4dd{0.0, 0.0, 0.0, 0.0};
+  // thread t stages row t % 64 of the chunk for columns t / 64 + 4 u; the
+  // column index is the same across the wave (scalar addressing)
+  static_assert(kTGChunk == 64, "one row per lane");
+  constexpr int NV = kTGChunk * kHB / 256, NC = kTGChunk * 64 / 256;
+  const int wi = __builtin_amdgcn_readfirstlane(w);
   for (int64_t ch = vb; ch < nchunk; ch += nvb) {
-    const int64_t rb = r0 + ch * kTGChunk;
-    __syncthreads();
-    for (int e = t; e < kTGChunk * kHB; e += 256) {
-      const int i = e / kTGChunk, rr = e % kTGChunk;
-      const int64_t r = rb + rr;
-      Vs[rr][i] = (r < rows) ? vview(X, ld, j0, i, jb, r) : 0.0;
-    }
-    for (int e = t; e < kTGChunk * 64; e += 256) {
-      const int c = e / kTGChunk, rr = e % kTGChunk;
-      const int64_t r = rb + rr;
+    const int64_t r = r0 + ch * kTGChunk + l;
+    const bool rok = r < rows;
+    // every load of the chunk is issued before the first LDS store
+    double vv[NV], cc[NC];
+#pragma unroll
+    for (int u = 0; u < NV; ++u) vv[u] = rok ? vview(X, ld, j0, wi + 4 * u, jb, r) : 0.0;
+#pragma unroll
+    for (int u = 0; u < NC; ++u) {
+      const int c = col0 + wi + 4 * u;
       double v = 0.0;
-      if (r < rows && col0 + c < p2) v = cv ? vview(X, ld, j0, col0 + c, jb, r) : C[(int64_t)(col0 + c) * ldc + r];
-      Cs[rr][c] = v;
+      if (rok && c < p2) v = cv ? vview(X, ld, j0, c, jb, r) : C[(int64_t)c * ldc + r];
+      cc[u] = v;
     }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < NV; ++u) Vs[l][wi + 4 * u] = vv[u];
+#pragma unroll
+    for (int u = 0; u < NC; ++u) Cs[l][wi + 4 * u] = cc[u];
     __syncthreads();
 #pragma unroll
     for (int s2 = 0; s2 < 2; ++s2) {
