@@ -20,7 +20,7 @@ krylov      a plain per-shift COCG solver for sizes where dense solves do not
             fit (used for CPU timing samples and moderate-size checks).
 sparse      CSR transpose and row-sampled products by their definitions.
 
-Parity status: every function is pinned by tests in ``tests/test_oracle_*.py``
+Parity status: every function is pinned by tests in ``tests/test_oracle_pins.py``
 against closed forms, invariants or exact spectra; none is "parity unpinned".
 """
 from . import quadrature, method, truth, krylov, sparse  # noqa: F401

@@ -81,9 +81,13 @@ def strict_count(s, a, b, band):
 
 
 def subspace_gap(X, Y):
-    """sin of the largest principal angle between span(X) and span(Y)
-    (both with orthonormal columns)."""
+    """sin of the largest principal angle between span(X) and span(Y), both
+    given by orthonormal columns of the same count: the 2-norm of the part
+    of Y outside span(X), (I - X X^T) Y.  Taking the sine directly (not
+    sqrt(1 - cos^2)) keeps small angles accurate."""
     if X.shape[1] == 0 and Y.shape[1] == 0:
         return 0.0
-    s = np.linalg.svd(X.T @ Y, compute_uv=False)
-    return float(np.sqrt(max(0.0, 1.0 - min(s.min(), 1.0) ** 2)))
+    if X.shape[1] != Y.shape[1]:
+        raise ValueError("subspaces of different dimension")
+    D = Y - X @ (X.T @ Y)
+    return float(np.linalg.norm(D, 2))

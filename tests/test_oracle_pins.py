@@ -345,3 +345,86 @@ def test_sparse_norm_is_a_lower_bound():
     est = truth.sparse_norm2_lower(I.rowptr, I.colidx, I.vals, I.m, I.n, iters=400)
     assert est <= nA * (1 + 1e-14)
     assert est >= nA * (1 - 1e-4)
+
+
+def test_residual_estimate_exp_against_matrix_log():
+    """eq. res_nonlinear, first factor: for Alg. 2 the unscaled estimate
+    ||r~_i|| stands for (1/sigma_i) ||g^-1(A^T A) v_i - g^-1(sigma_i^2) v_i||
+    with g^-1 = log (Sec. 3.4.1).  The matrix logarithm is formed here from
+    the exactly known factors of model problem 2 (log(A^T A) = V diag(2 log
+    sigma) V^T), not from the moments; the two agree to the accuracy of the
+    exp-transformed moment relation on a deliberately small subspace (L = 10,
+    N = 16) whose residuals sit far above rounding.  A missing factor 2 in
+    g^-1(sigma^2), a dropped 1/sigma or the wrong singular vectors of S-hat
+    each break the agreement by orders of magnitude."""
+    I = synth.model_problem(2)
+    out = method.ss_svd(I, I.a, I.b, synth.v_in(I.n, 10, 9), 10, 4, 16, transform=Q.EXP)
+    v, s = out["V"], out["sigma"]
+    assert s.size >= 30
+    logG = (I.V * (2.0 * np.log(I.sigma))) @ I.V.T
+    ref = np.linalg.norm(logG @ v - v * np.log(s ** 2)[None, :], axis=0) / s
+    assert ref.min() > 1e-3  # far above rounding
+    np.testing.assert_allclose(out["resid_est"], ref, rtol=1e-3)
+
+
+def test_nt_mu_reproduces_the_chosen_exact_residual():
+    """eq. res_nonlinear: mu = ||r_i'|| / ||r~_i'|| for one index i' taken from
+    the exact residuals (the oracle takes the largest), so mu ||r~_i'|| equals
+    ||r_i'|| exactly, and mu follows the estimates when every exact residual
+    is scaled by one factor."""
+    I = synth.model_problem(2)
+    out = method.ss_svd(I, I.a, I.b, synth.v_in(I.n, 10, 9), 10, 4, 16, transform=Q.EXP)
+    A = I.dense()
+    exact = np.linalg.norm(A.T @ out["U"] - out["V"] * out["sigma"], axis=0)
+    est = out["resid_est"]
+    mu = method.nt_mu(est, exact)
+    i = int(np.argmax(exact))
+    assert mu * est[i] == pytest.approx(exact[i], rel=1e-15)
+    assert method.nt_mu(est, 3.0 * exact) == pytest.approx(3.0 * mu, rel=1e-15)
+    assert method.nt_mu(2.0 * est, exact) == pytest.approx(0.5 * mu, rel=1e-15)
+
+
+def test_product_rows_against_dense_product():
+    """oracle.sparse.product_rows is (A X)[rows] by definition: checked
+    against the dense product on a matrix with empty rows, for all rows in
+    order and for a shuffled sample with repeats."""
+    from oracle import sparse
+    rng = np.random.default_rng(77)
+    m, n, k = 60, 45, 7
+    A = rng.standard_normal((m, n)) * (rng.random((m, n)) < 0.15)
+    A[[0, 13, 59]] = 0.0  # empty rows, including the first and the last
+    rp, ci, va = synth.csr_from_dense(A)
+    assert rp[1] == rp[0] and rp[14] == rp[13] and rp[-1] == rp[-2]
+    X = rng.standard_normal((n, k))
+    ref = A @ X
+    got = sparse.product_rows(rp, ci, va, X, range(m))
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-14 * np.abs(ref).max())
+    assert np.all(got[[0, 13, 59]] == 0.0)
+    rows = np.array([59, 3, 3, 40, 0, 22])
+    np.testing.assert_allclose(sparse.product_rows(rp, ci, va, X, rows), ref[rows], rtol=1e-14,
+                               atol=1e-14 * np.abs(ref).max())
+
+
+def test_subspace_gap_known_principal_angles():
+    """oracle.truth.subspace_gap is sin of the largest principal angle: two
+    subspaces built from one orthonormal basis with known angles (0, theta1,
+    theta2) give sin(max theta); the value does not depend on the bases
+    chosen inside the subspaces; equal subspaces give 0 and orthogonal ones
+    give 1."""
+    rng = np.random.default_rng(78)
+    n, k = 40, 3
+    Qm, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    th1, th2 = 0.3, 1.1
+    X = Qm[:, :k]
+    Y = np.column_stack([Qm[:, 0],
+                         np.cos(th1) * Qm[:, 1] + np.sin(th1) * Qm[:, k],
+                         np.cos(th2) * Qm[:, 2] + np.sin(th2) * Qm[:, k + 1]])
+    assert truth.subspace_gap(X, Y) == pytest.approx(np.sin(th2), rel=1e-13)
+    R1, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    R2, _ = np.linalg.qr(rng.standard_normal((k, k)))
+    assert truth.subspace_gap(X @ R1, Y @ R2) == pytest.approx(np.sin(th2), rel=1e-12)
+    assert truth.subspace_gap(X, X @ R1) <= 1e-14
+    assert truth.subspace_gap(X, Qm[:, k:2 * k]) == pytest.approx(1.0, abs=1e-15)
+    small = 1e-9  # tiny angles are resolved (the sine itself, not sqrt(1 - cos^2))
+    Z = np.column_stack([Qm[:, 0], Qm[:, 1], np.cos(small) * Qm[:, 2] + np.sin(small) * Qm[:, k]])
+    assert truth.subspace_gap(X, Z) == pytest.approx(small, rel=1e-5)
