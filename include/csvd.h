@@ -19,7 +19,11 @@
  *   - no exception crosses the ABI; after an error the context stays usable
  *     and csvd_last_error() describes the failure;
  *   - dense host arrays are column-major (Fortran order) float64;
- *   - one context is used by one host thread at a time;
+ *   - one context is used by one host thread at a time, and holds one solve at
+ *     a time: while a server request on it is queued or running, or a batch
+ *     runs it, every other call that solves on it or reads its results
+ *     returns CSVD_ESTATE (a batch rejects a context listed twice with
+ *     CSVD_EINVAL);
  *   - all device work runs on the HIP stream given at csvd_create (NULL means
  *     the default stream); calls return after that work has completed.
  */
@@ -38,7 +42,8 @@ enum {
   CSVD_OK = 0,
   CSVD_EINVAL = -1,     /* invalid argument (message says which)                 */
   CSVD_ENOMEM = -2,     /* device or host allocation failed                      */
-  CSVD_ENOTCONV = -3,   /* shifted solves hit max_iters before solve_rtol;        */
+  CSVD_ENOTCONV = -3,   /* shifted solves hit max_iters before solve_rtol, or a   */
+                        /* dense SVD of step 3 or 5 reached its sweep limit;      */
                         /* triplets were still extracted and can be read          */
   CSVD_EDEVICE = -4,    /* a HIP runtime call failed                             */
   CSVD_ESTATE = -5,     /* call out of order (e.g. triplets before a solve)      */
@@ -71,6 +76,8 @@ typedef struct {
                           /* tridiagonal; used to make residuals relative                */
   int32_t window;         /* Lanczos steps per basis window, 1..64 (0 -> automatic)      */
   int32_t check_solves;   /* 1: compute the true FP64 residual of every shifted solve    */
+                          /* (per-column solver; the block solver keeps no per-shift    */
+                          /* solutions and reports NaN)                                  */
   int32_t solver;         /* CSVD_SOLVER_BLOCK: one block Lanczos basis of width L (padded */
                           /* to a power of two <= 64) for all shifts, two passes; needs   */
                           /* CSVD_FP64 (else CSVD_EINVAL);                                 */
@@ -164,6 +171,8 @@ typedef struct {
                              /* Cholesky QR pass (see csvd_params.cholqr_passes)         */
   double  moments_ms;        /* block solver: average duration of one moment launch     */
                              /* over 16 basis blocks (sampled)                          */
+  int32_t svd_sweeps_exhausted; /* 1 if a one-sided Jacobi SVD of step 3 or 5 stopped at */
+                             /* its limit of 60 sweeps (the solve returns CSVD_ENOTCONV) */
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);
@@ -239,7 +248,8 @@ int csvd_server_create(csvd_server **srv, int64_t budget_bytes, int32_t max_batc
 
 /* Queues a request.  The context must stay alive until the request is done.
  * V_in may be NULL (seeded).  Returns a request id >= 0 in *req.  A request
- * whose footprint alone exceeds the budget is rejected with CSVD_ENOMEM. */
+ * whose footprint alone exceeds the budget is rejected with CSVD_ENOMEM; a
+ * context that already has a queued or running request, with CSVD_ESTATE. */
 int csvd_server_submit(csvd_server *srv, csvd_ctx *ctx, double a, double b,
                        const csvd_params *p, const double *V_in, int64_t *req);
 

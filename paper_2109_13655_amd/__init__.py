@@ -61,7 +61,7 @@ class csvd_info(C.Structure):
         ("spmm_a_bytes", C.c_double), ("spmm_at_bytes", C.c_double), ("window_bytes", C.c_double),
         ("window", C.c_int32), ("L_padded", C.c_int32), ("solver", C.c_int32), ("deflated", C.c_int32),
         ("rest_ms", C.c_double), ("basis_stored", C.c_int32), ("one_pass_steps", C.c_int32),
-        ("moments_ms", C.c_double),
+        ("moments_ms", C.c_double), ("svd_sweeps_exhausted", C.c_int32),
     ]
 
     def as_dict(self):
@@ -75,6 +75,7 @@ class CsvdError(RuntimeError):
 
 
 _lib = None
+_shape = {}  # (m, n) of every live context handle, for argument checks
 _P = C.c_void_p
 _DP = C.POINTER(C.c_double)
 _IP = C.POINTER(C.c_int32)
@@ -160,9 +161,14 @@ def csvd_create(m, n, rowptr, colidx, vals, hip_stream=None):
     rp = np.ascontiguousarray(rowptr, dtype=np.int32)
     ci = np.ascontiguousarray(colidx, dtype=np.int32)
     va = np.ascontiguousarray(vals, dtype=np.float64)
+    if rp.ndim != 1 or rp.size != int(m) + 1:
+        raise ValueError(f"rowptr must hold m + 1 = {int(m) + 1} entries, got {rp.size}")
+    if ci.shape != va.shape or ci.ndim != 1:
+        raise ValueError(f"colidx and vals must be 1-D of equal length, got {ci.shape} and {va.shape}")
     rc = lib.csvd_create(C.byref(h), int(m), int(n), int(va.size), _ptr(rp), _ptr(ci), _ptr(va), 0,
                          C.c_void_p(hip_stream) if hip_stream else None)
     _check(rc)
+    _shape[h.value] = (int(m), int(n))
     return h
 
 
@@ -173,14 +179,25 @@ def csvd_create_device(m, n, nnz, rowptr_addr, colidx_addr, vals_addr, hip_strea
                             C.c_void_p(colidx_addr), C.c_void_p(vals_addr), 1,
                             C.c_void_p(hip_stream) if hip_stream else None)
     _check(rc)
+    _shape[h.value] = (int(m), int(n))
     return h
+
+
+def _check_vin(ctx, V_in, L):
+    """V_in as a column-major float64 n x L array (n of the context)."""
+    V_in = _f64(V_in)
+    key = ctx.value if isinstance(ctx, C.c_void_p) else ctx
+    n = _shape.get(key, (None, None))[1]
+    if V_in.ndim != 2 or V_in.shape[1] != int(L) or (n is not None and V_in.shape[0] != n):
+        raise ValueError(f"V_in must be n x L = {n} x {int(L)}, got {V_in.shape}")
+    return V_in
 
 
 def csvd_solve_interval(ctx, a, b, params, V_in=None):
     """Returns the status (CSVD_OK or CSVD_ENOTCONV); raises on errors."""
     Vp = None
     if V_in is not None:
-        V_in = _f64(V_in)
+        V_in = _check_vin(ctx, V_in, params.L)
         Vp = _ptr(V_in)
     rc = load().csvd_solve_interval(ctx, float(a), float(b), C.byref(params), Vp)
     return _check(rc, ctx, allow=(CSVD_OK, CSVD_ENOTCONV))
@@ -269,6 +286,7 @@ def csvd_trim(ctx):
 
 def csvd_destroy(ctx):
     if ctx:
+        _shape.pop(ctx.value if isinstance(ctx, C.c_void_p) else ctx, None)
         load().csvd_destroy(ctx)
 
 
@@ -287,7 +305,7 @@ def csvd_solve_batch(ctxs, a, b, params, V_in=None):
             if v is None:
                 arr[i] = None
             else:
-                vv = _f64(v)
+                vv = _check_vin(ctxs[i], v, params[i].L)
                 keep.append(vv)
                 arr[i] = vv.ctypes.data
         vptr = C.cast(arr, C.c_void_p)
@@ -314,7 +332,7 @@ def csvd_server_submit(srv, ctx, a, b, params, V_in=None):
     req = C.c_int64()
     Vp = None
     if V_in is not None:
-        V_in = _f64(V_in)
+        V_in = _check_vin(ctx, V_in, params.L)
         Vp = _ptr(V_in)
     _srv_check(load().csvd_server_submit(srv, ctx, float(a), float(b), C.byref(params), Vp, C.byref(req)), srv)
     return req.value

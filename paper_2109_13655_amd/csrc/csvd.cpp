@@ -574,6 +574,7 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   // LAPACK's one-sided Jacobi): below it a rotation only moves noise
   // (square A and V of jacobi_padded_cols columns: pairs of column blocks
   // in LDS where the size allows, else one launch per column pairing)
+  bool sweeps_exhausted = false;
   auto jacobi = [&](double *A, int rows, int ncol_even, double *V, int vrows) -> int {
     const double tol = std::sqrt((double)rows) * 2.220446049250313e-16;
     const int w = jacobi_block_width(ncol_even);
@@ -593,7 +594,8 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
       HIPCHK(ctx, hipStreamSynchronize(st));
       if (cnt == 0) return CSVD_OK;
     }
-    return CSVD_OK;  // 60 sweeps: accept (reported through residuals)
+    sweeps_exhausted = true;  // reported in csvd_info and by the solve's status
+    return CSVD_OK;
   };
   int rc = jacobi(dRt.as<double>(), LMe, LMe, dJ.as<double>(), LMe);
   if (rc) return rc;
@@ -762,6 +764,7 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
     }
   }
   double t3 = now_ms();
+  info.svd_sweeps_exhausted = sweeps_exhausted ? 1 : 0;
   info.iterations = R.block ? R.iters_last : R.job->iters;
   info.iterations_total = R.iters_total;
   info.t_hat = t;
@@ -800,7 +803,10 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
 int check_solves(SolveRun &R) {
   csvd_ctx *ctx = R.ctx;
   hipStream_t st = ctx->st;
-  if (R.block) return CSVD_OK;  // the block solver keeps no per-shift solution vectors
+  if (R.block) {  // the block solver keeps no per-shift solution vectors
+    ctx->info.max_solve_resid_true = std::nan("");
+    return CSVD_OK;
+  }
   Job &J = *R.job;
   const int L = J.h.L, S = J.h.S;
   const int64_t n = ctx->n, m = ctx->m;
@@ -851,6 +857,22 @@ int check_solves(SolveRun &R) {
   return CSVD_OK;
 }
 
+// Status of a finished solve: CSVD_ENOTCONV when a shifted solve stopped at
+// max_iters or a dense SVD stopped at its sweep limit (triplets are still
+// readable), CSVD_OK otherwise.
+int finish_status(csvd_ctx *ctx) {
+  if (!ctx->info.converged) {
+    ctx->last_status = CSVD_ENOTCONV;
+    ctx->err = "shifted solves reached max_iters before solve_rtol";
+  } else if (ctx->info.svd_sweeps_exhausted) {
+    ctx->last_status = CSVD_ENOTCONV;
+    ctx->err = "a one-sided Jacobi SVD of step 3 or 5 reached its sweep limit";
+  } else {
+    ctx->last_status = CSVD_OK;
+  }
+  return ctx->last_status;
+}
+
 }  // namespace csvd
 
 // ============================================================================
@@ -895,9 +917,11 @@ int csvd_create(csvd_ctx **out, int64_t m, int64_t n, int64_t nnz, const int32_t
   c->nnz = nnz;
   c->st = (hipStream_t)hip_stream;
   if (!on_device) {
+    // every row pointer in [0, nnz] and non-decreasing before any entry is read
     if (rowptr[0] != 0 || rowptr[m] != nnz) return CSVD_EINVAL;
+    for (int64_t i = 0; i < m; ++i)
+      if (rowptr[i + 1] < rowptr[i] || rowptr[i + 1] > nnz) return CSVD_EINVAL;
     for (int64_t i = 0; i < m; ++i) {
-      if (rowptr[i + 1] < rowptr[i]) return CSVD_EINVAL;
       for (int64_t k = rowptr[i]; k < rowptr[i + 1]; ++k) {
         if (colidx[k] < 0 || colidx[k] >= n) return CSVD_EINVAL;
         if (k > rowptr[i] && colidx[k] <= colidx[k - 1]) return CSVD_EINVAL;
@@ -952,6 +976,7 @@ const char *csvd_last_error(const csvd_ctx *ctx) {
 
 int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p, const double *V_in) {
   if (!ctx) return CSVD_EINVAL;
+  if (ctx->busy) return set_err(ctx, CSVD_ESTATE, "the context is held by a live server request");
   ctx->err.clear();
   ctx->solved = false;
   std::unique_ptr<SolveRun> R(new SolveRun());
@@ -1018,14 +1043,13 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   ctx->info.spmm_samples = cnt[0];
   ctx->job = std::move(R->job);
   ctx->spec = R->spec;
-  ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
-  if (!ctx->info.converged) ctx->err = "shifted solves reached max_iters before solve_rtol";
-  return ctx->last_status;
+  return finish_status(ctx);
 }
 
 int csvd_get_triplets(csvd_ctx *ctx, int64_t *t_hat, int64_t capacity, double *sigma, double *U, double *V,
                       double *resid) {
   if (!ctx || !t_hat) return CSVD_EINVAL;
+  if (ctx->busy) return set_err(ctx, CSVD_ESTATE, "the context is held by a live server request");
   if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
   const int64_t t = (int64_t)ctx->sigma.size();
   *t_hat = t;
@@ -1041,6 +1065,7 @@ int csvd_get_triplets(csvd_ctx *ctx, int64_t *t_hat, int64_t capacity, double *s
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info) {
   if (!ctx || !info) return CSVD_EINVAL;
+  if (ctx->busy) return set_err(ctx, CSVD_ESTATE, "the context is held by a live server request");
   if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
   *info = ctx->info;
   return CSVD_OK;
@@ -1048,6 +1073,7 @@ int csvd_get_info(csvd_ctx *ctx, csvd_info *info) {
 
 int csvd_get_moment(csvd_ctx *ctx, int32_t k, double *S_k) {
   if (!ctx || !S_k) return CSVD_EINVAL;
+  if (ctx->busy) return set_err(ctx, CSVD_ESTATE, "the context is held by a live server request");
   if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
   if (k < 0 || k > ctx->M) return set_err(ctx, CSVD_EINVAL, "moment index out of range");
   const double *src = ctx->d_S.as<double>() + (size_t)k * ctx->L * ctx->npad;
@@ -1058,6 +1084,7 @@ int csvd_get_moment(csvd_ctx *ctx, int32_t k, double *S_k) {
 
 int csvd_get_solution(csvd_ctx *ctx, int32_t j, double *Y_re, double *Y_im) {
   if (!ctx || !Y_re || !Y_im) return CSVD_EINVAL;
+  if (ctx->busy) return set_err(ctx, CSVD_ESTATE, "the context is held by a live server request");
   if (!ctx->solved || !ctx->job) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
   if (j < 0 || j >= ctx->S) return set_err(ctx, CSVD_EINVAL, "shift index out of range");
   DevBuf re, im;
@@ -1210,8 +1237,14 @@ constexpr int kFinishThreads = 8;
 int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, const double *b,
                      const csvd_params *params, const double *const *V_in, int32_t *status) {
   if (count < 1 || !ctxs || !a || !b || !params || !status) return CSVD_EINVAL;
-  for (int i = 0; i < count; ++i)
+  for (int i = 0; i < count; ++i) {
     if (!ctxs[i]) return CSVD_EINVAL;
+    // each problem owns its context's results: a context listed twice would
+    // have two solves writing its moments and triplets at once
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return set_err(ctxs[i], CSVD_EINVAL, "a context is listed twice in the batch");
+    if (ctxs[i]->busy) return set_err(ctxs[i], CSVD_ESTATE, "the context is held by a live server request");
+  }
   hipStream_t st = ctxs[0]->st;
   const int W = pick_window(&params[0]);
   const bool mixed = params[0].precision == CSVD_MIXED;
@@ -1231,8 +1264,7 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
         status[i] = rc;
       } else {
         ctx->spec = R.spec;
-        ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
-        status[i] = ctx->last_status;
+        status[i] = finish_status(ctx);
       }
       R.bjob.reset();  // free the basis histories
     };
@@ -1329,8 +1361,7 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
       csvd_ctx *ctx = ctxs[i];
       ctx->job = std::move(R.job);
       ctx->spec = R.spec;
-      ctx->last_status = ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
-      status[i] = ctx->last_status;
+      status[i] = finish_status(ctx);
     }
   }
   return CSVD_OK;
@@ -1404,6 +1435,7 @@ static int srv_admit(csvd_server *s) {
       R.state = 2;
       R.status = rc;
       R.run.reset();
+      R.ctx->busy = false;
       continue;
     }
     // the budget covers the job's own allocation, not a stored basis
@@ -1424,6 +1456,7 @@ static int srv_admit(csvd_server *s) {
 
 static void srv_release(csvd_server *s, csvd_server::Req &R) {
   s->used -= R.bytes;
+  R.ctx->busy = false;
   for (auto it = s->owner.begin(); it != s->owner.end();) {
     if (R.run && it->first == R.run->job.get()) it = s->owner.erase(it);
     else ++it;
@@ -1441,8 +1474,7 @@ static void srv_finish(csvd_server *s, csvd_server::Req &R) {
   if (!r2) {
     if (R.run->job) R.ctx->job = std::move(R.run->job);
     R.ctx->spec = R.run->spec;
-    R.ctx->last_status = R.ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
-    r2 = R.ctx->last_status;
+    r2 = finish_status(R.ctx);
   }
   R.status = r2;
   R.state = 2;
@@ -1475,6 +1507,7 @@ int csvd_server_submit(csvd_server *s, csvd_ctx *ctx, double a, double b, const 
   if (rc) return srv_err(s, rc, ctx->err);
   if (pick_window(p) != 32) return srv_err(s, CSVD_EINVAL, "served requests use the server's window (0 or 32)");
   if (ctx->st != s->st) return srv_err(s, CSVD_EINVAL, "context stream differs from the server stream");
+  if (ctx->busy) return srv_err(s, CSVD_ESTATE, "the context already has a live request");
   const int64_t bytes = request_bytes(ctx, p);
   if (bytes > s->budget) return srv_err(s, CSVD_ENOMEM, "request footprint exceeds the server budget");
   const int64_t id = s->next_id++;
@@ -1489,6 +1522,8 @@ int csvd_server_submit(csvd_server *s, csvd_ctx *ctx, double a, double b, const 
     R.hasV = true;
   }
   s->queue.push_back(id);
+  ctx->busy = true;
+  ctx->solved = false;
   *req = id;
   return CSVD_OK;
 }
@@ -1553,8 +1588,7 @@ int csvd_server_step(csvd_server *s, int32_t steps, int32_t *n_active) {
         if (!r2) {
           R.ctx->job = std::move(R.run->job);
           R.ctx->spec = R.run->spec;
-          R.ctx->last_status = R.ctx->info.converged ? CSVD_OK : CSVD_ENOTCONV;
-          r2 = R.ctx->last_status;
+          r2 = finish_status(R.ctx);
         }
         R.status = r2;
         R.state = 2;
@@ -1592,6 +1626,7 @@ int csvd_server_cancel(csvd_server *s, int64_t req) {
   auto &R = it->second;
   if (R.state == 0) {
     s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), req), s->queue.end());
+    R.ctx->busy = false;
   } else if (R.state == 1) {
     if (R.run->block) s->beng->remove(R.run->bjob.get());
     else
@@ -1608,6 +1643,13 @@ int csvd_server_cancel(csvd_server *s, int64_t req) {
 
 const char *csvd_server_last_error(const csvd_server *s) { return s ? s->err.c_str() : "null server"; }
 
-void csvd_server_destroy(csvd_server *s) { delete s; }
+void csvd_server_destroy(csvd_server *s) {
+  if (!s) return;
+  // requests that never finished release their contexts (which, by the
+  // contract of csvd_server_submit, are still alive)
+  for (auto &kv : s->reqs)
+    if (kv.second.state == 0 || kv.second.state == 1) kv.second.ctx->busy = false;
+  delete s;
+}
 
 }  // extern "C"

@@ -178,6 +178,9 @@ struct csvd_ctx {
   std::unique_ptr<csvd::Job> job;    // last round's job (solutions), single-vector solver
   double norm_est = 0.0;             // cached ||A||_2 estimate
   csvd::SolveSpec spec;
+  // a server request (queued or running) or a batch holds the context: its
+  // moments, triplets and info belong to that solve until it is done
+  bool busy = false;
 };
 
 struct csvd_server;

@@ -375,3 +375,18 @@ def interval_from_sample(m: int, n: int, nnz_per_col: int, count: int, scale: in
     dens = np.sum(np.abs(ev - lq) <= w / 2) / w
     width = count / (scale * dens)
     return math.sqrt(lq - width / 2), math.sqrt(lq + width / 2), lq, dens
+
+
+def sample_spectrum(m: int, n: int, nnz_per_col: int, scale: int = 25, config: int = 2) -> np.ndarray:
+    """n singular values (descending) distributed like those of a random
+    sparse m x n matrix with k nonzeros per column: the eigenvalues of A^T A
+    of a same-distribution instance (m/scale) x (n/scale) define an empirical
+    quantile function, read at the n midpoints (i + 1/2)/n.  Used as the
+    exact spectrum of a known-spectrum surrogate of that matrix."""
+    ms, ns = max(m // scale, 2), max(n // scale, 1)
+    I = random_sparse(ms, ns, nnz_per_col, config=config, instance=99)
+    A = I.dense()
+    ev = np.sort(np.linalg.eigvalsh(A.T @ A))
+    q = (np.arange(n) + 0.5) / n
+    lam = np.interp(q, (np.arange(ns) + 0.5) / ns, ev)
+    return np.sqrt(np.maximum(lam, 0.0))[::-1].copy()

@@ -66,7 +66,7 @@ def _csr_small():
     return rp, ci, va
 
 
-@pytest.mark.parametrize("case", ["m_lt_n", "bad_rowptr", "unsorted", "out_of_range", "nan"])
+@pytest.mark.parametrize("case", ["m_lt_n", "bad_rowptr", "unsorted", "out_of_range", "nan", "rowptr_past_nnz"])
 def test_create_rejects_malformed_csr(case):
     rp, ci, va = _csr_small()
     m, n = 4, 3
@@ -83,6 +83,10 @@ def test_create_rejects_malformed_csr(case):
     elif case == "nan":
         va = va.copy(); va[3] = np.nan
         code = cs.CSVD_ENUMERIC
+    elif case == "rowptr_past_nnz":
+        # a row pointer beyond nnz with a valid last entry: rejected before
+        # any column index or value is read (the arrays hold nnz entries)
+        rp = rp.copy(); rp[1] = 100
     with pytest.raises(cs.CsvdError) as e:
         cs.csvd_create(m, n, rp, ci, va)
     assert e.value.code == code
@@ -97,3 +101,13 @@ def test_oracle_transpose_definition():
     for j in range(I.n):
         At[j, ci[rp[j]:rp[j + 1]]] = va[rp[j]:rp[j + 1]]
     assert np.array_equal(At, I.dense().T)
+
+
+def test_binding_checks_array_sizes():
+    """The binding refuses arrays whose sizes do not match m and nnz before
+    calling the library (which reads m + 1 row pointers and nnz entries)."""
+    rp, ci, va = _csr_small()
+    with pytest.raises(ValueError):
+        cs.csvd_create(5, 3, rp, ci, va)          # rowptr needs m + 1 entries
+    with pytest.raises(ValueError):
+        cs.csvd_create(4, 3, rp, ci[:-1], va)     # colidx and vals differ in length

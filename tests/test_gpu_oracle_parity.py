@@ -1,0 +1,257 @@
+"""GPU parity against the oracle where the earlier tests left holes: the
+device's own triplet residuals per triplet, the 64-wide block path the
+headline workload runs, exact counts at the headline shape on a
+known-spectrum surrogate, mixed precision, and the guards that keep one solve
+per context.
+
+Tolerances follow from the arithmetic: residuals are compared per triplet
+with a relative slack for summation order only; singular values against exact
+or oracle values at 1e-9 (FP64) or 1e-6 (mixed precision, with the residual
+target of that mode).
+"""
+import numpy as np
+import pytest
+
+import paper_2109_13655_amd as cs
+import synth
+from oracle import method, sparse, truth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-test]", *a, flush=True)
+
+
+def make_ctx(I):
+    return cs.csvd_create(I.m, I.n, I.rowptr, I.colidx, I.vals)
+
+
+def check_device_residuals(I, sig, U, V, res, normA, rtol=1e-6):
+    """The residuals the library reports (k_resid_cols on the device) equal
+    the oracle's dense residual definition per triplet (Sec. 4.2,
+    max(||A v - s u||, ||A^T u - s v||) / ||A||_2), up to summation order."""
+    r_host = truth.triplet_residuals(I, sig, U, V, normA=normA)
+    assert res.shape == r_host.shape
+    np.testing.assert_allclose(res, r_host, rtol=rtol, atol=1e-15)
+    return r_host
+
+
+def compare_with_oracle(I, sig, U, V, res, ref, tol_sigma, tol_res, normA):
+    """Triplets of the GPU against the oracle's (same count, values, vectors of
+    simple values) and the device residuals against the host's."""
+    s_o, U_o, V_o = ref
+    assert sig.size == s_o.size, (sig, s_o)
+    np.testing.assert_allclose(sig, s_o, rtol=tol_sigma, atol=0)
+    r_host = check_device_residuals(I, sig, U, V, res, normA)
+    assert r_host.max() <= tol_res
+    for i in range(sig.size):
+        if (i > 0 and sig[i] - sig[i - 1] < 1e-6) or (i + 1 < sig.size and sig[i + 1] - sig[i] < 1e-6):
+            continue
+        assert abs(abs(V[:, i] @ V_o[:, i]) - 1.0) < 1e-6
+        assert abs(abs(U[:, i] @ U_o[:, i]) - 1.0) < 1e-6
+
+
+def _mid_problem():
+    sig = np.linspace(0.02, 1.0, 1100)
+    return synth.givens_known(1300, 1100, sigma=sig, nrot=3000, config=85, a=0.40, b=0.41)
+
+
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_SINGLE, cs.CSVD_SOLVER_BLOCK])
+def test_device_residuals_per_triplet_loose_solves(solver):
+    """Loose shifted solves (solve_rtol 1e-6) leave triplet residuals far
+    above rounding, so a residual kernel that returned zeros, dropped the
+    sigma term or took the wrong column would differ from the host's values
+    here; the values must agree per triplet."""
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 21)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=8, M=4, N=16, solve_rtol=1e-6, norm_a=1.0, solver=solver)
+        st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+        assert st == cs.CSVD_OK
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+        info = cs.csvd_get_info(ctx)
+    finally:
+        cs.csvd_destroy(ctx)
+    say("loose solves: solver", info.solver, "t_hat", sig.size, "resid range", res.min(), res.max())
+    assert sig.size >= 5 and res.min() > 1e-13
+    r_host = check_device_residuals(I, sig, U, Vv, res, 1.0)
+    assert info.max_triplet_resid == pytest.approx(r_host.max(), rel=1e-6)
+    assert info.svd_sweeps_exhausted == 0
+
+
+def test_givens_ell2_triplets_against_oracle():
+    """The 1200 x 1000 Givens workload (exact sigma, [0.40, 0.45], N = 16,
+    L = 16, M = 8, ell = 2) against the oracle's triplets: values, vectors and
+    the device's residual per triplet on the 50 strict-interior values.  The
+    value 0.45000000000000007 sits on the end b up to rounding (an edge
+    value): either side may report it, and where reported it must be exact
+    and meet the residual target."""
+    I = synth.givens_known()
+    V = synth.v_in(I.n, 16, 9)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=16, M=8, N=16, ell=2, norm_a=1.0)
+        assert cs.csvd_solve_interval(ctx, I.a, I.b, p, V) == cs.CSVD_OK
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    o = method.ss_svd(I, I.a, I.b, V, 16, 8, 16, ell=2)
+    band = 1e-12
+    core = (sig > I.a + band) & (sig < I.b - band)
+    core_o = (o["sigma"] > I.a + band) & (o["sigma"] < I.b - band)
+    assert core.sum() == core_o.sum() == 50
+    compare_with_oracle(I, sig[core], U[:, core], Vv[:, core], res[core],
+                        (o["sigma"][core_o], o["U"][:, core_o], o["V"][:, core_o]), 1e-9, 1e-8, 1.0)
+    for s_ in np.concatenate([sig[~core], o["sigma"][~core_o]]):
+        assert np.min(np.abs(I.sigma - s_)) <= 1e-9 * s_
+    assert check_device_residuals(I, sig, U, Vv, res, 1.0).max() <= 1e-8
+
+
+def test_block_width_64_against_oracle_and_truth():
+    """The 64-wide block path of the headline workload (bs_tall_rg<64>,
+    bs_small1<64>, b_shift<64>, b_moments<64>): a random sparse 9216 x 4608
+    matrix (10 nonzeros per column) with L = 64, so the automatic choice takes
+    the block solver at width 64.  Moments against the oracle's direct
+    solves, triplets against the oracle and the dense truth (exact count of
+    an interval whose ends sit between eigenvalues)."""
+    I = synth.random_sparse(9216, 4608, 10, config=96)
+    A = I.dense()
+    G = A.T @ A
+    ev = np.linalg.eigvalsh(G)
+    a, b = synth.interval_by_count(ev, ev.size // 2, 24)
+    L, M, N = 64, 4, 16
+    V = synth.v_in(I.n, L, 22)
+    say("block width 64: n", I.n, "interval", a, b)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=L, M=M, N=N, solve_rtol=1e-12)
+        st = cs.csvd_solve_interval(ctx, a, b, p, V)
+        info = cs.csvd_get_info(ctx)
+        say("steps", info.iterations, "Lp", info.L_padded, "t_hat", info.t_hat, "stored", info.basis_stored)
+        assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK and info.L_padded == 64
+        Sg = [cs.csvd_get_moment(ctx, k, I.n, L) for k in range(M + 1)]
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    o = method.ss_svd(I, a, b, V, L, M, N, G=G)
+    ymax = max(np.linalg.norm(o["Y"][j]) for j in range(N // 2))
+    for k in range(M + 1):
+        scale = 2 * np.abs(o["c"][:, k]).sum() * ymax
+        assert np.linalg.norm(Sg[k] - o["S"][k]) <= 1e-9 * scale, k
+    s_t, U_t, V_t, sall = truth.dense_truth(I, a, b)
+    assert s_t.size == 24
+    compare_with_oracle(I, sig, U, Vv, res, (o["sigma"], o["U"], o["V"]), 1e-9, 1e-8, sall[0])
+    np.testing.assert_allclose(sig, s_t, rtol=1e-9)
+    assert truth.subspace_gap(Vv, V_t) <= 1e-7
+
+
+def test_headline_shape_known_spectrum_count():
+    """Count parity at the headline shape: a 2e5 x 1e5 surrogate with exactly
+    known singular values (distributed like the random c2 matrix's, from the
+    quantile function of a same-distribution sample) wrapped in two levels of
+    random Givens rotations on rows and columns (16 nonzeros per column).
+    With the bench's parameters (N = 32, L = 64, M = 8) and an interval whose
+    ends sit halfway between neighbouring exact values around 64 values at the
+    median, the GPU returns exactly those 64 values to 1e-9, each triplet
+    certified by the oracle's host sparse residuals <= 1e-8."""
+    m, n = 200000, 100000
+    sig_all = synth.sample_spectrum(m, n, 10, config=2)
+    I = synth.known_spectrum_sparse(m, n, sig_all, levels=2, config=21)
+    lam = np.sort(sig_all ** 2)
+    a, b = synth.interval_by_count(lam, lam.size // 2, 64)
+    exact = np.sort(sig_all[(sig_all >= a) & (sig_all <= b)])
+    assert exact.size == 64
+    nA = float(sig_all.max())
+    say("surrogate", m, "x", n, "nnz", I.nnz, "interval", a, b)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=64, M=8, N=32, norm_a=nA)
+        st = cs.csvd_solve_interval(ctx, a, b, p, synth.v_in(n, 64, 2, 1))
+        info = cs.csvd_get_info(ctx)
+        say("status", st, "steps", info.iterations, "t_hat", info.t_hat, "max resid", info.max_triplet_resid)
+        assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK and info.L_padded == 64
+        sig, U, V, res = cs.csvd_get_triplets(ctx, m, n)
+    finally:
+        cs.csvd_destroy(ctx)
+    assert sig.size == 64
+    np.testing.assert_allclose(sig, exact, rtol=1e-9)
+    r_host = truth.sparse_triplet_residuals(I.rowptr, I.colidx, I.vals, m, n, sig, U, V, nA)
+    assert r_host.max() <= 1e-8
+    np.testing.assert_allclose(res, r_host, rtol=1e-6, atol=1e-15)
+    rows = np.random.default_rng(6).choice(m, 64, replace=False)
+    AV = sparse.product_rows(I.rowptr, I.colidx, I.vals, V, rows)
+    np.testing.assert_allclose(AV, U[rows] * sig[None, :], rtol=0, atol=1e-8 * nA)
+
+
+@pytest.mark.parametrize("transform", [cs.CSVD_PLAIN, cs.CSVD_EXP])
+def test_mixed_precision_against_oracle(transform):
+    """CSVD_MIXED against the FP64 oracle: same count as the oracle and the
+    exact spectrum, values to 1e-6 and residuals within the 1e-6 target of
+    that mode."""
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 23)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=8, M=4, N=16, ell=2, norm_a=1.0, transform=transform,
+                                   precision=cs.CSVD_MIXED)
+        st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+        info = cs.csvd_get_info(ctx)
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    say("mixed: solver", info.solver, "status", st, "t_hat", sig.size, "max resid", res.max() if res.size else None)
+    assert st == cs.CSVD_OK
+    o = method.ss_svd(I, I.a, I.b, V, 8, 4, 16, ell=2, transform=transform)
+    exact = np.sort(I.sigma[(I.sigma >= I.a) & (I.sigma <= I.b)])
+    assert sig.size == o["sigma"].size == exact.size
+    np.testing.assert_allclose(sig, exact, rtol=1e-6)
+    r_host = check_device_residuals(I, sig, U, Vv, res, 1.0)
+    assert r_host.max() <= 1e-6
+
+
+def test_one_live_solve_per_context():
+    """A context with a queued server request refuses a second request, a
+    solo solve and result reads (CSVD_ESTATE); a batch refuses a context
+    listed twice (CSVD_EINVAL).  After the request is done the context is
+    usable again and its results are the request's."""
+    I = _mid_problem()
+    p = cs.csvd_params_default(L=8, M=2, N=16, norm_a=1.0)
+    V = synth.v_in(I.n, 8, 24)
+    ctx = make_ctx(I)
+    srv = cs.csvd_server_create(8 << 30, 2)
+    try:
+        rid = cs.csvd_server_submit(srv, ctx, I.a, I.b, p, V)
+        with pytest.raises(cs.CsvdError) as e:
+            cs.csvd_server_submit(srv, ctx, I.a, I.b, p, V)
+        assert e.value.code == cs.CSVD_ESTATE
+        with pytest.raises(cs.CsvdError) as e:
+            cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+        assert e.value.code == cs.CSVD_ESTATE
+        with pytest.raises(cs.CsvdError) as e:
+            cs.csvd_get_triplets(ctx, I.m, I.n)
+        assert e.value.code == cs.CSVD_ESTATE
+        with pytest.raises(cs.CsvdError) as e:
+            cs.csvd_solve_batch([ctx], [I.a], [I.b], [p], [V])
+        assert e.value.code == cs.CSVD_ESTATE
+        for _ in range(100000):
+            if cs.csvd_server_step(srv, 64) == 0:
+                break
+        done, st = cs.csvd_server_poll(srv, rid)
+        assert done and st == cs.CSVD_OK
+        served = cs.csvd_get_triplets(ctx, I.m, I.n)
+        assert cs.csvd_solve_interval(ctx, I.a, I.b, p, V) == cs.CSVD_OK
+        solo = cs.csvd_get_triplets(ctx, I.m, I.n)
+        for x, y in zip(served, solo):
+            assert np.array_equal(x, y)
+        ctx2 = make_ctx(I)
+        try:
+            with pytest.raises(cs.CsvdError) as e:
+                cs.csvd_solve_batch([ctx2, ctx2], [I.a, I.a], [I.b, I.b], [p, p], [V, V])
+            assert e.value.code == cs.CSVD_EINVAL
+        finally:
+            cs.csvd_destroy(ctx2)
+    finally:
+        cs.csvd_server_destroy(srv)
+        cs.csvd_destroy(ctx)

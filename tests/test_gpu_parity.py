@@ -637,6 +637,7 @@ def test_server_results_match_solo_and_cancel(solver):
     say("server solver", solver)
     ctxs = [make_ctx(I) for I, _, _ in probs]
     solo_ctx = [make_ctx(I) for I, _, _ in probs]
+    extra_ctx = make_ctx(probs[0][0])  # one live request per context
     srv = cs.csvd_server_create(8 << 30, 2)
     try:
         solo = []
@@ -645,7 +646,8 @@ def test_server_results_match_solo_and_cancel(solver):
             solo.append(cs.csvd_get_triplets(c, I.m, I.n))
         reqs = [cs.csvd_server_submit(srv, c, a, b, p, synth.v_in(I.n, 8, 11))
                 for (I, a, b), c in zip(probs, ctxs)]
-        extra = cs.csvd_server_submit(srv, ctxs[0], probs[0][1], probs[0][2], p, synth.v_in(probs[0][0].n, 8, 11))
+        extra = cs.csvd_server_submit(srv, extra_ctx, probs[0][1], probs[0][2], p,
+                                      synth.v_in(probs[0][0].n, 8, 11))
         cs.csvd_server_cancel(srv, extra)
         for _ in range(10000):
             if cs.csvd_server_step(srv, 64) == 0:
@@ -667,7 +669,7 @@ def test_server_results_match_solo_and_cancel(solver):
         cs.csvd_server_destroy(tiny)
     finally:
         cs.csvd_server_destroy(srv)
-        for c in ctxs + solo_ctx:
+        for c in ctxs + solo_ctx + [extra_ctx]:
             cs.csvd_destroy(c)
 
 
