@@ -199,6 +199,18 @@ int csvd_quadrature(double a, double b, const csvd_params *p,
  * operator alone. */
 int csvd_spmm(csvd_ctx *ctx, int32_t transpose, int64_t k, const double *X, double *Y);
 
+/* csvd_spmm for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid
+ * it): the same product with the same arguments and results, bit for bit,
+ * but its staging blocks (X and Y in column- and row-major order) live in a
+ * fixed device array of 32 MiB per GPU, held from the first call on that GPU
+ * until the process ends.  Calls no hipMalloc/hipFree.
+ * Limit: 2 k (rows of X + rows of Y) <= 4194304 doubles, else CSVD_EINVAL
+ * with a message (the context stays usable).  The array is shared by every
+ * call on the same GPU, so calls that overlap in time on one GPU (other host
+ * threads, other contexts) race: serialise them. */
+int csvd_spmm_noalloc(csvd_ctx *ctx, int32_t transpose, int64_t k, const double *X, double *Y);
+
 /* Dense FP64 product on the matrix cores: C (R x N) = A (R x K) B (K x N),
  * column-major host arrays, computed on the device (the kernel that forms
  * V-hat = V~ Q_sel in step 5).  Needs no context. */

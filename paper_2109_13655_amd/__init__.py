@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "CsvdError", "csvd_params", "csvd_info", "load", "lib_path",
     "csvd_params_default", "csvd_create", "csvd_solve_interval", "csvd_get_triplets",
-    "csvd_get_info", "csvd_get_moment", "csvd_get_solution", "csvd_quadrature", "csvd_spmm",
+    "csvd_get_info", "csvd_get_moment", "csvd_get_solution", "csvd_quadrature", "csvd_spmm", "csvd_spmm_noalloc",
     "csvd_get_transpose", "csvd_dense_gemm", "csvd_last_error", "csvd_destroy", "csvd_trim", "csvd_solve_batch",
     "csvd_server_create", "csvd_server_submit", "csvd_server_step", "csvd_server_poll",
     "csvd_server_cancel", "csvd_server_last_error", "csvd_server_destroy",
@@ -102,6 +102,7 @@ def load(build_if_missing: bool = True):
         "csvd_get_solution": (C.c_int, [_P, C.c_int32, _P, _P]),
         "csvd_quadrature": (C.c_int, [C.c_double, C.c_double, C.POINTER(csvd_params), _P, _P, _P, _P, _P, _P]),
         "csvd_spmm": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P]),
+        "csvd_spmm_noalloc": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P]),
         "csvd_get_transpose": (C.c_int, [_P, _P, _P, _P]),
         "csvd_dense_gemm": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
         "csvd_last_error": (C.c_char_p, [_P]),
@@ -252,6 +253,14 @@ def csvd_spmm(ctx, transpose, X, rows_out):
     k = X.shape[1]
     Y = np.zeros((rows_out, k), order="F")
     _check(load().csvd_spmm(ctx, int(transpose), int(k), _ptr(X), _ptr(Y)), ctx)
+    return Y
+
+
+def csvd_spmm_noalloc(ctx, transpose, X, rows_out):
+    X = _f64(X)
+    k = X.shape[1]
+    Y = np.zeros((rows_out, k), order="F")
+    _check(load().csvd_spmm_noalloc(ctx, int(transpose), int(k), _ptr(X), _ptr(Y)), ctx)
     return Y
 
 

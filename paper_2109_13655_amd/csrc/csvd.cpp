@@ -1140,6 +1140,69 @@ int csvd_spmm(csvd_ctx *ctx, int32_t transpose, int64_t k, const double *X, doub
   return CSVD_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free sparse product.  The four staging blocks of csvd_spmm (X
+// and Y, each column-major and row-major) live in one file-scope device
+// array instead of fresh allocations.  Every GPU the library runs on holds
+// its own copy of the array until the process ends.  Host code never hands
+// the array's name to a kernel or a copy (in host code it is only a
+// stand-in symbol): the device address is taken once per device with
+// hipGetSymbolAddress and that pointer is used everywhere.
+constexpr int64_t kNoAllocDoubles = (int64_t)4 << 20;  // 32 MiB of staging per device
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device (looked up on the first
+// call per device)
+int scratch_on_current_device(csvd_ctx *ctx, double **out) {
+  int dev = 0;
+  HIPCHK(ctx, hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_err(ctx, CSVD_EDEVICE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPCHK(ctx, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_err(ctx, CSVD_EDEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return CSVD_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int csvd_spmm_noalloc(csvd_ctx *ctx, int32_t transpose, int64_t k, const double *X, double *Y) {
+  if (!ctx || !X || !Y || k < 1) return CSVD_EINVAL;
+  const int64_t rows_out = transpose ? ctx->n : ctx->m;
+  const int64_t rows_in = transpose ? ctx->m : ctx->n;
+  if (k > kNoAllocDoubles || 2 * k * (rows_in + rows_out) > kNoAllocDoubles)
+    return set_err(ctx, CSVD_EINVAL,
+                   "csvd_spmm_noalloc: 2 k (rows of X + rows of Y) = " + std::to_string(2 * k * (rows_in + rows_out)) +
+                       " doubles exceeds its staging limit of " + std::to_string(kNoAllocDoubles));
+  double *s = nullptr;
+  XFER(scratch_on_current_device(ctx, &s));
+  double *xc = s, *xr = xc + rows_in * k, *yr = xr + rows_in * k, *yc = yr + rows_out * k;
+  HIPCHK(ctx, hipMemcpyAsync(xc, X, sizeof(double) * rows_in * k, hipMemcpyHostToDevice, ctx->st));
+  HIPCHK(ctx, launch_col_to_row((int)rows_in, (int)k, xc, rows_in, xr, k, ctx->st));
+  if (transpose)
+    HIPCHK(ctx, launch_spmm_rowmajor((int)ctx->n, k, ctx->rpT.as<int>(), ctx->ciT.as<int>(), ctx->vaT.as<double>(), xr,
+                                     yr, ctx->st));
+  else
+    HIPCHK(ctx, launch_spmm_rowmajor((int)ctx->m, k, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(), xr,
+                                     yr, ctx->st));
+  HIPCHK(ctx, launch_row_to_col((int)rows_out, (int)k, yr, k, yc, rows_out, ctx->st));
+  HIPCHK(ctx, hipMemcpyAsync(Y, yc, sizeof(double) * rows_out * k, hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
+
 int csvd_dense_gemm(int64_t R, int64_t N, int64_t K, const double *A, const double *B, double *Cm) {
   if (R < 1 || N < 1 || K < 1 || !A || !B || !Cm) return CSVD_EINVAL;
   DevBuf a, b, c;
