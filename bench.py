@@ -171,6 +171,24 @@ def roofline(info, config):
             "bytes_per_launch": b, "avg_launch_ms": t, "samples": int(info.spmm_samples)}
 
 
+def gather_ceiling(cs, info, W):
+    """The bare random-row gather of the two sparse products' shapes
+    (csvd_probe_gather: the same 512-byte rows, the same lane layout, no
+    matrix values or indices; one launch each for the A and A^T shapes), as
+    the ceiling the sparse products can reach on this memory system."""
+    if info.solver != 1 or int(info.L_padded) != 64 or not (info.spmm_a_ms > 0 and info.spmm_at_ms > 0):
+        return None
+    I = W["I"]
+    t1 = cs.csvd_probe_gather(I.n, 0, I.m, max(1, round(I.nnz / I.m)), seed=3, reps=20)
+    t2 = cs.csvd_probe_gather(I.m, 0, I.n, max(1, round(I.nnz / I.n)), seed=4, reps=20)
+    spmm = info.spmm_a_ms + info.spmm_at_ms
+    gathered = 2.0 * I.nnz * 512
+    return {"probe_ms": t1 + t2, "spmm_ms": spmm, "frac_of_ceiling": (t1 + t2) / spmm,
+            "probe_gather_gbs": gathered / ((t1 + t2) * 1e-3) / 1e9,
+            "spmm_gather_gbs": gathered / (spmm * 1e-3) / 1e9,
+            "note": "512-byte rows gathered per nonzero; the algorithmic bytes count the table once"}
+
+
 def roofline_moments(info, W, config):
     """The moment accumulation of the block solver, S += [Q_k0 .. Q_k0+15]
     [F_k0; ..; F_k0+15] on FP64 MFMA: 2 n Lp (M + 1) L flops per basis block,
@@ -464,6 +482,7 @@ def main():
         "roofline": roofline(info, args.config),
         "roofline_moments": roofline_moments(info, W, args.config),
     }
+    out["roofline"]["gather_ceiling"] = gather_ceiling(cs, info, W)
     if not args.no_cpu_baseline:
         log("cpu baseline (the oracle on the host cores)")
         W["solve_rtol"] = p.solve_rtol

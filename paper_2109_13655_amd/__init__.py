@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "CsvdError", "csvd_params", "csvd_info", "load", "lib_path",
     "csvd_params_default", "csvd_create", "csvd_solve_interval", "csvd_get_triplets",
-    "csvd_get_info", "csvd_get_moment", "csvd_get_solution", "csvd_quadrature", "csvd_spmm", "csvd_spmm_noalloc",
+    "csvd_get_info", "csvd_get_moment", "csvd_get_solution", "csvd_quadrature", "csvd_spmm", "csvd_spmm_noalloc", "csvd_probe_gather",
     "csvd_get_transpose", "csvd_dense_gemm", "csvd_last_error", "csvd_destroy", "csvd_trim", "csvd_solve_batch",
     "csvd_server_create", "csvd_server_submit", "csvd_server_step", "csvd_server_poll",
     "csvd_server_cancel", "csvd_server_last_error", "csvd_server_destroy",
@@ -103,6 +103,8 @@ def load(build_if_missing: bool = True):
         "csvd_quadrature": (C.c_int, [C.c_double, C.c_double, C.POINTER(csvd_params), _P, _P, _P, _P, _P, _P]),
         "csvd_spmm": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P]),
         "csvd_spmm_noalloc": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P]),
+        "csvd_probe_gather": (C.c_int, [C.c_int64, C.c_int32, C.c_int64, C.c_int32, C.c_uint64, C.c_int32,
+                                        C.POINTER(C.c_double)]),
         "csvd_get_transpose": (C.c_int, [_P, _P, _P, _P]),
         "csvd_dense_gemm": (C.c_int, [C.c_int64, C.c_int64, C.c_int64, _P, _P, _P]),
         "csvd_last_error": (C.c_char_p, [_P]),
@@ -262,6 +264,14 @@ def csvd_spmm_noalloc(ctx, transpose, X, rows_out):
     Y = np.zeros((rows_out, k), order="F")
     _check(load().csvd_spmm_noalloc(ctx, int(transpose), int(k), _ptr(X), _ptr(Y)), ctx)
     return Y
+
+
+def csvd_probe_gather(table_rows, variant, out_rows, per_out, seed=1, reps=20):
+    """Average ms of one random 512-byte-row gather launch (include/csvd_diag.h)."""
+    ms = C.c_double()
+    _check(load().csvd_probe_gather(int(table_rows), int(variant), int(out_rows), int(per_out), int(seed),
+                                    int(reps), C.byref(ms)))
+    return ms.value
 
 
 def csvd_get_transpose(ctx, n, nnz):

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcsvd.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["k_sparse.hip", "k_krylov.hip", "k_dense.hip", "k_block.hip", "k_bspmm.hip", "k_bstep.hip", "engine.cpp", "block.cpp", "csvd.cpp"]
+SOURCES = ["k_sparse.hip", "k_krylov.hip", "k_dense.hip", "k_block.hip", "k_bspmm.hip", "k_bstep.hip", "k_probe.hip",
+           "engine.cpp", "block.cpp", "csvd.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
