@@ -64,10 +64,17 @@ typedef struct {
                           /* singular value of S-hat (paper: 1e-20)                     */
   double  alpha;          /* ellipse aspect ratio (paper: 0.1)                          */
   int32_t transform;      /* CSVD_PLAIN or CSVD_EXP (EXP requires a > 0)                */
-  int32_t precision;      /* CSVD_FP64: everything in FP64.  CSVD_MIXED: the Lanczos     */
-                          /* recurrence and sparse products stay FP64, the per-shift    */
-                          /* solution/search vectors and the window basis are stored    */
-                          /* and updated in FP32; steps 3-5 in FP64                      */
+  int32_t precision;      /* CSVD_FP64: everything in FP64.  CSVD_MIXED: the Krylov      */
+                          /* bulk is stored in FP32 while the recurrence, the sparse    */
+                          /* products, the block orthogonalisation and steps 3-5 stay   */
+                          /* FP64.  Block solver: the basis kept for the moments holds  */
+                          /* FP32 copies of the blocks (half the memory of keep_basis,  */
+                          /* so larger problems avoid the second pass); a solve whose   */
+                          /* triplets miss 1e-6 is refined by accumulating the moments  */
+                          /* again from the basis regenerated in FP64 (csvd_info.       */
+                          /* mixed_refined); csvd_solve_batch keeps FP64 bases.         */
+                          /* Per-column solver: the per-shift solution/search vectors   */
+                          /* and the window basis are FP32.  Target residual 1e-6       */
   double  solve_rtol;     /* per (shift, column) stop: ||V - (z I - A^T A) Y|| / ||V||     */
   int32_t max_iters;      /* Lanczos step cap per round; reaching it -> CSVD_ENOTCONV     */
   double  spurious_eps;   /* drop a triplet when tau_i < eps * sigma_S,1 (Sec. 3.4.2)   */
@@ -79,8 +86,7 @@ typedef struct {
                           /* (per-column solver; the block solver keeps no per-shift    */
                           /* solutions and reports NaN)                                  */
   int32_t solver;         /* CSVD_SOLVER_BLOCK: one block Lanczos basis of width L (padded */
-                          /* to a power of two <= 64) for all shifts, two passes; needs   */
-                          /* CSVD_FP64 (else CSVD_EINVAL);                                 */
+                          /* to a power of two <= 64) for all shifts (L > 64: CSVD_EINVAL); */
                           /* CSVD_SOLVER_SINGLE: one Lanczos basis per column with        */
                           /* windowed per-shift updates (any L <= 256);                    */
                           /* CSVD_SOLVER_AUTO: BLOCK when it applies and n >= 64 x padded  */
@@ -173,6 +179,10 @@ typedef struct {
                              /* over 16 basis blocks (sampled)                          */
   int32_t svd_sweeps_exhausted; /* 1 if a one-sided Jacobi SVD of step 3 or 5 stopped at */
                              /* its limit of 60 sweeps (the solve returns CSVD_ENOTCONV) */
+  int32_t mixed_refined;     /* CSVD_MIXED, block solver: 1 if the triplets from the FP32  */
+                             /* stored basis missed the 1e-6 residual target and the      */
+                             /* moments were accumulated again from the basis regenerated */
+                             /* in FP64 (steps 3-5 then ran again)                         */
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);

@@ -158,6 +158,11 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   e = d_qtab.alloc(sizeof(double *) * qtab.size());
   if (e != hipSuccess) return e;
   J.Qtab = d_qtab.as<double *>();
+  q32tab.assign(qtab.size(), nullptr);
+  e = d_q32tab.alloc(sizeof(float *) * q32tab.size());
+  if (e != hipSuccess) return e;
+  J.Q32tab = d_q32tab.as<float *>();
+  J.store32 = 0;
   if ((e = set_ring(st)) != hipSuccess) return e;
   // solo tables: one job
   e = d_desc.alloc(sizeof(BJobDesc));
@@ -185,6 +190,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
 hipError_t BlockJob::set_ring(hipStream_t st) {
   h.qC = h.nring;
   h.qT = 1;
+  h.store32 = 0;
   std::fill(qtab.begin(), qtab.end(), nullptr);
   qtab[0] = h.Q;
   store = false;
@@ -195,7 +201,8 @@ hipError_t BlockJob::set_ring(hipStream_t st) {
 
 bool BlockJob::grow_store(int kneed, hipStream_t st) {
   if (store_cap > 0 && kneed >= store_cap) return false;  // blocks 0 .. kneed would pass the cap
-  const size_t bytes = sizeof(double) * (size_t)kStoreChunk * h.n * h.Lp;
+  const size_t esz = mixed ? sizeof(float) : sizeof(double);
+  const size_t bytes = esz * (size_t)kStoreChunk * h.n * h.Lp;
   bool changed = false;
   while ((int64_t)chunks.size() * kStoreChunk <= kneed) {
     if (chunks.size() + 1 >= qtab.size()) return false;
@@ -222,14 +229,17 @@ bool BlockJob::grow_store(int kneed, hipStream_t st) {
         if (c->alloc(bytes) != hipSuccess) return false;
       }
     }
-    qtab[chunks.size()] = c->as<double>();
+    if (mixed) q32tab[chunks.size()] = c->as<float>();
+    else qtab[chunks.size()] = c->as<double>();
     chunks.push_back(std::move(c));
     changed = true;
   }
   if (changed) {
-    if (hipMemcpyAsync(d_qtab.p, qtab.data(), sizeof(double *) * qtab.size(), hipMemcpyHostToDevice, st) !=
-        hipSuccess)
-      return false;
+    const hipError_t ec = mixed ? hipMemcpyAsync(d_q32tab.p, q32tab.data(), sizeof(float *) * q32tab.size(),
+                                                 hipMemcpyHostToDevice, st)
+                                : hipMemcpyAsync(d_qtab.p, qtab.data(), sizeof(double *) * qtab.size(),
+                                                 hipMemcpyHostToDevice, st);
+    if (ec != hipSuccess) return false;
     if (hipStreamSynchronize(st) != hipSuccess) return false;
   }
   return true;
@@ -295,7 +305,16 @@ hipError_t BEngine::start(BlockJob *j) {
   // store mode if the first chunks fit (blocks 0 .. kBlockPoll + 1 before the first poll)
   j->free_store(true);
   if ((e = j->set_ring(st_)) != hipSuccess) return e;
-  if (j->want_store) {
+  if (j->want_store && j->mixed) {
+    // FP32 copies of the blocks in the store, the FP64 recurrence in the ring
+    std::fill(j->q32tab.begin(), j->q32tab.end(), nullptr);
+    if (j->grow_store(std::min(kBlockPollSteps + 2, j->Kcap + 1), st_)) {
+      j->store = true;
+      J.store32 = 1;
+    } else {
+      j->free_store(false);
+    }
+  } else if (j->want_store) {
     J.qC = kStoreChunk;
     J.qT = (int)j->qtab.size();
     std::fill(j->qtab.begin(), j->qtab.end(), nullptr);
@@ -314,6 +333,7 @@ hipError_t BEngine::start(BlockJob *j) {
   // one-pass flag, counter and robust-step mark of this round start at zero
   if ((e = hipMemsetAsync(J.flags + 1, 0, 3 * sizeof(int), st_)) != hipSuccess) return e;
   if ((e = start_block(j, true)) != hipSuccess) return e;
+  if ((e = launch_b_store32(J, 0, st_)) != hipSuccess) return e;
   BBatch b = j->solo;
   b.clock = clock_;
   if ((e = launch_shift(b, 1)) != hipSuccess) return e;
@@ -366,6 +386,7 @@ hipError_t BEngine::robust_finish(std::vector<BlockJob *> &v, bool first_pass) {
     const size_t L2 = (size_t)j->h.Lp * j->h.Lp;
     hipError_t e = orth_block(j, blk, blk, first_pass ? j->h.Bh + (size_t)(k + 1) * L2 : nullptr, nullptr);
     if (e != hipSuccess) return e;
+    if ((e = launch_b_store32(j->h, k + 1, st_)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -394,11 +415,13 @@ hipError_t BEngine::finish_stored(BlockJob *j) {
   return j->set_ring(st_);
 }
 
-hipError_t BEngine::enter_pass2(BlockJob *j) {
+hipError_t BEngine::enter_pass2(BlockJob *j, bool coefficients) {
   BJobDesc &J = j->h;
-  hipError_t e = launch_b_backsolve(J, j->K, st_);
-  if (e != hipSuccess) return e;
-  if ((e = launch_b_fcoef(J, j->K, st_)) != hipSuccess) return e;
+  hipError_t e;
+  if (coefficients) {
+    if ((e = launch_b_backsolve(J, j->K, st_)) != hipSuccess) return e;
+    if ((e = launch_b_fcoef(J, j->K, st_)) != hipSuccess) return e;
+  }
   if ((e = hipMemsetAsync(J.Sout, 0, 8 * (size_t)J.npad * J.Kmom * J.L, st_)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(J.Q, 0, 8 * (size_t)J.nring * J.n * J.Lp, st_)) != hipSuccess) return e;
   J.start_clock = (int)clock_;
@@ -615,10 +638,11 @@ hipError_t BEngine::poll(std::vector<BlockJob *> *finished) {
       // blocks up to Q_{steps + kBlockPoll + 1} exist before the next poll (none past Q_Kcap)
       if (j->store && !j->grow_store(std::min(steps + kBlockPollSteps + 2, j->Kcap + 1), st_)) {
         // out of memory for the stored basis: continue with the ring (blocks
-        // Q_{k-1} and Q_k move there) and regenerate the basis in pass 2
+        // Q_{k-1} and Q_k move there; a mixed-precision job has them there
+        // already) and regenerate the basis in pass 2
         BJobDesc &J = j->h;
         const size_t blk = sizeof(double) * (size_t)J.n * J.Lp;
-        for (int kk = std::max(steps - 1, 0); kk <= steps; ++kk) {
+        for (int kk = std::max(steps - 1, 0); !j->mixed && kk <= steps; ++kk) {
           const double *src = j->qtab[kk / kStoreChunk] + (size_t)(kk % kStoreChunk) * J.n * J.Lp;
           double *dst = J.Q + (size_t)(kk % J.nring) * J.n * J.Lp;
           if ((e = hipMemcpyAsync(dst, src, blk, hipMemcpyDeviceToDevice, st_)) != hipSuccess) return e;

@@ -8,8 +8,6 @@
 
 namespace csvd {
 
-// Basis blocks per allocation of the stored basis
-constexpr int kStoreChunk = 64;
 // device memory left free when the stored basis grows (bytes)
 constexpr size_t kStoreReserve = (size_t)8 << 30;
 
@@ -24,10 +22,13 @@ void release_idle_chunks();
 // blocks and accumulates the moments as it goes.
 struct BlockJob {
   BJobDesc h{};
-  DevBuf mem, d_shift, d_cmom, d_desc, d_toff, d_qtab;
+  DevBuf mem, d_shift, d_cmom, d_desc, d_toff, d_qtab, d_q32tab;
   BBatch solo{};
   std::vector<double *> qtab;                  // host copy of the basis table
+  std::vector<float *> q32tab;                 // host copy of the FP32 basis table (mixed precision)
   std::vector<std::unique_ptr<DevBuf>> chunks;  // stored basis, kStoreChunk blocks each
+  bool mixed = false;      // CSVD_MIXED: the stored basis holds FP32 copies (h.store32) and the
+                           // recurrence keeps its FP64 blocks in the ring
   bool want_store = true;  // try store mode (the server keeps the ring: its budget covers the job only)
   int store_cap = 0;       // most basis blocks to store (0: as device memory allows)
   bool store = false;      // store mode active for the current pass 1
@@ -54,8 +55,10 @@ struct BlockJob {
                     const std::vector<double> &cre, const std::vector<double> &cim, int cstride, hipStream_t st);
   // copies the host descriptor to the device copy used by solo launches
   hipError_t sync_desc(hipStream_t st);
-  // basis table: ring mode, or store mode with chunks covering blocks
-  // 0 .. kneed (false: memory did not allow it)
+  // basis table: ring mode (no stored basis, FP64 or FP32), or store mode
+  // with chunks covering blocks 0 .. kneed (false: memory did not allow it);
+  // chunks hold FP64 blocks (qtab) or, for a mixed-precision job, FP32 ones
+  // (q32tab)
   hipError_t set_ring(hipStream_t st);
   bool grow_store(int kneed, hipStream_t st);
   // keep: the chunks go to the device's pool of idle chunks; else they are freed
@@ -80,12 +83,17 @@ class BEngine {
   // jobs whose pass 2 is complete
   hipError_t poll(std::vector<BlockJob *> *finished);
   void remove(BlockJob *j);
+  // a finished job whose moments came from a stored basis runs the second
+  // pass (regenerating its basis in FP64) and accumulates its moments again
+  // from the coefficients it already has (the backward solution works in
+  // place on the histories and runs once)
+  hipError_t regenerate(BlockJob *j) { return enter_pass2(j, false); }
   size_t active() const { return p1_.size() + p2_.size(); }
   int64_t clock() const { return clock_; }
 
  private:
   hipError_t rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &dt, BBatch &b);
-  hipError_t enter_pass2(BlockJob *j);
+  hipError_t enter_pass2(BlockJob *j, bool coefficients = true);
   hipError_t finish_stored(BlockJob *j);
   hipError_t start_block(BlockJob *j, bool first);
   // Householder QR of the row-major n x Lp block src: Q into dst (may be src),

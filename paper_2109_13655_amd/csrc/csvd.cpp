@@ -206,8 +206,8 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
   if (!(p->norm_a >= 0.0)) return set_err(ctx, CSVD_EINVAL, "norm_a must be >= 0");
   if (p->solver != CSVD_SOLVER_AUTO && p->solver != CSVD_SOLVER_BLOCK && p->solver != CSVD_SOLVER_SINGLE)
     return set_err(ctx, CSVD_EINVAL, "solver must be CSVD_SOLVER_AUTO, CSVD_SOLVER_BLOCK or CSVD_SOLVER_SINGLE");
-  if (p->solver == CSVD_SOLVER_BLOCK && (pad_L(p->L) > kBlockMaxLp || p->precision != CSVD_FP64))
-    return set_err(ctx, CSVD_EINVAL, "the block solver needs L <= 64 and CSVD_FP64");
+  if (p->solver == CSVD_SOLVER_BLOCK && pad_L(p->L) > kBlockMaxLp)
+    return set_err(ctx, CSVD_EINVAL, "the block solver needs L <= 64");
   if (p->keep_basis < 0) return set_err(ctx, CSVD_EINVAL, "keep_basis must be >= 0");
   if (p->cholqr_passes != 0 && p->cholqr_passes != 2)
     return set_err(ctx, CSVD_EINVAL, "cholqr_passes must be 0 or 2");
@@ -236,12 +236,15 @@ constexpr int kBlockPoll = kBlockPollSteps;
 // bases degrade gracefully there instead.
 constexpr int kBlockMinRatio = 64;
 
+// residual target of CSVD_MIXED (relative triplet residual)
+constexpr double kMixedResidTarget = 1e-6;
+
 // the block basis is at least one MFMA tile wide
 int block_Lp(int L) { return std::max(kBlockMinLp, pad_L(L)); }
 
 bool use_block(const csvd_params *p, int64_t n) {
   if (p->solver == CSVD_SOLVER_SINGLE) return false;
-  const bool fits = pad_L(p->L) <= kBlockMaxLp && p->precision == CSVD_FP64;
+  const bool fits = pad_L(p->L) <= kBlockMaxLp;
   if (p->solver == CSVD_SOLVER_BLOCK) return fits;
   return fits && n >= (int64_t)kBlockMinRatio * block_Lp(p->L);
 }
@@ -374,6 +377,7 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
                                M + 1, ctx->st));
     R.bjob->h.Kmom = Kmom;
     R.bjob->want_store = (p->keep_basis != 0);
+    R.bjob->mixed = (p->precision == CSVD_MIXED);
     R.bjob->store_cap = (p->keep_basis >= 2) ? p->keep_basis : 0;
     R.bjob->h.onepass_rho = (p->cholqr_passes == 2) ? 0.0 : kOnePassRho;
     // the deflation test of the basis is relative to ||A^T A||
@@ -985,8 +989,10 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   int rc = run_begin(*R, ctx, a, b, p, V_in, W, mixed);
   if (rc) return rc;
   KernelTimer timer;
+  std::unique_ptr<BEngine> beng;
   if (R->block) {
-    BEngine eng(ctx->st);
+    beng.reset(new BEngine(ctx->st));
+    BEngine &eng = *beng;
     HIPCHK(ctx, eng.init());
     HIPCHK(ctx, eng.start(R->bjob.get()));
     int64_t step = 0;
@@ -1027,6 +1033,22 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   }
   rc = run_finalize(*R);
   if (rc) return rc;
+  if (R->block && R->bjob->mixed && R->bjob->stored_last && !(ctx->info.max_triplet_resid <= kMixedResidTarget)) {
+    // FP64 refinement of a mixed-precision solve whose triplets miss the
+    // mixed target: the moments are accumulated again from the basis
+    // regenerated in FP64 (the histories and coefficients of the last round
+    // are kept), then steps 3-5 run again
+    HIPCHK(ctx, beng->regenerate(R->bjob.get()));
+    while (true) {
+      for (int q = 0; q < kBlockPoll; ++q) HIPCHK(ctx, beng->step(&timer, false));
+      std::vector<BlockJob *> fin;
+      HIPCHK(ctx, beng->poll(&fin));
+      if (!fin.empty()) break;
+    }
+    rc = run_finalize(*R);
+    if (rc) return rc;
+    ctx->info.mixed_refined = 1;
+  }
   if (p->check_solves) {
     rc = check_solves(*R);
     if (rc) return rc;
@@ -1349,6 +1371,10 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
         runs[i].reset();
         continue;
       }
+      // a batch keeps FP64 stored bases: the FP64 refinement of a mixed
+      // solve needs the engine after the epilogue, which a batch runs on
+      // worker threads
+      runs[i]->bjob->mixed = false;
       owner[runs[i]->bjob.get()] = i;
       if (eng.start(runs[i]->bjob.get()) != hipSuccess) return CSVD_EDEVICE;
     }

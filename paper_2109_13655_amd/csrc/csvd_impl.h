@@ -130,13 +130,27 @@ struct BJobDesc {
   double *beta0;                   // Lp column norms of Vpad
   double *F;                       // Kcap x (Kmom L) x Lp moment coefficients (column-major per step)
   double *Sout;                    // npad x (Kmom L) column-major moments
+  // mixed precision (CSVD_MIXED): the basis blocks for the moments are kept
+  // as FP32 copies, block k at Q32tab[k / kStoreChunk] + (k mod kStoreChunk)
+  // n Lp, while the recurrence reads its FP64 blocks from the ring
+  float *const *Q32tab;
+  int store32;                     // 1: gamma also writes the FP32 copy of Q_{k+1}
 };
+
+constexpr int kStoreChunk = 64;  // basis blocks per allocation of a stored basis
 
 // Q_k of a block job (ring slot, or the stored basis)
 __device__ __forceinline__ GLB double *qblock(const BJobDesc &J, int k) {
   typedef GLB double *gptr;
   const GLB gptr *tab = (const GLB gptr *)(J.Qtab);
   return tab[(k / J.qC) % J.qT] + (int64_t)(k % J.qC) * J.n * J.Lp;
+}
+
+// FP32 copy of Q_k (mixed-precision stored basis)
+__device__ __forceinline__ GLB float *q32block(const BJobDesc &J, int k) {
+  typedef GLB float *gptr;
+  const GLB gptr *tab = (const GLB gptr *)(J.Q32tab);
+  return tab[k / kStoreChunk] + (int64_t)(k % kStoreChunk) * J.n * J.Lp;
 }
 
 struct BBatch {
@@ -160,9 +174,12 @@ constexpr double kOnePassRho = 1.5;  // one Cholesky pass when ||R1||_F ||R1^-1|
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);
 hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st);
-// S += sum_{b < T} Q_{k0+b} F_{k0+b} for one job (second pass): the basis
-// blocks are read from the ring, F from the coefficient history
+// S += sum_{b < T} Q_{k0+b} F_{k0+b} for one job: the basis blocks are read
+// from the ring or the stored basis (its FP32 copies when hj.store32), F from
+// the coefficient history
 hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st);
+// FP32 copy of block kb of the basis (qblock -> q32block) of one job
+hipError_t launch_b_store32(const BJobDesc &hj, int kb, hipStream_t st);
 // Tall kernels of one block step (see k_bstep.hip).  mode 0 (alpha): W' =
 // W - Q_{k-1} B_k^T and (grams = 1) the partial Gram matrix Q_k^T W'; mode 1
 // (beta): partial Gram matrices of W2 = W' - Q_k P; mode 2 (gamma0): partial

@@ -16,6 +16,8 @@
 // the moment coefficients F_k = sum_s 2 Re(c_sk Y_{s,k}) are formed, and
 // S += Q_k F_k is accumulated from the stored basis, or from a second pass
 // that regenerates Q_k bit for bit.
+#include <algorithm>
+
 #include "csvd_impl.h"
 
 namespace csvd {
@@ -58,6 +60,7 @@ __device__ __forceinline__ double2 cdivb(double2 a, double2 b) {
 // right-hand sides).
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ v4d mfma4b(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -550,7 +553,9 @@ constexpr int kMomWR = 1;             // 16-row tiles per wave
 constexpr int kMomOcc = 3;            // workgroups per CU the registers are sized for
 constexpr int kMomCols = 96;          // result columns per workgroup
 
-template <int LP, int WR, int OCC, int COLS>
+// QT = float: the basis blocks come from the FP32 copies of a mixed-precision
+// stored basis and are widened to FP64 as they are loaded (same products).
+template <int LP, int WR, int OCC, int COLS, typename QT>
 __global__ __launch_bounds__(kThreads, OCC) void b_moments(BJobDesc J, int k0, int T) {
   static_assert(LP % kMomKC == 0, "chunks of 16 contraction indices");
   constexpr int NTL = COLS / 16, NCH = LP / kMomKC;
@@ -600,19 +605,36 @@ __global__ __launch_bounds__(kThreads, OCC) void b_moments(BJobDesc J, int k0, i
     }
   };
   auto load_q = [&](int g, double (&x)[WR][4]) {
-    const GLB double *__restrict__ Qk = qblock(J, k0 + g / NCH) + (g % NCH) * kMomKC + 4 * q;
+    if constexpr (sizeof(QT) == 4) {
+      const GLB float *__restrict__ Qk = q32block(J, k0 + g / NCH) + (g % NCH) * kMomKC + 4 * q;
 #pragma unroll
-    for (int r = 0; r < WR; ++r) {
-      const int64_t row = rb + 16 * (w * WR + r) + rl;
-      if (row < n) {
-        const GLB v2d *p = reinterpret_cast<const GLB v2d *>(Qk + row * LP);
-        const v2d x0 = p[0], x1 = p[1];
-        x[r][0] = x0.x;
-        x[r][1] = x0.y;
-        x[r][2] = x1.x;
-        x[r][3] = x1.y;
-      } else {
-        x[r][0] = x[r][1] = x[r][2] = x[r][3] = 0.0;
+      for (int r = 0; r < WR; ++r) {
+        const int64_t row = rb + 16 * (w * WR + r) + rl;
+        if (row < n) {
+          const v4f x0 = *reinterpret_cast<const GLB v4f *>(Qk + row * LP);
+          x[r][0] = (double)x0.x;
+          x[r][1] = (double)x0.y;
+          x[r][2] = (double)x0.z;
+          x[r][3] = (double)x0.w;
+        } else {
+          x[r][0] = x[r][1] = x[r][2] = x[r][3] = 0.0;
+        }
+      }
+    } else {
+      const GLB double *__restrict__ Qk = qblock(J, k0 + g / NCH) + (g % NCH) * kMomKC + 4 * q;
+#pragma unroll
+      for (int r = 0; r < WR; ++r) {
+        const int64_t row = rb + 16 * (w * WR + r) + rl;
+        if (row < n) {
+          const GLB v2d *p = reinterpret_cast<const GLB v2d *>(Qk + row * LP);
+          const v2d x0 = p[0], x1 = p[1];
+          x[r][0] = x0.x;
+          x[r][1] = x0.y;
+          x[r][2] = x1.x;
+          x[r][3] = x1.y;
+        } else {
+          x[r][0] = x[r][1] = x[r][2] = x[r][3] = 0.0;
+        }
       }
     }
   };
@@ -677,11 +699,40 @@ hipError_t launch_b_moments(const BJobDesc &hj, int k0, int T, hipStream_t st) {
   constexpr int ROWS = 64 * kMomWR, C = kMomCols;
   const int64_t tiles8 = (hj.n + 8 * ROWS - 1) / (8 * ROWS) * 8;  // row tiles padded to a multiple of 8
   const dim3 g((unsigned)(tiles8 * ((KL + C - 1) / C)));
-  switch (hj.Lp) {
-    case 16: hipLaunchKernelGGL((b_moments<16, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
-    case 32: hipLaunchKernelGGL((b_moments<32, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
-    default: hipLaunchKernelGGL((b_moments<64, kMomWR, kMomOcc, C>), g, dim3(kThreads), 0, st, hj, k0, T); break;
+#define CSVD_MOM(LPV, QTV) \
+  hipLaunchKernelGGL((b_moments<LPV, kMomWR, kMomOcc, C, QTV>), g, dim3(kThreads), 0, st, hj, k0, T)
+  if (hj.store32) {
+    switch (hj.Lp) {
+      case 16: CSVD_MOM(16, float); break;
+      case 32: CSVD_MOM(32, float); break;
+      default: CSVD_MOM(64, float); break;
+    }
+  } else {
+    switch (hj.Lp) {
+      case 16: CSVD_MOM(16, double); break;
+      case 32: CSVD_MOM(32, double); break;
+      default: CSVD_MOM(64, double); break;
+    }
   }
+#undef CSVD_MOM
+  return hipGetLastError();
+}
+
+// FP32 copy of one basis block (the blocks gamma does not write: Q_0 and the
+// Householder-orthonormalised blocks of robust steps), rounded to nearest
+__global__ void b_store32(BJobDesc J, int kb) {
+  const GLB double *__restrict__ src = qblock(J, kb);
+  GLB float *__restrict__ dst = q32block(J, kb);
+  const int64_t cnt = (int64_t)J.n * J.Lp;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+hipError_t launch_b_store32(const BJobDesc &hj, int kb, hipStream_t st) {
+  if (!hj.store32) return hipSuccess;
+  const int64_t cnt = (int64_t)hj.n * hj.Lp;
+  const unsigned grid = (unsigned)std::min<int64_t>((cnt + kThreads - 1) / kThreads, 4096);
+  hipLaunchKernelGGL(b_store32, dim3(grid), dim3(kThreads), 0, st, hj, kb);
   return hipGetLastError();
 }
 

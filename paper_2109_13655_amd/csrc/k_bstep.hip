@@ -133,6 +133,21 @@ __device__ __forceinline__ void store_dl(GLB double *__restrict__ X, int64_t row
   }
 }
 
+// the same rows rounded to FP32 (the stored basis of mixed precision)
+template <int LP>
+__device__ __forceinline__ void store_dl32(GLB float *__restrict__ X, int64_t row0, int64_t n, const v4d (&D)[4]) {
+  constexpr int NT = LP / 16;
+  const int l = threadIdx.x & 63, rl = l & 15, q = l >> 4;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t row = row0 + q + 4 * v;
+      if (row < n) X[row * LP + 16 * nt + rl] = (float)D[nt][v];
+    }
+  }
+}
+
 __device__ __forceinline__ void zero4(v4d (&D)[4]) {
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) D[nt] = v4d{0.0, 0.0, 0.0, 0.0};
@@ -317,6 +332,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
     __builtin_amdgcn_sched_barrier(0);
     panel_mm<LP>(Qc, r0, n, S2, D);
     store_dl<LP>(Qn, r0, n, D);
+    if (J.store32) store_dl32<LP>(q32block(J, k + 1), r0, n, D);  // mixed precision: FP32 copy
   }
 }
 

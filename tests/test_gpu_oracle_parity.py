@@ -185,24 +185,28 @@ def test_headline_shape_known_spectrum_count():
     np.testing.assert_allclose(AV, U[rows] * sig[None, :], rtol=0, atol=1e-8 * nA)
 
 
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_SINGLE, cs.CSVD_SOLVER_BLOCK])
 @pytest.mark.parametrize("transform", [cs.CSVD_PLAIN, cs.CSVD_EXP])
-def test_mixed_precision_against_oracle(transform):
-    """CSVD_MIXED against the FP64 oracle: same count as the oracle and the
-    exact spectrum, values to 1e-6 and residuals within the 1e-6 target of
-    that mode."""
+def test_mixed_precision_against_oracle(transform, solver):
+    """CSVD_MIXED against the FP64 oracle, on both solvers (the block solver
+    with its FP32 stored basis): same count as the oracle and the exact
+    spectrum, values to 1e-6 and residuals within the 1e-6 target of that
+    mode."""
     I = _mid_problem()
     V = synth.v_in(I.n, 8, 23)
     ctx = make_ctx(I)
     try:
         p = cs.csvd_params_default(L=8, M=4, N=16, ell=2, norm_a=1.0, transform=transform,
-                                   precision=cs.CSVD_MIXED)
+                                   precision=cs.CSVD_MIXED, solver=solver)
         st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
         info = cs.csvd_get_info(ctx)
         sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
     finally:
         cs.csvd_destroy(ctx)
     say("mixed: solver", info.solver, "status", st, "t_hat", sig.size, "max resid", res.max() if res.size else None)
-    assert st == cs.CSVD_OK
+    assert st == cs.CSVD_OK and info.solver == solver
+    if solver == cs.CSVD_SOLVER_BLOCK:
+        assert info.basis_stored == 1
     o = method.ss_svd(I, I.a, I.b, V, 8, 4, 16, ell=2, transform=transform)
     exact = np.sort(I.sigma[(I.sigma >= I.a) & (I.sigma <= I.b)])
     assert sig.size == o["sigma"].size == exact.size
@@ -255,3 +259,48 @@ def test_one_live_solve_per_context():
     finally:
         cs.csvd_server_destroy(srv)
         cs.csvd_destroy(ctx)
+
+
+def test_block_mixed_stored_basis_and_its_fallback():
+    """The block solver in mixed precision on the 64-wide path (random sparse
+    9216 x 4608, L = 64): the dense truth's count and values to 1e-9 and
+    residuals below the 1e-6 target of mixed precision.  Here the basis (112
+    blocks of 64 for n = 4608) is far from orthogonal, the moments from its
+    FP32 copies miss the target (1.8e-6 measured), and the FP64 refinement
+    (moments again from the basis regenerated in FP64) makes the result the
+    FP64 solver's.  Capping the stored basis (keep_basis = 40) sends the
+    solve to the FP64 ring and a second pass after 40 blocks: the FP64
+    solver's result without a stored basis, bit for bit."""
+    I = synth.random_sparse(9216, 4608, 10, config=96)
+    A = I.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    a, b = synth.interval_by_count(ev, ev.size // 2, 24)
+    s_t, U_t, V_t, sall = truth.dense_truth(I, a, b)
+    V = synth.v_in(I.n, 64, 25)
+    ctx = make_ctx(I)
+    try:
+        out = {}
+        for name, prec, keep in (("mixed", cs.CSVD_MIXED, 1), ("mixed_cap", cs.CSVD_MIXED, 40),
+                                 ("fp64_ring", cs.CSVD_FP64, 0)):
+            p = cs.csvd_params_default(L=64, M=4, N=16, precision=prec, keep_basis=keep)
+            st = cs.csvd_solve_interval(ctx, a, b, p, V)
+            info = cs.csvd_get_info(ctx)
+            say(name, "status", st, "steps", info.iterations, "stored", info.basis_stored, "t_hat", info.t_hat,
+                "max resid", info.max_triplet_resid)
+            assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK and info.L_padded == 64
+            assert info.basis_stored == (name == "mixed")
+            if name == "mixed":
+                refined = info.mixed_refined
+            out[name] = cs.csvd_get_triplets(ctx, I.m, I.n) + (cs.csvd_get_moment(ctx, 1, I.n, 64),)
+    finally:
+        cs.csvd_destroy(ctx)
+    sig, U, Vv, res, _ = out["mixed"]
+    assert sig.size == s_t.size == 24
+    np.testing.assert_allclose(sig, s_t, rtol=1e-9)
+    r_host = check_device_residuals(I, sig, U, Vv, res, sall[0])
+    assert r_host.max() <= 1e-6
+    if refined:
+        for x, y in zip(out["mixed"], out["fp64_ring"]):
+            assert np.array_equal(x, y)
+    for x, y in zip(out["mixed_cap"], out["fp64_ring"]):
+        assert np.array_equal(x, y)
