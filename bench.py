@@ -56,6 +56,20 @@ def workload(name):
         a, b, lq, dens = synth.interval_from_sample(m, n, 10, 64, config=2)
         return dict(I=I, a=a, b=b, L=64, M=8, N=32, ell=1, norm_a=0.0,
                     desc=f"random_sparse_{m}x{n}_10nnz_per_col_interval_64_near_median")
+    if name == "c5":
+        m, n = 2000000, 1000000
+        I = synth.zipf_rows(m, n, config=5)
+        a, b, lq, dens = synth.interval_from_zipf_sample(m, n, 128, config=5)
+        return dict(I=I, a=a, b=b, L=128, M=8, N=32, ell=1, norm_a=0.0,
+                    desc=f"zipf_rows_{m}x{n}_alpha1.8_mean20nnz_interval_128_near_median")
+    if name == "c2big":
+        # the c2 recipe at 1.6x the size: an FP64 stored basis (about 430 GB)
+        # no longer fits one GPU, an FP32 one (about 215 GB) does
+        m, n = 320000, 160000
+        I = synth.random_sparse(m, n, 10, config=2, instance=1)
+        a, b, lq, dens = synth.interval_from_sample(m, n, 10, 64, config=2)
+        return dict(I=I, a=a, b=b, L=64, M=8, N=32, ell=1, norm_a=0.0,
+                    desc=f"random_sparse_{m}x{n}_10nnz_per_col_interval_64_near_median")
     raise SystemExit(f"unknown config {name}")
 
 
@@ -362,6 +376,78 @@ def bench_c4(args, cs, torch):
     print(json.dumps(out), flush=True)
 
 
+def bench_c5(args, cs, torch):
+    """Large power-law case at full shape: m = 2e6, n = 1e6, Zipf(1.8) row
+    lengths (mean 20 nonzeros, rows up to 42,207), L = 128 (two column groups
+    of 64), N = 32, M = 8, mixed precision.  A full solve needs tens of
+    thousands of block steps; this run caps the steps (--max-iters, default
+    200), measures the step and the sparse products at this working set
+    (tables of 0.5 and 1 GB, beyond the 256 MB Infinity Cache), certifies
+    the extracted triplets with the oracle's host FP64 residuals and states
+    the projection of a full solve from the measured step time."""
+    import numpy as np
+    import synth
+    from oracle import truth
+    t0 = time.perf_counter()
+    W = workload("c5")
+    I = W["I"]
+    log("c5:", W["desc"], "nnz", I.nnz, "generated in", round(time.perf_counter() - t0, 1), "s; interval",
+        W["a"], W["b"])
+    steps = args.max_iters or 200
+    ctx = cs.csvd_create(I.m, I.n, I.rowptr, I.colidx, I.vals)
+    p = cs.csvd_params_default(L=W["L"], M=W["M"], N=W["N"], ell=1, precision=cs.CSVD_MIXED, max_iters=steps)
+    V = synth.v_in(I.n, W["L"], 5, 0)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    st = cs.csvd_solve_interval(ctx, W["a"], W["b"], p, V)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - s0
+    info = cs.csvd_get_info(ctx)
+    log(f"capped solve: {wall:.2f}s status {st} steps {info.iterations} groups {info.column_groups} "
+        f"t_hat {info.t_hat} rank {info.rank} phases {info.t_solve_ms:.0f}/{info.t_lowrank_ms:.0f}/"
+        f"{info.t_qr_ms:.0f}/{info.t_extract_ms:.0f} ms")
+    sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+    cs.csvd_destroy(ctx)
+    nA = truth.sparse_norm2_lower(I.rowptr, I.colidx, I.vals, I.m, I.n, iters=30)
+    cert = truth.sparse_triplet_residuals(I.rowptr, I.colidx, I.vals, I.m, I.n, sig, U, Vv, nA) if sig.size else \
+        np.zeros(0)
+    K = int(info.iterations)
+    # one block step (both column groups, one launch per stage): the sampled
+    # durations of the two sparse products and of the rest of the step
+    step_ms = info.spmm_a_ms + info.spmm_at_ms + info.rest_ms
+    rl = roofline(info, "c5")
+    groups = int(info.column_groups)
+    # projection: block steps of a full solve from the c2 measurement (3368
+    # steps at n / Lp = 1562, i.e. 2.16 n / Lp), two passes (no basis store of
+    # that size fits), the measured time per step
+    k_full = 2.16 * I.n / 64
+    out = {
+        "metric": "c5 capped-step run: ms per block step and SpMM HBM GB/s at full shape; projected full solve",
+        "value": step_ms, "unit": "ms/step", "n_gpus": 1, "steps": K, "warmup": 0,
+        "ms_per_step": step_ms, "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": W["desc"], "m": I.m, "n": I.n, "nnz": I.nnz, "interval": [W["a"], W["b"]],
+                   "N": W["N"], "L": W["L"], "M": W["M"], "precision": "mixed", "max_iters": steps},
+        "status": st, "column_groups": int(info.column_groups), "basis_stored": bool(info.basis_stored),
+        "phase_ms": {"solve": info.t_solve_ms, "lowrank": info.t_lowrank_ms, "qr": info.t_qr_ms,
+                     "extract": info.t_extract_ms},
+        "wall_s": wall, "roofline": rl,
+        "spmm_a_ms": info.spmm_a_ms, "spmm_at_ms": info.spmm_at_ms,
+        "rest_of_step_ms": info.rest_ms,
+        "spmm_gather_gbs": 2.0 * groups * I.nnz * 512 / ((info.spmm_a_ms + info.spmm_at_ms) * 1e-3) / 1e9
+        if info.spmm_a_ms > 0 else None,
+        "setup_and_moments_ms": info.t_solve_ms - K * step_ms,
+        "certificate": {"t_hat": int(sig.size), "max_rel_residual_host_fp64": float(cert.max()) if cert.size else None,
+                        "norm_a_lower": nA, "note": "capped run: the shifted solves have not converged"},
+        "gather_ceiling_ms": {"A": cs.csvd_probe_gather(I.n, 0, I.m, round(I.nnz / I.m), seed=3, reps=3) * groups,
+                              "At": cs.csvd_probe_gather(I.m, 0, I.n, round(I.nnz / I.n), seed=4, reps=3) * groups},
+        "projection": {"block_steps": k_full, "passes": 2, "solve_s": 2 * k_full * step_ms / 1e3,
+                       "basis": "steps from the c2 ratio 2.16 n / Lp; two passes since no stored basis of that "
+                                "size fits"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -407,6 +493,8 @@ def main():
     if args.config == "c4":
         args.pool = args.pool or 8
         return bench_c4(args, cs, torch)
+    if args.config == "c5":
+        return bench_c5(args, cs, torch)
     W = workload(args.config)
     I = W["I"]
     log("workload", W["desc"], "nnz", I.nnz, "interval", W["a"], W["b"])
@@ -475,6 +563,7 @@ def main():
         "deflated": int(info.deflated),
         "one_pass_steps": int(info.one_pass_steps),
         "basis_stored": bool(info.basis_stored),
+        "mixed_refined": bool(info.mixed_refined), "mixed_resid_fp32": info.mixed_resid_fp32,
         "converged": bool(info.converged),
         "status": status,
         "phase_ms": {"solve": info.t_solve_ms, "lowrank": info.t_lowrank_ms, "qr": info.t_qr_ms,

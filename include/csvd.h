@@ -86,7 +86,9 @@ typedef struct {
                           /* (per-column solver; the block solver keeps no per-shift    */
                           /* solutions and reports NaN)                                  */
   int32_t solver;         /* CSVD_SOLVER_BLOCK: one block Lanczos basis of width L (padded */
-                          /* to a power of two <= 64) for all shifts (L > 64: CSVD_EINVAL); */
+                          /* to a power of two <= 64) for all shifts; a wider L runs as   */
+                          /* independent groups of <= 64 columns stepped together        */
+                          /* (csvd_solve_interval only; batches and servers need L <= 64) */
                           /* CSVD_SOLVER_SINGLE: one Lanczos basis per column with        */
                           /* windowed per-shift updates (any L <= 256);                    */
                           /* CSVD_SOLVER_AUTO: BLOCK when it applies and n >= 64 x padded  */
@@ -179,10 +181,15 @@ typedef struct {
                              /* over 16 basis blocks (sampled)                          */
   int32_t svd_sweeps_exhausted; /* 1 if a one-sided Jacobi SVD of step 3 or 5 stopped at */
                              /* its limit of 60 sweeps (the solve returns CSVD_ENOTCONV) */
+  int32_t column_groups;     /* block solver: independent column groups of at most 64     */
+                             /* columns that L was split into (1 when L <= 64)            */
   int32_t mixed_refined;     /* CSVD_MIXED, block solver: 1 if the triplets from the FP32  */
                              /* stored basis missed the 1e-6 residual target and the      */
                              /* moments were accumulated again from the basis regenerated */
                              /* in FP64 (steps 3-5 then ran again)                         */
+  double  mixed_resid_fp32;  /* CSVD_MIXED with an FP32 stored basis: the largest relative */
+                             /* triplet residual of the result from the FP32 basis (before */
+                             /* any refinement); 0 otherwise                               */
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);

@@ -38,10 +38,46 @@ void release_idle_chunks() {
 
 static int lp_bit(int Lp) { return Lp == 16 ? 1 : (Lp == 32 ? 2 : 4); }
 
+hipError_t LongRows::build(const std::vector<int> &rowptr, hipStream_t st) {
+  std::vector<int> b, e, r, ls(1, 0);
+  nnz_long = 0;
+  for (size_t i = 0; i + 1 < rowptr.size(); ++i) {
+    const int s0 = rowptr[i], s1 = rowptr[i + 1];
+    if (s1 - s0 <= kLongRow) continue;
+    r.push_back((int)i);
+    for (int p = s0; p < s1; p += kLongRow) {
+      b.push_back(p);
+      e.push_back(std::min(p + kLongRow, s1));
+    }
+    ls.push_back((int)b.size());
+    nnz_long += s1 - s0;
+  }
+  nseg = (int)b.size();
+  nlong = (int)r.size();
+  hipError_t err;
+  if ((err = sgb.alloc(sizeof(int) * std::max(nseg, 1))) != hipSuccess) return err;
+  if ((err = sge.alloc(sizeof(int) * std::max(nseg, 1))) != hipSuccess) return err;
+  if ((err = lrow.alloc(sizeof(int) * std::max(nlong, 1))) != hipSuccess) return err;
+  if ((err = lseg.alloc(sizeof(int) * (nlong + 1))) != hipSuccess) return err;
+  if (nseg > 0) {
+    if ((err = hipMemcpyAsync(sgb.p, b.data(), sizeof(int) * nseg, hipMemcpyHostToDevice, st)) != hipSuccess) return err;
+    if ((err = hipMemcpyAsync(sge.p, e.data(), sizeof(int) * nseg, hipMemcpyHostToDevice, st)) != hipSuccess) return err;
+    if ((err = hipMemcpyAsync(lrow.p, r.data(), sizeof(int) * nlong, hipMemcpyHostToDevice, st)) != hipSuccess)
+      return err;
+  }
+  if ((err = hipMemcpyAsync(lseg.p, ls.data(), sizeof(int) * (nlong + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
+    return err;
+  return hipStreamSynchronize(st);  // the host vectors are temporaries
+}
+
 // Tiles of the block sparse products: rows with few nonzeros (G = 1) are
 // handled four columns per lane, kThreads / (Lp / 4) rows per tile.
-static Tiling block_tiling(int64_t rows, int64_t nnz, int Lp) {
-  Tiling t = tiling_for(rows, nnz, Lp);
+// The lane split G follows the mean length of the rows the tiles compute
+// (rows longer than kLongRow are summed from segments); the tiles cover all
+// rows.
+static Tiling block_tiling(int64_t rows, int64_t nnz, int Lp, int64_t long_rows = 0, int64_t long_nnz = 0) {
+  const int64_t sr = std::max<int64_t>(rows - long_rows, 1);
+  Tiling t = tiling_for(rows, (nnz - long_nnz) * rows / sr, Lp);
   if (t.G == 1) {
     t.E = 1;
     t.rpt = kThreads * 4 / Lp;
@@ -81,7 +117,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
                             const double *vaT, int64_t m, int64_t n, int64_t nnz, int L, int Lp, int S, int Kcap_,
                             int Kmom, double tol, const std::vector<double> &sre, const std::vector<double> &sim,
                             const std::vector<double> &cre, const std::vector<double> &cim, int cstride,
-                            hipStream_t st) {
+                            hipStream_t st, const LongRows *lr) {
   Kcap = Kcap_;
   const int64_t L2 = (int64_t)Lp * Lp;
   hipError_t e = mem.alloc(bytes_needed(m, n, nnz, Lp, S, Kcap, L, Kmom));
@@ -99,7 +135,10 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.rp = rp; J.ci = ci; J.va = va; J.rpT = rpT; J.ciT = ciT; J.vaT = vaT;
   J.m = (int)m; J.n = (int)n; J.Lp = Lp; J.lgLp = ilog2i(Lp); J.L = L; J.S = S;
   J.npad = (int)round_up(n, kRowPad);
-  const Tiling t1 = block_tiling(m, nnz, Lp), t2 = block_tiling(n, nnz, Lp);
+  // the row tiles hold the rows up to kLongRow nonzeros; longer rows are
+  // summed from segments (lr[0]: rows of A, lr[1]: rows of A^T)
+  const Tiling t1 = block_tiling(m, nnz, Lp, lr ? lr[0].nlong : 0, lr ? lr[0].nnz_long : 0);
+  const Tiling t2 = block_tiling(n, nnz, Lp, lr ? lr[1].nlong : 0, lr ? lr[1].nnz_long : 0);
   J.G1 = t1.G; J.lgG1 = t1.lgG; J.E1 = t1.E; J.rpt1 = t1.rpt; J.tiles1 = t1.tiles;
   J.G2 = t2.G; J.lgG2 = t2.lgG; J.E2 = t2.E; J.rpt2 = t2.rpt; J.tiles2 = t2.tiles;
   J.nchunk = (int)((n + kBlockPanel - 1) / kBlockPanel);
@@ -131,6 +170,19 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.flags = (int *)take(4 * 4);
   J.F = (double *)take(8 * (size_t)((int64_t)Kcap * Kmom * L * Lp));
   if (off > mem.bytes) return hipErrorOutOfMemory;
+  J.tlong = lr ? kLongRow : 0x7fffffff;  // without segment tables every row is tiled
+  if (lr) {
+    J.sgb1 = lr[0].sgb.as<int>(); J.sge1 = lr[0].sge.as<int>(); J.lrow1 = lr[0].lrow.as<int>();
+    J.lseg1 = lr[0].lseg.as<int>(); J.nseg1 = lr[0].nseg; J.nlong1 = lr[0].nlong;
+    J.sgb2 = lr[1].sgb.as<int>(); J.sge2 = lr[1].sge.as<int>(); J.lrow2 = lr[1].lrow.as<int>();
+    J.lseg2 = lr[1].lseg.as<int>(); J.nseg2 = lr[1].nseg; J.nlong2 = lr[1].nlong;
+  }
+  if (J.nseg1 + J.nseg2 > 0) {
+    e = seg_part.alloc(8 * (size_t)(J.nseg1 + J.nseg2) * Lp);
+    if (e != hipSuccess) return e;
+    J.sgp1 = seg_part.as<double>();
+    J.sgp2 = J.sgp1 + (size_t)J.nseg1 * Lp;
+  }
   // shifts and moment coefficients
   e = d_shift.alloc(sizeof(double2) * S);
   if (e != hipSuccess) return e;
@@ -163,6 +215,8 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   if (e != hipSuccess) return e;
   J.Q32tab = d_q32tab.as<float *>();
   J.store32 = 0;
+  J.sL = L;
+  J.soff = 0;
   if ((e = set_ring(st)) != hipSuccess) return e;
   // solo tables: one job
   e = d_desc.alloc(sizeof(BJobDesc));
@@ -391,6 +445,18 @@ hipError_t BEngine::robust_finish(std::vector<BlockJob *> &v, bool first_pass) {
   return hipSuccess;
 }
 
+// zero the job's columns of Sout (all of it, or the Kmom column ranges of a
+// column group)
+hipError_t BEngine::clear_moments(const BJobDesc &J) {
+  if (J.sL == J.L && J.soff == 0)
+    return hipMemsetAsync(J.Sout, 0, 8 * (size_t)J.npad * J.Kmom * J.L, st_);
+  for (int k = 0; k < J.Kmom; ++k) {
+    hipError_t e = hipMemsetAsync(J.Sout + ((size_t)k * J.sL + J.soff) * J.npad, 0, 8 * (size_t)J.npad * J.L, st_);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Store mode: the basis is complete in memory; solve the projected systems
 // backwards, form the coefficients and accumulate the moments from the stored
 // blocks in the same windows as the second pass would (same bits).
@@ -399,7 +465,7 @@ hipError_t BEngine::finish_stored(BlockJob *j) {
   hipError_t e = launch_b_backsolve(J, j->K, st_);
   if (e != hipSuccess) return e;
   if ((e = launch_b_fcoef(J, j->K, st_)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(J.Sout, 0, 8 * (size_t)J.npad * J.Kmom * J.L, st_)) != hipSuccess) return e;
+  if ((e = clear_moments(J)) != hipSuccess) return e;
   for (int k0 = 0; k0 < j->K; k0 += kMomWindow) {
     const int T = std::min(kMomWindow, j->K - k0);
     const bool timed = timer_ && T == kMomWindow;
@@ -422,7 +488,7 @@ hipError_t BEngine::enter_pass2(BlockJob *j, bool coefficients) {
     if ((e = launch_b_backsolve(J, j->K, st_)) != hipSuccess) return e;
     if ((e = launch_b_fcoef(J, j->K, st_)) != hipSuccess) return e;
   }
-  if ((e = hipMemsetAsync(J.Sout, 0, 8 * (size_t)J.npad * J.Kmom * J.L, st_)) != hipSuccess) return e;
+  if ((e = clear_moments(J)) != hipSuccess) return e;
   if ((e = hipMemsetAsync(J.Q, 0, 8 * (size_t)J.nring * J.n * J.Lp, st_)) != hipSuccess) return e;
   J.start_clock = (int)clock_;
   J.Kstop = j->K;
@@ -493,9 +559,11 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     const BBatch &b = b1_;
     if (timer && sample) timer->begin(0, st_);
     if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
+    if ((e = long_rows(p1_, 1)) != hipSuccess) return e;
     if (timer && sample) timer->end(st_);
     if (timer && sample) timer->begin(1, st_);
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
+    if ((e = long_rows(p1_, 2)) != hipSuccess) return e;
     if (timer && sample) timer->end(st_);
     if (timer && sample) timer->begin(2, st_);
     if ((e = launch_bs_tall(b, 0, 1, st_)) != hipSuccess) return e;   // W', P
@@ -535,7 +603,9 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
       }
     }
     if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
+    if ((e = long_rows(p2_, 1)) != hipSuccess) return e;
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
+    if ((e = long_rows(p2_, 2)) != hipSuccess) return e;
     if ((e = launch_bs_tall(b, 0, 0, st_)) != hipSuccess) return e;
     if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
     if ((e = robust_finish(p2_, false)) != hipSuccess) return e;
@@ -544,6 +614,17 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
   ++clock_;
   for (BlockJob *j : p1_) j->steps_total++;
   for (BlockJob *j : p2_) j->steps_total++;
+  return hipSuccess;
+}
+
+hipError_t BEngine::long_rows(const std::vector<BlockJob *> &v, int side) {
+  for (BlockJob *j : v) {
+    const BJobDesc &J = j->h;
+    const int k = (int)(clock_ - J.start_clock);
+    if (k >= J.Kstop || (side == 1 ? J.nseg1 : J.nseg2) == 0) continue;
+    hipError_t e = launch_b_spmm_long(J, side, k, st_);
+    if (e != hipSuccess) return e;
+  }
   return hipSuccess;
 }
 

@@ -23,6 +23,7 @@ void release_idle_chunks();
 struct BlockJob {
   BJobDesc h{};
   DevBuf mem, d_shift, d_cmom, d_desc, d_toff, d_qtab, d_q32tab;
+  DevBuf seg_part;  // partial rows of the long-row segments (both products)
   BBatch solo{};
   std::vector<double *> qtab;                  // host copy of the basis table
   std::vector<float *> q32tab;                 // host copy of the FP32 basis table (mixed precision)
@@ -52,7 +53,8 @@ struct BlockJob {
   hipError_t create(const int *rp, const int *ci, const double *va, const int *rpT, const int *ciT,
                     const double *vaT, int64_t m, int64_t n, int64_t nnz, int L, int Lp, int S, int Kcap, int Kmom,
                     double tol, const std::vector<double> &sre, const std::vector<double> &sim,
-                    const std::vector<double> &cre, const std::vector<double> &cim, int cstride, hipStream_t st);
+                    const std::vector<double> &cre, const std::vector<double> &cim, int cstride, hipStream_t st,
+                    const LongRows *lr = nullptr);
   // copies the host descriptor to the device copy used by solo launches
   hipError_t sync_desc(hipStream_t st);
   // basis table: ring mode (no stored basis, FP64 or FP32), or store mode
@@ -95,6 +97,7 @@ class BEngine {
   hipError_t rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &dt, BBatch &b);
   hipError_t enter_pass2(BlockJob *j, bool coefficients = true);
   hipError_t finish_stored(BlockJob *j);
+  hipError_t clear_moments(const BJobDesc &J);
   hipError_t start_block(BlockJob *j, bool first);
   // Householder QR of the row-major n x Lp block src: Q into dst (may be src),
   // optionally R (row-major Lp x Lp, zero below) and the column norms of src
@@ -102,6 +105,8 @@ class BEngine {
   // robust steps of the jobs in v after their gamma (Q_{k+1} from W3)
   hipError_t robust_finish(std::vector<BlockJob *> &v, bool first_pass);
   hipError_t launch_shift(const BBatch &b, int init);
+  // long rows of the jobs in v for one product (side 1: A, side 2: A^T)
+  hipError_t long_rows(const std::vector<BlockJob *> &v, int side);
   // The shift recurrences of the steps since the last poll, launched together
   // behind one event (they read only history entries of their own steps).
   hipError_t flush_shifts();

@@ -206,8 +206,6 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
   if (!(p->norm_a >= 0.0)) return set_err(ctx, CSVD_EINVAL, "norm_a must be >= 0");
   if (p->solver != CSVD_SOLVER_AUTO && p->solver != CSVD_SOLVER_BLOCK && p->solver != CSVD_SOLVER_SINGLE)
     return set_err(ctx, CSVD_EINVAL, "solver must be CSVD_SOLVER_AUTO, CSVD_SOLVER_BLOCK or CSVD_SOLVER_SINGLE");
-  if (p->solver == CSVD_SOLVER_BLOCK && pad_L(p->L) > kBlockMaxLp)
-    return set_err(ctx, CSVD_EINVAL, "the block solver needs L <= 64");
   if (p->keep_basis < 0) return set_err(ctx, CSVD_EINVAL, "keep_basis must be >= 0");
   if (p->cholqr_passes != 0 && p->cholqr_passes != 2)
     return set_err(ctx, CSVD_EINVAL, "cholqr_passes must be 0 or 2");
@@ -242,11 +240,12 @@ constexpr double kMixedResidTarget = 1e-6;
 // the block basis is at least one MFMA tile wide
 int block_Lp(int L) { return std::max(kBlockMinLp, pad_L(L)); }
 
-bool use_block(const csvd_params *p, int64_t n) {
+// groups_ok: L > kBlockMaxLp may run as column groups (solo solves only)
+bool use_block(const csvd_params *p, int64_t n, bool groups_ok = false) {
   if (p->solver == CSVD_SOLVER_SINGLE) return false;
-  const bool fits = pad_L(p->L) <= kBlockMaxLp;
+  const bool fits = pad_L(p->L) <= kBlockMaxLp || groups_ok;
   if (p->solver == CSVD_SOLVER_BLOCK) return fits;
-  return fits && n >= (int64_t)kBlockMinRatio * block_Lp(p->L);
+  return fits && n >= (int64_t)kBlockMinRatio * block_Lp(std::min(p->L, kBlockMaxLp));
 }
 
 }  // namespace
@@ -264,8 +263,12 @@ struct SolveRun {
   DevBuf d_coef;          // S x (M+1) moment coefficients (double2)
   std::unique_ptr<Job> job;        // single-vector solver
   bool block = false;
-  std::unique_ptr<BlockJob> bjob;  // block solver
-  std::vector<double> pad_cols;    // seeded padding columns of the block (n x (Lp - L), column-major)
+  std::unique_ptr<BlockJob> bjob;  // block solver (first column group)
+  // further column groups of the block solver: L > kBlockMaxLp columns run as
+  // independent block jobs of at most kBlockMaxLp columns each, in one engine
+  std::vector<std::unique_ptr<BlockJob>> bextra;
+  std::vector<std::vector<double>> pad_cols;  // per group: seeded padding columns (n x (Lp - Lg), column-major)
+  int gdone = 0;                   // groups whose current round has finished
   DevBuf d_Stmp;                   // S_0 of the intermediate rounds (block solver)
   int64_t iters_total = 0;
   int64_t iters_last = 0;
@@ -274,6 +277,12 @@ struct SolveRun {
   int status = CSVD_OK;
   double t_start = 0, t_solve_end = 0;
   std::vector<double> hist;  // column-0 Lanczos scalars of the first round
+  std::vector<BlockJob *> groups() const {
+    std::vector<BlockJob *> g;
+    if (bjob) g.push_back(bjob.get());
+    for (auto &x : bextra) g.push_back(x.get());
+    return g;
+  }
 };
 
 // ||A||_2 by power iteration on A^T A (60 products with one column); used to
@@ -314,25 +323,29 @@ static int estimate_norm(csvd_ctx *ctx, double *out) {
   return CSVD_OK;
 }
 
-// Uploads the padded starting block: columns 0..L-1 from V (column-major,
-// leading dimension ldv, host), padding columns from pad_cols.
+// Uploads the padded starting block of every column group: its columns
+// soff .. soff + Lg - 1 of V (column-major, leading dimension ldv, host),
+// padding columns from pad_cols.
 static int upload_vpad(SolveRun &R, const double *V, int64_t ldv) {
   csvd_ctx *ctx = R.ctx;
-  BlockJob &B = *R.bjob;
   const int64_t n = ctx->n;
-  const int L = B.h.L, Lp = B.h.Lp;
-  std::vector<double> Vp((size_t)n * Lp);
-  for (int64_t i = 0; i < n; ++i) {
-    for (int l = 0; l < L; ++l) Vp[(size_t)i * Lp + l] = V[(size_t)l * ldv + i];
-    for (int l = L; l < Lp; ++l) Vp[(size_t)i * Lp + l] = R.pad_cols[(size_t)(l - L) * n + i];
+  const std::vector<BlockJob *> gs = R.groups();
+  for (size_t g = 0; g < gs.size(); ++g) {
+    BlockJob &B = *gs[g];
+    const int L = B.h.L, Lp = B.h.Lp, l0 = B.h.soff;
+    std::vector<double> Vp((size_t)n * Lp);
+    for (int64_t i = 0; i < n; ++i) {
+      for (int l = 0; l < L; ++l) Vp[(size_t)i * Lp + l] = V[(size_t)(l0 + l) * ldv + i];
+      for (int l = L; l < Lp; ++l) Vp[(size_t)i * Lp + l] = R.pad_cols[g][(size_t)(l - L) * n + i];
+    }
+    HIPCHK(ctx, hipMemcpyAsync(B.h.Vpad, Vp.data(), 8 * Vp.size(), hipMemcpyHostToDevice, ctx->st));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
   }
-  HIPCHK(ctx, hipMemcpyAsync(B.h.Vpad, Vp.data(), 8 * Vp.size(), hipMemcpyHostToDevice, ctx->st));
-  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
   return CSVD_OK;
 }
 
 int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params *p, const double *V_host,
-              int W, bool mixed) {
+              int W, bool mixed, bool groups_ok = false) {
   R.ctx = ctx;
   int rc = check_params(ctx, a, b, p);
   if (rc) return rc;
@@ -342,7 +355,7 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
   R.spec.b = b;
   R.spec.p = *p;
   quadrature(a, b, p->N, p->M, p->alpha, p->transform, &R.spec);
-  R.spec.Lp = use_block(p, ctx->n) ? block_Lp(p->L) : pad_L(p->L);
+  R.spec.Lp = use_block(p, ctx->n, groups_ok) ? block_Lp(std::min(p->L, kBlockMaxLp)) : pad_L(p->L);
   R.spec.W = W;
   const int S = R.spec.S, M = p->M, L = p->L;
   const int64_t n = ctx->n;
@@ -365,38 +378,47 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
   }
   HIPCHK(ctx, R.d_coef.alloc(sizeof(double) * cc.size()));
   HIPCHK(ctx, hipMemcpyAsync(R.d_coef.p, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice, ctx->st));
-  R.block = use_block(p, ctx->n);
+  R.block = use_block(p, ctx->n, groups_ok);
   if (R.block) {
-    const int Lp = R.spec.Lp;
     const int Kmom = (p->ell == 1) ? M + 1 : 1;
-    const int64_t kc = std::min<int64_t>(p->max_iters, (int64_t)std::ceil(3.5 * (double)n / Lp) + 32);
-    R.bjob.reset(new BlockJob());
-    HIPCHK(ctx, R.bjob->create(ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(), ctx->rpT.as<int>(),
-                               ctx->ciT.as<int>(), ctx->vaT.as<double>(), ctx->m, n, ctx->nnz, L, Lp, S, (int)kc,
-                               M + 1, p->solve_rtol, R.spec.shift_re, R.spec.shift_im, R.spec.c_re, R.spec.c_im,
-                               M + 1, ctx->st));
-    R.bjob->h.Kmom = Kmom;
-    R.bjob->want_store = (p->keep_basis != 0);
-    R.bjob->mixed = (p->precision == CSVD_MIXED);
-    R.bjob->store_cap = (p->keep_basis >= 2) ? p->keep_basis : 0;
-    R.bjob->h.onepass_rho = (p->cholqr_passes == 2) ? 0.0 : kOnePassRho;
     // the deflation test of the basis is relative to ||A^T A||
     double na = p->norm_a;
     if (!(na > 0)) {
       int rc1 = estimate_norm(ctx, &na);
       if (rc1) return rc1;
     }
-    R.bjob->h.dscale = na * na;
     const int64_t npad = round_up(n, kRowPad);
     HIPCHK(ctx, ctx->d_S.alloc(sizeof(double) * npad * (size_t)(M + 1) * L));
-    if (p->ell > 1) {
-      HIPCHK(ctx, R.d_Stmp.alloc(sizeof(double) * npad * (size_t)L));
-      R.bjob->h.Sout = R.d_Stmp.as<double>();
-    } else {
-      R.bjob->h.Sout = ctx->d_S.as<double>();
+    if (p->ell > 1) HIPCHK(ctx, R.d_Stmp.alloc(sizeof(double) * npad * (size_t)L));
+    // column groups of at most kBlockMaxLp columns (one group when L fits)
+    const int ng = (L + kBlockMaxLp - 1) / kBlockMaxLp;
+    R.bextra.clear();
+    R.pad_cols.assign(ng, std::vector<double>());
+    for (int g = 0; g < ng; ++g) {
+      const int l0 = g * kBlockMaxLp, Lg = std::min(kBlockMaxLp, L - l0), Lp = block_Lp(Lg);
+      const int64_t kc = std::min<int64_t>(p->max_iters, (int64_t)std::ceil(3.5 * (double)n / Lp) + 32);
+      std::unique_ptr<BlockJob> B(new BlockJob());
+      HIPCHK(ctx, B->create(ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(), ctx->rpT.as<int>(),
+                            ctx->ciT.as<int>(), ctx->vaT.as<double>(), ctx->m, n, ctx->nnz, Lg, Lp, S, (int)kc,
+                            M + 1, p->solve_rtol, R.spec.shift_re, R.spec.shift_im, R.spec.c_re, R.spec.c_im,
+                            M + 1, ctx->st, ctx->lr));
+      B->h.Kmom = Kmom;
+      B->want_store = (p->keep_basis != 0);
+      B->mixed = (p->precision == CSVD_MIXED);
+      B->store_cap = (p->keep_basis >= 2) ? p->keep_basis : 0;
+      B->h.onepass_rho = (p->cholqr_passes == 2) ? 0.0 : kOnePassRho;
+      B->h.dscale = na * na;
+      B->h.sL = L;
+      B->h.soff = l0;
+      B->h.Sout = (p->ell > 1) ? R.d_Stmp.as<double>() : ctx->d_S.as<double>();
+      R.pad_cols[g].assign((size_t)n * (Lp - Lg), 0.0);
+      if (Lp > Lg)
+        gaussian_block(p->seed ^ (0xA5A5F00DCAFEULL + (uint64_t)g * 0x9E3779B97F4A7C15ULL),
+                       (int64_t)R.pad_cols[g].size(), R.pad_cols[g].data());
+      if (g == 0) R.bjob = std::move(B);
+      else R.bextra.push_back(std::move(B));
     }
-    R.pad_cols.assign((size_t)n * (Lp - L), 0.0);
-    if (Lp > L) gaussian_block(p->seed ^ 0xA5A5F00DCAFEULL, (int64_t)R.pad_cols.size(), R.pad_cols.data());
+    R.gdone = 0;
     int rc2 = upload_vpad(R, V.data(), n);
     if (rc2) return rc2;
     R.round = 0;
@@ -447,25 +469,32 @@ static int harvest_job(SolveRun &R) {
 // when another round was started (the caller must re-add the job).
 static int run_after_round_block(SolveRun &R, bool *more) {
   csvd_ctx *ctx = R.ctx;
-  BlockJob &B = *R.bjob;
-  const int S = B.h.S, Lp = B.h.Lp, L = B.h.L;
-  std::vector<double> res((size_t)S * Lp);
-  HIPCHK(ctx, hipMemcpyAsync(res.data(), B.h.res, sizeof(double) * res.size(), hipMemcpyDeviceToHost, ctx->st));
-  HIPCHK(ctx, hipStreamSynchronize(ctx->st));
-  double mx = 0;
-  for (int s = 0; s < S; ++s)
-    for (int l = 0; l < L; ++l) mx = std::max(mx, res[(size_t)s * Lp + l]);
-  R.max_res_est = std::max(R.max_res_est, mx);
-  R.iters_total += B.K;
-  R.iters_last = B.K;
-  if (!B.converged) R.all_converged = false;
+  const std::vector<BlockJob *> gs = R.groups();
+  int kmax = 0;
+  for (BlockJob *Bp : gs) {
+    BlockJob &B = *Bp;
+    const int S = B.h.S, Lp = B.h.Lp, L = B.h.L;
+    std::vector<double> res((size_t)S * Lp);
+    HIPCHK(ctx, hipMemcpyAsync(res.data(), B.h.res, sizeof(double) * res.size(), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+    double mx = 0;
+    for (int s = 0; s < S; ++s)
+      for (int l = 0; l < L; ++l) mx = std::max(mx, res[(size_t)s * Lp + l]);
+    R.max_res_est = std::max(R.max_res_est, mx);
+    kmax = std::max(kmax, B.K);  // the groups step together: the round takes the longest
+    if (!B.converged) R.all_converged = false;
+  }
+  R.iters_total += kmax;
+  R.iters_last = kmax;
+  R.gdone = 0;
   *more = false;
   const csvd_params &p = R.spec.p;
   if (R.round + 1 < p.ell) {
     // eq. iter1: S_0^(nu) becomes the next right-hand side
-    const int64_t n = ctx->n, npad = B.h.npad;
+    const int L = p.L;
+    const int64_t n = ctx->n, npad = R.bjob->h.npad;
     std::vector<double> S0((size_t)npad * L);
-    HIPCHK(ctx, hipMemcpyAsync(S0.data(), B.h.Sout, sizeof(double) * S0.size(), hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(ctx, hipMemcpyAsync(S0.data(), R.d_Stmp.p, sizeof(double) * S0.size(), hipMemcpyDeviceToHost, ctx->st));
     HIPCHK(ctx, hipStreamSynchronize(ctx->st));
     int rc = upload_vpad(R, S0.data(), npad);
     if (rc) return rc;
@@ -476,10 +505,13 @@ static int run_after_round_block(SolveRun &R, bool *more) {
     HIPCHK(ctx, hipMemcpyAsync(R.d_rhs.p, Vc.data(), 8 * Vc.size(), hipMemcpyHostToDevice, ctx->st));
     HIPCHK(ctx, hipStreamSynchronize(ctx->st));
     R.round += 1;
-    B.robust_steps = kRobustSteps;  // the filtered block: first Krylov blocks by Householder QR
-    if (R.round + 1 == p.ell) {
-      B.h.Kmom = p.M + 1;
-      B.h.Sout = ctx->d_S.as<double>();
+    for (BlockJob *Bp : gs) {
+      BlockJob &B = *Bp;
+      B.robust_steps = kRobustSteps;  // the filtered block: first Krylov blocks by Householder QR
+      if (R.round + 1 == p.ell) {
+        B.h.Kmom = p.M + 1;
+        B.h.Sout = ctx->d_S.as<double>();
+      }
     }
     *more = true;
   }
@@ -786,13 +818,20 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   const double Lp = R.spec.Lp;
   int64_t nnz = ctx->nnz;
   if (R.block) {
-    // one A product: A, x gather (n x Lp), y write (m x Lp); one A^T product:
-    // A^T, u gather (m x Lp), w write (n x Lp)
-    info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
-    info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + n);
-    info.deflated = R.bjob->deflated_last;
+    // one A product launch: per column group A, x gather (n x Lp), y write
+    // (m x Lp); one A^T product launch: per group A^T, u gather (m x Lp), w
+    // write (n x Lp)
+    info.spmm_a_bytes = info.spmm_at_bytes = 0.0;
+    info.basis_stored = 1;
+    for (BlockJob *B : R.groups()) {
+      const double lp = B->h.Lp;
+      info.spmm_a_bytes += nnz * 12.0 + 4.0 * (m + 1) + 8.0 * lp * (n + m);
+      info.spmm_at_bytes += nnz * 12.0 + 4.0 * (n + 1) + 8.0 * lp * (m + n);
+      info.deflated += B->deflated_last;
+      if (!B->stored_last) info.basis_stored = 0;
+    }
     info.one_pass_steps = R.bjob->one_pass_last;
-    info.basis_stored = R.bjob->stored_last ? 1 : 0;
+    info.column_groups = (int32_t)R.groups().size();
   } else {
     info.spmm_a_bytes = nnz * 12.0 + 4.0 * (m + 1) + 8.0 * Lp * (n + m);
     info.spmm_at_bytes = nnz * 12.0 + 4.0 * (n + 1) + 8.0 * Lp * (m + 4.0 * n);
@@ -959,6 +998,17 @@ int csvd_create(csvd_ctx **out, int64_t m, int64_t n, int64_t nnz, const int32_t
                            c->st) != hipSuccess)
     return CSVD_EDEVICE;
   if (hipStreamSynchronize(c->st) != hipSuccess) return CSVD_EDEVICE;
+  // long rows of A and of A^T for the block products (segment tables)
+  {
+    std::vector<int> rph((size_t)m + 1), rpth((size_t)n + 1);
+    if (hipMemcpy(rph.data(), c->rp.p, sizeof(int) * (m + 1), hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(rpth.data(), c->rpT.p, sizeof(int) * (n + 1), hipMemcpyDeviceToHost) != hipSuccess)
+      return CSVD_EDEVICE;
+    const hipError_t e0 = c->lr[0].build(rph, c->st);
+    if (e0 != hipSuccess) return hip_code(e0);
+    const hipError_t e1 = c->lr[1].build(rpth, c->st);
+    if (e1 != hipSuccess) return hip_code(e1);
+  }
   *out = ctx.release();
   return CSVD_OK;
 }
@@ -986,26 +1036,29 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   std::unique_ptr<SolveRun> R(new SolveRun());
   const bool mixed = p && p->precision == CSVD_MIXED;
   const int W = p ? pick_window(p) : 32;
-  int rc = run_begin(*R, ctx, a, b, p, V_in, W, mixed);
+  int rc = run_begin(*R, ctx, a, b, p, V_in, W, mixed, true);
   if (rc) return rc;
   KernelTimer timer;
   std::unique_ptr<BEngine> beng;
   if (R->block) {
+    // every column group is one job of the engine; a round ends when all have
     beng.reset(new BEngine(ctx->st));
     BEngine &eng = *beng;
+    const std::vector<BlockJob *> gs = R->groups();
     HIPCHK(ctx, eng.init());
-    HIPCHK(ctx, eng.start(R->bjob.get()));
+    for (BlockJob *B : gs) HIPCHK(ctx, eng.start(B));
     int64_t step = 0;
     while (true) {
       for (int q = 0; q < kBlockPoll; ++q, ++step) HIPCHK(ctx, eng.step(&timer, (step % 8) == 3));
       std::vector<BlockJob *> fin;
       HIPCHK(ctx, eng.poll(&fin));
-      if (!fin.empty()) {
+      R->gdone += (int)fin.size();
+      if (R->gdone == (int)gs.size()) {
         bool more = false;
         rc = run_after_round(*R, &more);
         if (rc) return rc;
         if (more) {
-          HIPCHK(ctx, eng.start(R->bjob.get()));
+          for (BlockJob *B : gs) HIPCHK(ctx, eng.start(B));
           continue;
         }
         break;
@@ -1033,22 +1086,30 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   }
   rc = run_finalize(*R);
   if (rc) return rc;
-  if (R->block && R->bjob->mixed && R->bjob->stored_last && !(ctx->info.max_triplet_resid <= kMixedResidTarget)) {
+  const bool mixed_stored = R->block && R->bjob->mixed && R->bjob->stored_last;
+  const double resid_fp32 = ctx->info.max_triplet_resid;
+  if (mixed_stored && !(ctx->info.max_triplet_resid <= kMixedResidTarget)) {
     // FP64 refinement of a mixed-precision solve whose triplets miss the
     // mixed target: the moments are accumulated again from the basis
     // regenerated in FP64 (the histories and coefficients of the last round
     // are kept), then steps 3-5 run again
-    HIPCHK(ctx, beng->regenerate(R->bjob.get()));
-    while (true) {
+    int pending = 0;
+    for (BlockJob *B : R->groups())
+      if (B->stored_last) {
+        HIPCHK(ctx, beng->regenerate(B));
+        ++pending;
+      }
+    while (pending > 0) {
       for (int q = 0; q < kBlockPoll; ++q) HIPCHK(ctx, beng->step(&timer, false));
       std::vector<BlockJob *> fin;
       HIPCHK(ctx, beng->poll(&fin));
-      if (!fin.empty()) break;
+      pending -= (int)fin.size();
     }
     rc = run_finalize(*R);
     if (rc) return rc;
     ctx->info.mixed_refined = 1;
   }
+  if (mixed_stored) ctx->info.mixed_resid_fp32 = resid_fp32;
   if (p->check_solves) {
     rc = check_solves(*R);
     if (rc) return rc;
@@ -1360,7 +1421,8 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
       status[i] = CSVD_OK;
       ctxs[i]->err.clear();
       ctxs[i]->solved = false;
-      if (ctxs[i]->st != st || !use_block(&params[i], ctxs[i]->n)) {
+      if (ctxs[i]->st != st || !use_block(&params[i], ctxs[i]->n) ||
+          (params[i].solver == CSVD_SOLVER_BLOCK && pad_L(params[i].L) > kBlockMaxLp)) {
         status[i] = set_err(ctxs[i], CSVD_EINVAL, "batched problems must share the stream and the solver");
         continue;
       }
@@ -1597,6 +1659,8 @@ int csvd_server_submit(csvd_server *s, csvd_ctx *ctx, double a, double b, const 
   if (pick_window(p) != 32) return srv_err(s, CSVD_EINVAL, "served requests use the server's window (0 or 32)");
   if (ctx->st != s->st) return srv_err(s, CSVD_EINVAL, "context stream differs from the server stream");
   if (ctx->busy) return srv_err(s, CSVD_ESTATE, "the context already has a live request");
+  if (p->solver == CSVD_SOLVER_BLOCK && pad_L(p->L) > kBlockMaxLp)
+    return srv_err(s, CSVD_EINVAL, "served block solves need L <= 64 (wider L: solver AUTO or SINGLE)");
   const int64_t bytes = request_bytes(ctx, p);
   if (bytes > s->budget) return srv_err(s, CSVD_ENOMEM, "request footprint exceeds the server budget");
   const int64_t id = s->next_id++;

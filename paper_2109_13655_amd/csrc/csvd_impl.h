@@ -135,6 +135,21 @@ struct BJobDesc {
   // n Lp, while the recurrence reads its FP64 blocks from the ring
   float *const *Q32tab;
   int store32;                     // 1: gamma also writes the FP32 copy of Q_{k+1}
+  // rows with more than tlong nonzeros (A product: side 1, A^T product:
+  // side 2) are left out of the row tiles and split into segments of at
+  // most tlong nonzeros [sgb, sge); each segment's partial row goes to sgp
+  // (nseg x Lp) and the long row lrow[r] is the sum of its segments
+  // lseg[r] .. lseg[r+1]-1 added in order
+  int tlong;
+  const int *sgb1, *sge1, *lrow1, *lseg1;
+  const int *sgb2, *sge2, *lrow2, *lseg2;
+  int nseg1, nlong1, nseg2, nlong2;
+  double *sgp1, *sgp2;
+  // column group of a wider right-hand side (L > kBlockMaxLp, solved as
+  // independent groups of at most kBlockMaxLp columns): moment k of the
+  // group's column l is column k sL + soff + l of Sout (sL = L, soff = 0
+  // for a job that holds every column)
+  int sL, soff;
 };
 
 constexpr int kStoreChunk = 64;  // basis blocks per allocation of a stored basis
@@ -174,6 +189,10 @@ constexpr double kOnePassRho = 1.5;  // one Cholesky pass when ||R1||_F ||R1^-1|
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);
 hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st);
+// the long rows of one job's product at step k (side 1: U = A Q_k, side 2:
+// W = A^T U): segment partial rows, then their sums in order
+hipError_t launch_b_spmm_long(const BJobDesc &hj, int side, int k, hipStream_t st);
+constexpr int kLongRow = 128;  // rows with more nonzeros are split into segments of this many
 // S += sum_{b < T} Q_{k0+b} F_{k0+b} for one job: the basis blocks are read
 // from the ring or the stored basis (its FP32 copies when hj.store32), F from
 // the coefficient history

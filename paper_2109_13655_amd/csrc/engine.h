@@ -85,6 +85,17 @@ inline Tiling tiling_for(int64_t rows, int64_t nnz, int Lp) {
 
 
 
+// Rows of one side of the block products (A or A^T) with more than
+// kLongRow nonzeros, cut into segments of at most kLongRow nonzeros:
+// segment s covers nonzeros [sgb_s, sge_s); long row r is row lrow_r with
+// segments lseg_r .. lseg_{r+1} - 1.  Built once per matrix.
+struct LongRows {
+  DevBuf sgb, sge, lrow, lseg;
+  int nseg = 0, nlong = 0;
+  int64_t nnz_long = 0;
+  hipError_t build(const std::vector<int> &rowptr, hipStream_t st);
+};
+
 struct SolveSpec {
   double a = 0, b = 0;
   csvd_params p{};
@@ -181,6 +192,7 @@ struct csvd_ctx {
   // a server request (queued or running) or a batch holds the context: its
   // moments, triplets and info belong to that solve until it is done
   bool busy = false;
+  csvd::LongRows lr[2];              // long rows of A (0) and of A^T (1)
 };
 
 struct csvd_server;

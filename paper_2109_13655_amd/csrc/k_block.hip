@@ -686,7 +686,8 @@ __global__ __launch_bounds__(kThreads, OCC) void b_moments(BJobDesc J, int k0, i
       const int col = col0 + cg + cl;
       const int64_t row = rb + rr;
       if (col < KL && row < n) {
-        GLB double *sp = gp(J.Sout) + (int64_t)col * J.npad + row;
+        const int gcol = (col / J.L) * J.sL + J.soff + col % J.L;  // column of S (groups of a wide L)
+        GLB double *sp = gp(J.Sout) + (int64_t)gcol * J.npad + row;
         *sp += Cs[cl * CS + rr];
       }
     }

@@ -119,9 +119,33 @@ __global__ void k_spmm_rowmajor(int rows, int64_t k, const int *__restrict__ rp,
   }
 }
 
+// y = M x for one column (k = 1): one wave per row, the lanes take the
+// nonzeros p = lane, lane + 64, ... of the row and their partial sums are
+// added in a fixed butterfly order, so a row of tens of thousands of
+// nonzeros is spread over a wave instead of one thread.
+__global__ __launch_bounds__(kThreads) void k_spmv_wave(int rows, const int *__restrict__ rp,
+                                                        const int *__restrict__ ci, const double *__restrict__ va,
+                                                        const double *__restrict__ x, double *__restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t row = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); row < rows; row += nwave) {
+    double acc = 0.0;
+    const int e = rp[row + 1];
+    for (int p = rp[row] + lane; p < e; p += 64) acc = fma(va[p], x[ci[p]], acc);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) y[row] = acc;
+  }
+}
+
 hipError_t launch_spmm_rowmajor(int rows, int64_t k, const int *rp, const int *ci, const double *va,
                                 const double *x, double *y, hipStream_t st) {
   if (rows <= 0 || k <= 0) return hipSuccess;
+  if (k == 1) {
+    hipLaunchKernelGGL(k_spmv_wave, dim3(grid_for(rows, kThreads / 64, 16384)), dim3(kThreads), 0, st, rows, rp, ci,
+                       va, x, y);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_spmm_rowmajor, dim3(grid_for((int64_t)rows * k, kThreads, 65536)), dim3(kThreads), 0, st,
                      rows, k, rp, ci, va, x, y);
   return hipGetLastError();

@@ -390,3 +390,22 @@ def sample_spectrum(m: int, n: int, nnz_per_col: int, scale: int = 25, config: i
     q = (np.arange(n) + 0.5) / n
     lam = np.interp(q, (np.arange(ns) + 0.5) / ns, ev)
     return np.sqrt(np.maximum(lam, 0.0))[::-1].copy()
+
+
+def interval_from_zipf_sample(m: int, n: int, count: int, scale: int = 200, config: int = 5,
+                              quantile: float = 0.5):
+    """The recipe of ``interval_from_sample`` for Zipf-row matrices
+    (``zipf_rows``): a same-distribution instance (m/scale) x (n/scale)
+    (row lengths still truncated at 42,207, then capped at its n), dense
+    eigenvalues of its A^T A for the quantile and the local density, scaled
+    by ``scale`` to hold about ``count`` values.  Returns (a, b, lambda_q,
+    density)."""
+    ms, ns = max(m // scale, 2), max(n // scale, 1)
+    I = zipf_rows(ms, ns, config=config, instance=99)
+    A = I.dense()
+    ev = np.linalg.eigvalsh(A.T @ A)
+    lq = float(np.quantile(ev, quantile))
+    w = 0.05 * (ev[-1] - ev[0])
+    dens = np.sum(np.abs(ev - lq) <= w / 2) / w
+    width = count / (scale * dens)
+    return math.sqrt(max(lq - width / 2, 0.0)), math.sqrt(lq + width / 2), lq, dens

@@ -304,3 +304,97 @@ def test_block_mixed_stored_basis_and_its_fallback():
             assert np.array_equal(x, y)
     for x, y in zip(out["mixed_cap"], out["fp64_ring"]):
         assert np.array_equal(x, y)
+
+
+def test_wide_block_as_column_groups():
+    """L = 80 > 64 on the block solver: two independent column groups (64 and
+    16 columns) stepped together in one engine.  Each group's moments are
+    bit for bit those of a solo solve on its own columns (the moments are
+    linear in the right-hand side, column by column), and the triplets match
+    the oracle with L = 80 and the dense truth."""
+    I = synth.random_sparse(9216, 4608, 10, config=96)
+    A = I.dense()
+    G = A.T @ A
+    ev = np.linalg.eigvalsh(G)
+    a, b = synth.interval_by_count(ev, ev.size // 2, 24)
+    L, M, N = 80, 4, 16
+    V = synth.v_in(I.n, L, 26)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=L, M=M, N=N, solve_rtol=1e-12)
+        st = cs.csvd_solve_interval(ctx, a, b, p, V)
+        info = cs.csvd_get_info(ctx)
+        say("L = 80: groups", info.column_groups, "steps", info.iterations, "t_hat", info.t_hat)
+        assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK and info.column_groups == 2
+        Sw = [cs.csvd_get_moment(ctx, k, I.n, L) for k in range(M + 1)]
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+        for lo, hi in ((0, 64), (64, 80)):
+            ps = cs.csvd_params_default(L=hi - lo, M=M, N=N, solve_rtol=1e-12)
+            assert cs.csvd_solve_interval(ctx, a, b, ps, np.asfortranarray(V[:, lo:hi])) == cs.CSVD_OK
+            for k in range(M + 1):
+                assert np.array_equal(cs.csvd_get_moment(ctx, k, I.n, hi - lo), Sw[k][:, lo:hi]), (lo, k)
+    finally:
+        cs.csvd_destroy(ctx)
+    o = method.ss_svd(I, a, b, V, L, M, N, G=G)
+    s_t, U_t, V_t, sall = truth.dense_truth(I, a, b)
+    compare_with_oracle(I, sig, U, Vv, res, (o["sigma"], o["U"], o["V"]), 1e-9, 1e-8, sall[0])
+    np.testing.assert_allclose(sig, s_t, rtol=1e-9)
+
+
+def _long_row_matrix():
+    """Zipf(1.8) row lengths (up to 400 nonzeros per row) plus six dense-ish
+    columns (300 nonzeros each): rows of A and of A^T longer than the
+    128-nonzero segment length of the block products."""
+    import scipy.sparse as sp
+    m, n = 8192, 4096
+    Z = synth.zipf_rows(m, n, kmax=400, config=97)
+    rng = np.random.default_rng(np.random.SeedSequence([2109, 13655, 97, 1]))
+    rows = np.concatenate([rng.choice(m, 300, replace=False) for _ in range(6)])
+    cols = np.repeat(rng.choice(n, 6, replace=False), 300)
+    D = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(m, n))
+    A = (Z.scipy() + D).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    return synth.Instance(m, n, A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data.astype(np.float64),
+                          name="zipf_long_rows")
+
+
+def test_block_long_rows_against_oracle():
+    """Rows with more than 128 nonzeros in A (Zipf lengths up to 2000) and in
+    A^T (dense-ish columns) are summed from 128-nonzero segments in a fixed
+    order: the block solver's moments match the oracle's direct solves and
+    its triplets the dense truth (exact count of an interval whose ends sit
+    between eigenvalues).  The interval sits at the 85% point of the
+    spectrum: the long rows stretch the spectrum to about 4e2 and the block
+    solves around its median need more steps than the solver's cap at this
+    small n."""
+    I = _long_row_matrix()
+    rl, cl = np.diff(I.rowptr), np.bincount(I.colidx, minlength=I.n)
+    assert rl.max() > 300 and (rl > 128).sum() > 20 and (cl > 128).sum() >= 6
+    A = I.dense()
+    G = A.T @ A
+    ev = np.linalg.eigvalsh(G)
+    a, b = synth.interval_by_count(ev, int(0.85 * ev.size), 12)
+    L, M, N = 32, 4, 16
+    V = synth.v_in(I.n, L, 27)
+    say("long rows: max row", rl.max(), "long rows", (rl > 128).sum(), "long cols", (cl > 128).sum())
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=L, M=M, N=N, solve_rtol=1e-12)
+        st = cs.csvd_solve_interval(ctx, a, b, p, V)
+        info = cs.csvd_get_info(ctx)
+        say("steps", info.iterations, "t_hat", info.t_hat)
+        assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK and info.L_padded == 32
+        Sg = [cs.csvd_get_moment(ctx, k, I.n, L) for k in range(M + 1)]
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    o = method.ss_svd(I, a, b, V, L, M, N, G=G)
+    ymax = max(np.linalg.norm(o["Y"][j]) for j in range(N // 2))
+    for k in range(M + 1):
+        scale = 2 * np.abs(o["c"][:, k]).sum() * ymax
+        assert np.linalg.norm(Sg[k] - o["S"][k]) <= 1e-9 * scale, k
+    s_t, U_t, V_t, sall = truth.dense_truth(I, a, b)
+    assert s_t.size == 12
+    compare_with_oracle(I, sig, U, Vv, res, (o["sigma"], o["U"], o["V"]), 1e-9, 1e-8, sall[0])
+    np.testing.assert_allclose(sig, s_t, rtol=1e-9)
