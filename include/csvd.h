@@ -143,6 +143,18 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
 int csvd_get_triplets(csvd_ctx *ctx, int64_t *t_hat, int64_t capacity,
                       double *sigma, double *U, double *V, double *resid);
 
+/* Residual estimates of the last solve (Sec. 3.4.1), one per triplet in the
+ * order of csvd_get_triplets, relative to ||A||_2 like its resid: the norm
+ * ||A^T u_i - s_i v_i|| computed from the moments without a product with A,
+ *   CSVD_PLAIN (eq. residual):  || S_+ W_S1 Sigma_S1^-1 q_i - s_i^2 U_S1 q_i || / s_i,
+ *     S_+ = [S_1 .. S_M], U_S1, Sigma_S1, W_S1 from the low-rank step, q_i the
+ *     i-th right singular vector of B (step 5);
+ *   CSVD_EXP (eq. res_nonlinear): the same with log(s_i^2) in place of s_i^2,
+ *     times mu = ||r_i'|| / ||r~_i'|| taken from the triplet i' with the
+ *     largest computed residual ||A^T u - s v||.
+ * capacity >= t_hat (CSVD_EINVAL otherwise); CSVD_ESTATE before a solve. */
+int csvd_get_residual_estimates(csvd_ctx *ctx, int64_t capacity, double *est);
+
 /* Summary of the last solve. */
 typedef struct {
   int64_t iterations;        /* Lanczos steps of the last round                      */

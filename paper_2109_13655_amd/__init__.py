@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "CsvdError", "csvd_params", "csvd_info", "load", "lib_path",
     "csvd_params_default", "csvd_create", "csvd_solve_interval", "csvd_get_triplets",
-    "csvd_get_info", "csvd_get_moment", "csvd_get_solution", "csvd_quadrature", "csvd_spmm", "csvd_spmm_noalloc", "csvd_probe_gather",
+    "csvd_get_info", "csvd_get_residual_estimates", "csvd_get_moment", "csvd_get_solution", "csvd_quadrature", "csvd_spmm", "csvd_spmm_noalloc", "csvd_probe_gather",
     "csvd_get_transpose", "csvd_dense_gemm", "csvd_last_error", "csvd_destroy", "csvd_trim", "csvd_solve_batch",
     "csvd_server_create", "csvd_server_submit", "csvd_server_step", "csvd_server_poll",
     "csvd_server_cancel", "csvd_server_last_error", "csvd_server_destroy",
@@ -99,6 +99,7 @@ def load(build_if_missing: bool = True):
         "csvd_solve_interval": (C.c_int, [_P, C.c_double, C.c_double, C.POINTER(csvd_params), _P]),
         "csvd_get_triplets": (C.c_int, [_P, C.POINTER(C.c_int64), C.c_int64, _P, _P, _P, _P]),
         "csvd_get_info": (C.c_int, [_P, C.POINTER(csvd_info)]),
+        "csvd_get_residual_estimates": (C.c_int, [_P, C.c_int64, _P]),
         "csvd_get_moment": (C.c_int, [_P, C.c_int32, _P]),
         "csvd_get_solution": (C.c_int, [_P, C.c_int32, _P, _P]),
         "csvd_quadrature": (C.c_int, [C.c_double, C.c_double, C.POINTER(csvd_params), _P, _P, _P, _P, _P, _P]),
@@ -220,6 +221,13 @@ def csvd_get_triplets(ctx, m, n, want_vectors=True):
     if k:
         _check(lib.csvd_get_triplets(ctx, C.byref(t), k, _ptr(sigma), _ptr(U), _ptr(V), _ptr(resid)), ctx)
     return sigma, U, V, resid
+
+
+def csvd_get_residual_estimates(ctx, t_hat):
+    """Residual estimates of Sec. 3.4.1 per triplet (relative to ||A||_2)."""
+    est = np.zeros(int(t_hat))
+    _check(load().csvd_get_residual_estimates(ctx, int(t_hat), _ptr(est) if t_hat else None), ctx)
+    return est
 
 
 def csvd_get_info(ctx) -> csvd_info:

@@ -732,6 +732,7 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   const int t = (int)sel.size();
   ctx->sigma.assign(t, 0.0);
   ctx->resid.assign(t, 0.0);
+  ctx->resid_est.assign(t, 0.0);
   HIPCHK(ctx, ctx->d_U.alloc(sizeof(double) * mpad * std::max(t, 1)));
   HIPCHK(ctx, ctx->d_V.alloc(sizeof(double) * npad * std::max(t, 1)));
   double normA = p.norm_a;
@@ -797,6 +798,59 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
     for (int c = 0; c < t; ++c) {
       ctx->resid[c] = std::sqrt(std::max(h1[c], h2[c])) / (normA > 0 ? normA : 1.0);
       info.max_triplet_resid = std::max(info.max_triplet_resid, ctx->resid[c]);
+    }
+    // Sec. 3.4.1: the residual ||A^T u_i - s_i v_i|| estimated from the
+    // moments alone.  With S-hat = Q_S R and R^T J = B (one-sided Jacobi),
+    // R = J Sigma W^T, so U_S1 = Q_S J(:, 1:r), W_S1 Sigma_S1^-1 =
+    // B(:, 1:r) Sigma_S1^-2, and v_i = U_S1 q_i.  eq. residual (plain):
+    // ||S_+ W_S1 Sigma_S1^-1 q_i - s_i^2 U_S1 q_i|| / s_i, S_+ = [S_1 .. S_M];
+    // exp transform: the same with log(s_i^2) in place of s_i^2, scaled by mu
+    // of eq. res_nonlinear from one computed residual (the largest).
+    {
+      const int LMe2 = LMe;
+      std::vector<double> Bm((size_t)LMe2 * LMe2);
+      HIPCHK(ctx, hipMemcpyAsync(Bm.data(), dRt.p, sizeof(double) * Bm.size(), hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      const bool nt = (p.transform == CSVD_EXP);
+      std::vector<double> Z((size_t)LM * t, 0.0), Qg((size_t)r * t);
+      for (int c = 0; c < t; ++c) {
+        const int i = sel[c];
+        const double s2 = ctx->sigma[c] * ctx->sigma[c];
+        const double g = nt ? std::log(s2) : s2;  // g^-1(s^2)
+        for (int j = 0; j < r; ++j) {
+          const double q = Jb[(size_t)i * re + j];
+          const double w = q / (sS[perm[j]] * sS[perm[j]]);
+          const double *bcol = Bm.data() + (size_t)perm[j] * LMe2;
+          for (int a = 0; a < LM; ++a) Z[(size_t)c * LM + a] += bcol[a] * w;
+          Qg[(size_t)c * r + j] = g * q;
+        }
+      }
+      DevBuf dZ, dQg, dE, dn;
+      HIPCHK(ctx, dZ.alloc(sizeof(double) * Z.size()));
+      HIPCHK(ctx, dQg.alloc(sizeof(double) * Qg.size()));
+      HIPCHK(ctx, dE.alloc(sizeof(double) * npad * t));
+      HIPCHK(ctx, dn.alloc(sizeof(double) * t));
+      HIPCHK(ctx, hipMemcpyAsync(dZ.p, Z.data(), sizeof(double) * Z.size(), hipMemcpyHostToDevice, st));
+      HIPCHK(ctx, hipMemcpyAsync(dQg.p, Qg.data(), sizeof(double) * Qg.size(), hipMemcpyHostToDevice, st));
+      // E = S_+ Z - V~ (g Q_sel) on the matrix cores, then column norms
+      HIPCHK(ctx, launch_gemm((int)npad, t, LM, 1.0, ctx->d_S.as<double>() + (size_t)L * npad, npad,
+                              dZ.as<double>(), LM, 0.0, dE.as<double>(), npad, st));
+      HIPCHK(ctx, launch_gemm((int)npad, t, r, -1.0, Vt.as<double>(), npad, dQg.as<double>(), r, 1.0,
+                              dE.as<double>(), npad, st));
+      HIPCHK(ctx, launch_col_norms(dE.as<double>(), npad, (int)n, t, dn.as<double>(), st));
+      std::vector<double> en(t);
+      HIPCHK(ctx, hipMemcpyAsync(en.data(), dn.p, sizeof(double) * t, hipMemcpyDeviceToHost, st));
+      HIPCHK(ctx, hipStreamSynchronize(st));
+      double mu = 1.0;
+      if (nt) {  // eq. res_nonlinear: mu from the triplet with the largest computed residual
+        int ip = 0;
+        for (int c = 1; c < t; ++c)
+          if (h2[c] > h2[ip]) ip = c;
+        const double rt = en[ip] / ctx->sigma[ip];
+        mu = rt > 0 ? std::sqrt(h2[ip]) / rt : 0.0;
+      }
+      ctx->resid_est.assign(t, 0.0);
+      for (int c = 0; c < t; ++c) ctx->resid_est[c] = mu * en[c] / ctx->sigma[c] / (normA > 0 ? normA : 1.0);
     }
   }
   double t3 = now_ms();
@@ -1143,6 +1197,16 @@ int csvd_get_triplets(csvd_ctx *ctx, int64_t *t_hat, int64_t capacity, double *s
   if (t > 0 && U) XFER(d2h_cols(ctx, U, ctx->d_U.as<double>(), ctx->mpad, ctx->m, t, ctx->st));
   if (t > 0 && V) XFER(d2h_cols(ctx, V, ctx->d_V.as<double>(), ctx->npad, ctx->n, t, ctx->st));
   HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+  return CSVD_OK;
+}
+
+int csvd_get_residual_estimates(csvd_ctx *ctx, int64_t capacity, double *est) {
+  if (!ctx || (capacity > 0 && !est)) return CSVD_EINVAL;
+  if (ctx->busy) return set_err(ctx, CSVD_ESTATE, "the context is held by a live server request");
+  if (!ctx->solved) return set_err(ctx, CSVD_ESTATE, "no solve has completed on this context");
+  const int64_t t = (int64_t)ctx->resid_est.size();
+  if (capacity < t) return set_err(ctx, CSVD_EINVAL, "capacity smaller than t_hat");
+  if (t > 0) std::memcpy(est, ctx->resid_est.data(), sizeof(double) * t);
   return CSVD_OK;
 }
 

@@ -185,6 +185,7 @@ struct csvd_ctx {
   csvd::DevBuf d_S;                  // moments, npad x (M+1)L
   csvd::DevBuf d_U, d_V;             // triplet vectors, mpad x t / npad x t
   std::vector<double> sigma, resid;  // t_hat
+  std::vector<double> resid_est;     // t_hat: residual estimates of Sec. 3.4.1
   csvd_info info{};
   std::unique_ptr<csvd::Job> job;    // last round's job (solutions), single-vector solver
   double norm_est = 0.0;             // cached ||A||_2 estimate

@@ -398,3 +398,44 @@ def test_block_long_rows_against_oracle():
     assert s_t.size == 12
     compare_with_oracle(I, sig, U, Vv, res, (o["sigma"], o["U"], o["V"]), 1e-9, 1e-8, sall[0])
     np.testing.assert_allclose(sig, s_t, rtol=1e-9)
+
+
+@pytest.mark.parametrize("kind,transform,L,solver", [(1, cs.CSVD_PLAIN, 14, cs.CSVD_SOLVER_SINGLE),
+                                                     (2, cs.CSVD_EXP, 10, cs.CSVD_SOLVER_SINGLE),
+                                                     (0, cs.CSVD_PLAIN, 8, cs.CSVD_SOLVER_BLOCK)])
+def test_residual_estimates_against_oracle(kind, transform, L, solver):
+    """Sec. 3.4.1 on the device: the residual estimates from the moments
+    (eq. residual; eq. res_nonlinear with mu from the largest computed
+    residual) against the oracle's, on deliberately small subspaces whose
+    residuals sit far above the solve accuracy (model problems 1 and 2 of
+    Sec. 4.2 with N = 16; the 1300 x 1100 Givens matrix with M = 2 on the
+    block solver)."""
+    from oracle import quadrature as Q
+    if kind:
+        I = synth.model_problem(kind)
+        nA, M, N = float(I.sigma[0]), 4, 16
+    else:
+        I = _mid_problem()
+        nA, M, N = 1.0, 2, 16
+    V = synth.v_in(I.n, L, 9)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=L, M=M, N=N, transform=transform, norm_a=nA, solve_rtol=1e-13, solver=solver)
+        st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+        assert st == cs.CSVD_OK
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+        est = cs.csvd_get_residual_estimates(ctx, sig.size)
+    finally:
+        cs.csvd_destroy(ctx)
+    o = method.ss_svd(I, I.a, I.b, V, L, M, N, transform=Q.EXP if transform == cs.CSVD_EXP else Q.PLAIN)
+    assert sig.size == o["sigma"].size and sig.size >= 5
+    np.testing.assert_allclose(sig, o["sigma"], rtol=1e-6)
+    A = I.dense()
+    exact_o = np.linalg.norm(A.T @ o["U"] - o["V"] * o["sigma"], axis=0)
+    ref = o["resid_est"] if transform == cs.CSVD_PLAIN else method.nt_mu(o["resid_est"], exact_o) * o["resid_est"]
+    say("residual estimates: kind", kind, "gpu", est.min(), est.max(), "oracle", (ref / nA).min(), (ref / nA).max())
+    assert (ref / nA).min() > 1e-9  # far above the solve accuracy
+    np.testing.assert_allclose(est, ref / nA, rtol=1e-4)
+    if transform == cs.CSVD_PLAIN:  # eq. residual is exact for Alg. 1 (Prop. 1)
+        exact = np.linalg.norm(A.T @ U - Vv * sig, axis=0) / nA
+        np.testing.assert_allclose(est, exact, rtol=1e-4)
