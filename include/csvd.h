@@ -99,12 +99,17 @@ typedef struct {
                           /* pass; 0 always regenerates it in a second pass; k >= 2 keeps */
                           /* at most k blocks and, past them, goes on with the ring and a */
                           /* second pass (memory is taken in chunks of 64 blocks, so up   */
-                          /* to k rounded up to 64).  All give the same bits.  Jobs of    */
-                          /* csvd_server never keep it                                    */
+                          /* to k rounded up to 64).  All give the same bits.  A served   */
+                          /* request keeps it only when its largest size also fits the   */
+                          /* server's budget                                              */
   int32_t cholqr_passes;  /* block solver: 0 (default) orthonormalises a new basis block  */
                           /* with one Cholesky QR pass when the first factor R1 is well   */
                           /* conditioned (||R1||_F ||R1^-1||_F <= 1.5 Lp, no deflated    */
                           /* column) and with two otherwise; 2 always uses two passes     */
+  double  resid_target;   /* > 0: triplets whose relative residual exceeds this are not   */
+                          /* returned; csvd_info.dropped counts them and the solve        */
+                          /* returns CSVD_ENOTCONV.  0 (default): every triplet in [a, b] */
+                          /* that passes the spurious test is returned (Algorithm 1)     */
 } csvd_params;
 
 enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
@@ -112,7 +117,7 @@ enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
 /* Fills *p with the paper's defaults: L=16, M=8, N=32, ell=1, delta=1e-20,
  * alpha=0.1, PLAIN, FP64, solve_rtol=1e-10, max_iters=1000000,
  * spurious_eps=1e-12, seed=2109, norm_a=0, window=0, check_solves=0,
- * solver=CSVD_SOLVER_AUTO, keep_basis=1, cholqr_passes=0. */
+ * solver=CSVD_SOLVER_AUTO, keep_basis=1, cholqr_passes=0, resid_target=0. */
 int csvd_params_default(csvd_params *p);
 
 /* Creates a context holding a device copy of A in CSR form (and of A^T,
@@ -199,6 +204,8 @@ typedef struct {
                              /* stored basis missed the 1e-6 residual target and the      */
                              /* moments were accumulated again from the basis regenerated */
                              /* in FP64 (steps 3-5 then ran again)                         */
+  int32_t dropped;           /* triplets not returned because their residual exceeded     */
+                             /* csvd_params.resid_target                                   */
   double  mixed_resid_fp32;  /* CSVD_MIXED with an FP32 stored basis: the largest relative */
                              /* triplet residual of the result from the FP32 basis (before */
                              /* any refinement); 0 otherwise                               */

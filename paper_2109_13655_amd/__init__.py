@@ -44,7 +44,7 @@ class csvd_params(C.Structure):
         ("solve_rtol", C.c_double), ("max_iters", C.c_int32),
         ("spurious_eps", C.c_double), ("seed", C.c_uint64), ("norm_a", C.c_double),
         ("window", C.c_int32), ("check_solves", C.c_int32), ("solver", C.c_int32),
-        ("keep_basis", C.c_int32), ("cholqr_passes", C.c_int32),
+        ("keep_basis", C.c_int32), ("cholqr_passes", C.c_int32), ("resid_target", C.c_double),
     ]
 
 
@@ -62,7 +62,8 @@ class csvd_info(C.Structure):
         ("window", C.c_int32), ("L_padded", C.c_int32), ("solver", C.c_int32), ("deflated", C.c_int32),
         ("rest_ms", C.c_double), ("basis_stored", C.c_int32), ("one_pass_steps", C.c_int32),
         ("moments_ms", C.c_double), ("svd_sweeps_exhausted", C.c_int32),
-        ("column_groups", C.c_int32), ("mixed_refined", C.c_int32), ("mixed_resid_fp32", C.c_double),
+        ("column_groups", C.c_int32), ("mixed_refined", C.c_int32), ("dropped", C.c_int32),
+        ("mixed_resid_fp32", C.c_double),
     ]
 
     def as_dict(self):

@@ -209,6 +209,7 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
   if (p->keep_basis < 0) return set_err(ctx, CSVD_EINVAL, "keep_basis must be >= 0");
   if (p->cholqr_passes != 0 && p->cholqr_passes != 2)
     return set_err(ctx, CSVD_EINVAL, "cholqr_passes must be 0 or 2");
+  if (!(p->resid_target >= 0.0)) return set_err(ctx, CSVD_EINVAL, "resid_target must be >= 0");
   return CSVD_OK;
 }
 
@@ -853,11 +854,40 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
       for (int c = 0; c < t; ++c) ctx->resid_est[c] = mu * en[c] / ctx->sigma[c] / (normA > 0 ? normA : 1.0);
     }
   }
+  // resid_target > 0: triplets whose computed residual exceeds it are not
+  // returned (their columns of U and V are closed up, order kept); the
+  // count goes to csvd_info.dropped and the solve's status says so
+  int t_out = t;
+  ctx->resid_all_max = info.max_triplet_resid;
+  if (p.resid_target > 0 && t > 0) {
+    int w = 0;
+    for (int c = 0; c < t; ++c) {
+      if (!(ctx->resid[c] <= p.resid_target)) continue;
+      if (w != c) {
+        ctx->sigma[w] = ctx->sigma[c];
+        ctx->resid[w] = ctx->resid[c];
+        ctx->resid_est[w] = ctx->resid_est[c];
+        HIPCHK(ctx, hipMemcpyAsync(ctx->d_U.as<double>() + (size_t)w * mpad, ctx->d_U.as<double>() + (size_t)c * mpad,
+                                   sizeof(double) * mpad, hipMemcpyDeviceToDevice, st));
+        HIPCHK(ctx, hipMemcpyAsync(ctx->d_V.as<double>() + (size_t)w * npad, ctx->d_V.as<double>() + (size_t)c * npad,
+                                   sizeof(double) * npad, hipMemcpyDeviceToDevice, st));
+      }
+      ++w;
+    }
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    t_out = w;
+    ctx->sigma.resize(w);
+    ctx->resid.resize(w);
+    ctx->resid_est.resize(w);
+    info.max_triplet_resid = 0.0;
+    for (int c = 0; c < w; ++c) info.max_triplet_resid = std::max(info.max_triplet_resid, ctx->resid[c]);
+  }
+  info.dropped = t - t_out;
   double t3 = now_ms();
   info.svd_sweeps_exhausted = sweeps_exhausted ? 1 : 0;
   info.iterations = R.block ? R.iters_last : R.job->iters;
   info.iterations_total = R.iters_total;
-  info.t_hat = t;
+  info.t_hat = t_out;
   info.converged = R.all_converged ? 1 : 0;
   info.n_shift = S;
   info.max_solve_resid_est = R.max_res_est;
@@ -964,6 +994,9 @@ int finish_status(csvd_ctx *ctx) {
   } else if (ctx->info.svd_sweeps_exhausted) {
     ctx->last_status = CSVD_ENOTCONV;
     ctx->err = "a one-sided Jacobi SVD of step 3 or 5 reached its sweep limit";
+  } else if (ctx->info.dropped > 0) {
+    ctx->last_status = CSVD_ENOTCONV;
+    ctx->err = std::to_string(ctx->info.dropped) + " triplet(s) above resid_target were not returned";
   } else {
     ctx->last_status = CSVD_OK;
   }
@@ -997,6 +1030,7 @@ int csvd_params_default(csvd_params *p) {
   p->solver = CSVD_SOLVER_AUTO;
   p->keep_basis = 1;
   p->cholqr_passes = 0;
+  p->resid_target = 0.0;
   return CSVD_OK;
 }
 
@@ -1141,8 +1175,8 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   rc = run_finalize(*R);
   if (rc) return rc;
   const bool mixed_stored = R->block && R->bjob->mixed && R->bjob->stored_last;
-  const double resid_fp32 = ctx->info.max_triplet_resid;
-  if (mixed_stored && !(ctx->info.max_triplet_resid <= kMixedResidTarget)) {
+  const double resid_fp32 = ctx->resid_all_max;  // before any resid_target drop
+  if (mixed_stored && !(resid_fp32 <= kMixedResidTarget)) {
     // FP64 refinement of a mixed-precision solve whose triplets miss the
     // mixed target: the moments are accumulated again from the basis
     // regenerated in FP64 (the histories and coefficients of the last round
@@ -1653,8 +1687,20 @@ static int srv_admit(csvd_server *s) {
       R.ctx->busy = false;
       continue;
     }
-    // the budget covers the job's own allocation, not a stored basis
-    if (R.run->bjob) R.run->bjob->want_store = false;
+    // a stored basis (no second pass) only when its largest possible size
+    // (Kcap + 1 blocks, in whole chunks) also fits the budget; the budget
+    // then holds it until the request is done
+    if (R.run->bjob) {
+      BlockJob &B = *R.run->bjob;
+      const int64_t blocks = ((int64_t)B.Kcap + 1 + kStoreChunk - 1) / kStoreChunk * kStoreChunk;
+      const int64_t sb = blocks * B.h.n * B.h.Lp * (B.mixed ? 4 : 8);
+      if (R.p.keep_basis != 0 && s->used + R.bytes + sb <= s->budget) {
+        B.want_store = true;
+        R.bytes += sb;
+      } else {
+        B.want_store = false;
+      }
+    }
     s->used += R.bytes;
     R.state = 1;
     if (R.run->block) {

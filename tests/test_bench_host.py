@@ -40,3 +40,17 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_experiment1_filter_values_match_the_oracle():
+    """The filter curves of the Experiment I harness (from the library's
+    quadrature) equal the oracle's filter functions f and f_g."""
+    import numpy as np
+    import paper_2109_13655_amd as cs
+    from oracle import quadrature as Q
+    for a, b in ((0.8, 1.2), (1e-3, 1e-1)):
+        s = np.logspace(-4, 0.2, 37)
+        for tr, qt in ((cs.CSVD_PLAIN, Q.PLAIN), (cs.CSVD_EXP, Q.EXP)):
+            got = bench.filter_values(cs, a, b, s, tr)
+            ref = Q.filter_f(s, a, b, 32, alpha=0.1, transform=qt)
+            np.testing.assert_allclose(got, ref.real, rtol=1e-10, atol=1e-13)

@@ -439,3 +439,32 @@ def test_residual_estimates_against_oracle(kind, transform, L, solver):
     if transform == cs.CSVD_PLAIN:  # eq. residual is exact for Alg. 1 (Prop. 1)
         exact = np.linalg.norm(A.T @ U - Vv * sig, axis=0) / nA
         np.testing.assert_allclose(est, exact, rtol=1e-4)
+
+
+def test_resid_target_drops_and_reports():
+    """resid_target: triplets whose residual exceeds it are not returned, the
+    rest are exactly those of the solve without a target (same values, same
+    vectors, same order), csvd_info.dropped counts the others and the status
+    is CSVD_ENOTCONV.  Loose shifted solves spread the residuals so that a
+    target between them splits the set."""
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 21)
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=8, M=4, N=16, solve_rtol=1e-6, norm_a=1.0)
+        assert cs.csvd_solve_interval(ctx, I.a, I.b, p, V) == cs.CSVD_OK
+        full = cs.csvd_get_triplets(ctx, I.m, I.n)
+        target = float(np.median(full[3]))
+        p.resid_target = target
+        st = cs.csvd_solve_interval(ctx, I.a, I.b, p, V)
+        info = cs.csvd_get_info(ctx)
+        kept = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    keep = full[3] <= target
+    say("resid_target", target, "kept", keep.sum(), "of", keep.size, "dropped", info.dropped)
+    assert 0 < keep.sum() < keep.size
+    assert st == cs.CSVD_ENOTCONV and info.dropped == keep.size - keep.sum() and info.t_hat == keep.sum()
+    assert np.array_equal(kept[0], full[0][keep]) and np.array_equal(kept[3], full[3][keep])
+    assert np.array_equal(kept[1], full[1][:, keep]) and np.array_equal(kept[2], full[2][:, keep])
+    assert info.max_triplet_resid <= target
