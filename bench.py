@@ -31,12 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 of csrc/k_bspmm.hip) and for the c2 workload.
 SPMM_TRAFFIC_C2 = {"source": "k_bspmm.hip",
-                   "sha256": "a0fe56dfeda4fea741dc0993e30f69eb7540bbb44c2c8d634decb2970d8c5642",
-                   "bytes": (244866.6 * 2.0 + 100001.0 + 250738.6 * 2.0 + 50011.0) * 1024.0}
+                   "sha256": "3d71087b9640299886c0da92f52699a046a8d2d4f4f855f829b5512d9fd5854e",
+                   "bytes": (244876.3 * 2.0 + 100000.9 + 252112.4 * 2.0 + 50017.9) * 1024.0}
 # the same for one full 16-block launch of b_moments (sha256 of csrc/k_block.hip)
 MOMENTS_TRAFFIC_C2 = {"source": "k_block.hip",
-                      "sha256": "752f71d8b47b4e831f937d6a1ced1706bf75cb438683d5e95ef2f4cc5cd7daee",
-                      "bytes": (1325056.1 * 2.0 + 450000.0) * 1024.0}
+                      "sha256": "045b8779d602205c40b26fd964dac385dbedd30ce48e5e2046096bd13ea5a6a3",
+                      "bytes": (1323882.0 * 2.0 + 450000.0) * 1024.0}
 
 
 def log(*a):
