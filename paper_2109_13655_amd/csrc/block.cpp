@@ -319,6 +319,15 @@ hipError_t BlockJob::sync_desc(hipStream_t st) {
 hipError_t BEngine::init() {
   hipError_t e = hipStreamCreateWithFlags(&side_, hipStreamNonBlocking);
   if (e != hipSuccess) return e;
+  {
+    // step graphs are opt-in: replays measured slower than eager launches
+    // (each step kernel then waits on a dependent load of the clock, and the
+    // host already runs ahead of the device)
+    const char *v = std::getenv("CSVD_STEP_GRAPH");
+    graphs_ = (v && v[0] == '1');
+  }
+  if ((e = hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = clk_.alloc(sizeof(int64_t))) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&ev_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&snap_main_, hipEventDisableTiming)) != hipSuccess) return e;
   if ((e = hipEventCreateWithFlags(&snap_side_, hipEventDisableTiming)) != hipSuccess) return e;
@@ -331,6 +340,8 @@ BEngine::~BEngine() {
     (void)hipStreamDestroy(side_);
   }
   (void)hipStreamSynchronize(st_);
+  if (gexec_) (void)hipGraphExecDestroy(gexec_);
+  if (cap_) (void)hipStreamDestroy(cap_);
   if (ev_) (void)hipEventDestroy(ev_);
   if (snap_main_) (void)hipEventDestroy(snap_main_);
   if (snap_side_) (void)hipEventDestroy(snap_side_);
@@ -505,6 +516,11 @@ hipError_t BEngine::rebuild(std::vector<BlockJob *> &jobs, DevBuf &dj, DevBuf &d
   // the side stream may still read the old tables
   hipError_t es = hipStreamSynchronize(side_);
   if (es != hipSuccess) return es;
+  if (&b == &b1_ && gexec_) {  // the step graph holds the old tables
+    if ((es = hipStreamSynchronize(st_)) != hipSuccess) return es;
+    (void)hipGraphExecDestroy(gexec_);
+    gexec_ = nullptr;
+  }
   const int nj = (int)jobs.size();
   std::vector<BJobDesc> descs(nj);
   std::vector<int> toff(4 * (nj + 1), 0);
@@ -556,35 +572,46 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
       dirty1_ = false;
     }
     b1_.clock = clock_;
+    b1_.clkp = nullptr;
     const BBatch &b = b1_;
-    if (timer && sample) timer->begin(0, st_);
-    if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
-    if ((e = long_rows(p1_, 1)) != hipSuccess) return e;
-    if (timer && sample) timer->end(st_);
-    if (timer && sample) timer->begin(1, st_);
-    if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
-    if ((e = long_rows(p1_, 2)) != hipSuccess) return e;
-    if (timer && sample) timer->end(st_);
-    if (timer && sample) timer->begin(2, st_);
-    if ((e = launch_bs_tall(b, 0, 1, st_)) != hipSuccess) return e;   // W', P
-    if ((e = launch_bs_reduce(b, 0, 1, 0, 0, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_tall(b, 1, 1, st_)) != hipSuccess) return e;   // C, G2
-    if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
-    for (BlockJob *j : p1_) {  // mark the robust steps for small1
-      const int k = (int)(clock_ - j->h.start_clock);
-      if (j->robust_steps > 0 && (k == 0 || k == j->robust_steps) &&
-          (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(j->h.flags + 3), k == 0 ? 1 : 0, 1, st_)) !=
-              hipSuccess)
-        return e;
+    if (!(timer && sample) && graph_step_ok()) {
+      if (!gexec_ && (e = capture_step()) != hipSuccess) return e;
+      if (!clk_synced_ && (e = launch_b_setclock(clk_.as<int64_t>(), clock_, st_)) != hipSuccess) return e;
+      if ((e = hipGraphLaunch(gexec_, st_)) != hipSuccess) return e;  // ends with clk_ = clock_ + 1
+      clk_synced_ = true;
+      ++graph_steps_;
+    } else {
+      clk_synced_ = false;
+      ++eager_steps_;
+      if (timer && sample) timer->begin(0, st_);
+      if ((e = launch_b_spmm_a(b, st_)) != hipSuccess) return e;
+      if ((e = long_rows(p1_, 1)) != hipSuccess) return e;
+      if (timer && sample) timer->end(st_);
+      if (timer && sample) timer->begin(1, st_);
+      if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
+      if ((e = long_rows(p1_, 2)) != hipSuccess) return e;
+      if (timer && sample) timer->end(st_);
+      if (timer && sample) timer->begin(2, st_);
+      if ((e = launch_bs_tall(b, 0, 1, st_)) != hipSuccess) return e;   // W', P
+      if ((e = launch_bs_reduce(b, 0, 1, 0, 0, st_)) != hipSuccess) return e;
+      if ((e = launch_bs_tall(b, 1, 1, st_)) != hipSuccess) return e;   // C, G2
+      if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
+      for (BlockJob *j : p1_) {  // mark the robust steps for small1
+        const int k = (int)(clock_ - j->h.start_clock);
+        if (j->robust_steps > 0 && (k == 0 || k == j->robust_steps) &&
+            (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(j->h.flags + 3), k == 0 ? 1 : 0, 1, st_)) !=
+                hipSuccess)
+          return e;
+      }
+      if ((e = launch_bs_small1(b, st_)) != hipSuccess) return e;
+      if ((e = launch_bs_tall(b, 2, 1, st_)) != hipSuccess) return e;   // G3
+      if ((e = launch_bs_reduce(b, 1, 1, 3, 1, st_)) != hipSuccess) return e;
+      if ((e = launch_bs_small2(b, st_)) != hipSuccess) return e;
+      if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
+      if ((e = robust_finish(p1_, true)) != hipSuccess) return e;
+      if (timer && sample) timer->end(st_);
     }
-    if ((e = launch_bs_small1(b, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_tall(b, 2, 1, st_)) != hipSuccess) return e;   // G3
-    if ((e = launch_bs_reduce(b, 1, 1, 3, 1, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_small2(b, st_)) != hipSuccess) return e;
-    if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
-    if ((e = robust_finish(p1_, true)) != hipSuccess) return e;
     ++npend_;  // its shift recurrences run at the next poll
-    if (timer && sample) timer->end(st_);
   }
   if (!p2_.empty()) {
     if (dirty2_) {
@@ -615,6 +642,55 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
   for (BlockJob *j : p1_) j->steps_total++;
   for (BlockJob *j : p2_) j->steps_total++;
   return hipSuccess;
+}
+
+// A pass-1 step is replayed from the graph when no second-pass job shares
+// the engine and no job needs host-side work in it: no robust step (their
+// marks and Householder QR), no long-row segments (launched per job).
+bool BEngine::graph_step_ok() const {
+  if (!graphs_ || !p2_.empty()) return false;
+  for (const BlockJob *j : p1_) {
+    const int k = (int)(clock_ - j->h.start_clock);
+    if (j->robust_steps > 0 && k <= j->robust_steps) return false;
+    if (j->h.nseg1 + j->h.nseg2 > 0) return false;
+  }
+  return true;
+}
+
+// The step kernels of the batch b (the eager sequence of a plain step, the
+// clock read from b.clkp) and the tick, captured on the private stream.
+hipError_t BEngine::capture_step() {
+  BBatch b = b1_;
+  b.clkp = clk_.as<int64_t>();
+  hipError_t e = hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t el = step_kernels(b, cap_);
+  if (el == hipSuccess) el = launch_b_tick(clk_.as<int64_t>(), cap_);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(cap_, &g);
+  if (el != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return el;
+  }
+  if (e != hipSuccess) return e;
+  e = hipGraphInstantiate(&gexec_, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  return e;
+}
+
+hipError_t BEngine::step_kernels(const BBatch &b, hipStream_t st) {
+  hipError_t e;
+  if ((e = launch_b_spmm_a(b, st)) != hipSuccess) return e;
+  if ((e = launch_b_spmm_at(b, st)) != hipSuccess) return e;
+  if ((e = launch_bs_tall(b, 0, 1, st)) != hipSuccess) return e;   // W', P
+  if ((e = launch_bs_reduce(b, 0, 1, 0, 0, st)) != hipSuccess) return e;
+  if ((e = launch_bs_tall(b, 1, 1, st)) != hipSuccess) return e;   // C, G2
+  if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st)) != hipSuccess) return e;
+  if ((e = launch_bs_small1(b, st)) != hipSuccess) return e;
+  if ((e = launch_bs_tall(b, 2, 1, st)) != hipSuccess) return e;   // G3
+  if ((e = launch_bs_reduce(b, 1, 1, 3, 1, st)) != hipSuccess) return e;
+  if ((e = launch_bs_small2(b, st)) != hipSuccess) return e;
+  return launch_bs_gamma(b, st);
 }
 
 hipError_t BEngine::long_rows(const std::vector<BlockJob *> &v, int side) {

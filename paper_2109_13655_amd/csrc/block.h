@@ -131,6 +131,27 @@ class BEngine {
   hipStream_t st_;
   hipStream_t side_ = nullptr;
   hipEvent_t ev_ = nullptr;
+  // Step graph: the kernels of one pass-1 step of the current batch tables,
+  // captured once (on a private stream) and replayed at successive clocks;
+  // the kernels read the clock from clk_ and a tick kernel at the end of the
+  // graph advances it.  Steps with host-side work (robust steps, long-row
+  // segments, sampled timings) or second-pass jobs run as eager launches.
+  // Opt-in: CSVD_STEP_GRAPH=1 in the environment (eager launches otherwise).
+  hipError_t step_kernels(const BBatch &b, hipStream_t st);
+  hipError_t capture_step();
+  bool graph_step_ok() const;
+  bool graphs_ = true;
+  hipStream_t cap_ = nullptr;
+  DevBuf clk_;
+  hipGraphExec_t gexec_ = nullptr;
+  bool clk_synced_ = false;
+  int64_t graph_steps_ = 0, eager_steps_ = 0;
+
+ public:
+  int64_t graph_steps() const { return graph_steps_; }
+  int64_t eager_steps() const { return eager_steps_; }
+
+ private:
   int64_t clock_ = 0;
   std::vector<BlockJob *> p1_, p2_;
   DevBuf dj1_, dt1_, dj2_, dt2_;

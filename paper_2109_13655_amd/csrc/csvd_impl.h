@@ -175,7 +175,19 @@ struct BBatch {
   int total1, total2, totalr, totals;
   int lpmask;  // block widths present: bit 0 -> 16, bit 1 -> 32, bit 2 -> 64
   int64_t clock;  // engine step clock of the launches (step k of a job: clock - start_clock)
+  // non-null: the step kernels read the clock from this device word instead
+  // (a captured step graph, replayed at successive clocks; a tick kernel at
+  // the end of the step advances it)
+  const int64_t *clkp;
 };
+
+// The step clock a step kernel runs at: by value, or from device memory.
+struct StepClock {
+  int64_t value;
+  const int64_t *ptr;
+};
+__device__ __forceinline__ int64_t sclock(const StepClock &c) { return c.ptr ? *c.ptr : c.value; }
+inline StepClock step_clock(const BBatch &b) { return StepClock{b.clock, b.clkp}; }
 
 constexpr int kBlockMaxLp = 64;   // widest block of the block Lanczos engine
 constexpr int kBlockMinLp = 16;   // narrowest (MFMA tile width)
@@ -220,6 +232,9 @@ hipError_t launch_b_fcoef(const BJobDesc &hj, int K, hipStream_t st);
 // part 1: flags[0..2], on the step stream)
 hipError_t launch_b_snap(const BBatch &b, int part, int *host, hipStream_t st);
 hipError_t launch_b_r0(const double *X, int64_t ld, int Lp, double *B, hipStream_t st);
+// device step clock of captured steps: set to a value / advance by one
+hipError_t launch_b_setclock(int64_t *clk, int64_t value, hipStream_t st);
+hipError_t launch_b_tick(int64_t *clk, hipStream_t st);
 hipError_t launch_b_eye(double *Z, int64_t ld, int64_t rows, int cols, hipStream_t st);
 
 struct Ctx;  // defined in csvd.cpp

@@ -772,6 +772,19 @@ hipError_t launch_b_eye(double *Z, int64_t ld, int64_t rows, int cols, hipStream
 // job): part 0 the active count after the job's newest step (written by the
 // shift recurrences), part 1 its flags[0..2] (written by the step kernels).
 // Jobs whose first step has not run get -1.
+__global__ void b_setclock(int64_t *clk, int64_t value) { *clk = value; }
+__global__ void b_tick(int64_t *clk) { *clk += 1; }
+
+hipError_t launch_b_setclock(int64_t *clk, int64_t value, hipStream_t st) {
+  hipLaunchKernelGGL(b_setclock, dim3(1), dim3(1), 0, st, clk, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_b_tick(int64_t *clk, hipStream_t st) {
+  hipLaunchKernelGGL(b_tick, dim3(1), dim3(1), 0, st, clk);
+  return hipGetLastError();
+}
+
 __global__ void b_snap(const BJobDesc *__restrict__ jobs, int njob, int64_t clock, int part, int *host) {
   for (int i = threadIdx.x; i < njob; i += blockDim.x) {
     const BJobDesc &J = jobs[i];

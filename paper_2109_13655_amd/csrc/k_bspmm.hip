@@ -127,9 +127,9 @@ __device__ __forceinline__ void tile_any(const GLB int *__restrict__ rp, const G
 
 __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff, int total,
-                                                     int64_t clock) {
+                                                     StepClock clock) {
   __shared__ double gsum[kThreads];
-  const int64_t ck = clock;
+  const int64_t ck = sclock(clock);
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const int j = bfind_sp(toff, njob, g);
     const BJobDesc &J = jobs[j];
@@ -143,9 +143,9 @@ __global__ __launch_bounds__(kThreads) void b_spmm_a(const BJobDesc *__restrict_
 
 __global__ __launch_bounds__(kThreads) void b_spmm_at(const BJobDesc *__restrict__ jobs, int njob,
                                                       const int *__restrict__ toff, int total,
-                                                      int64_t clock) {
+                                                      StepClock clock) {
   __shared__ double gsum[kThreads];
-  const int64_t ck = clock;
+  const int64_t ck = sclock(clock);
   for (int g = blockIdx.x; g < total; g += gridDim.x) {
     const int j = bfind_sp(toff, njob, g);
     const BJobDesc &J = jobs[j];
@@ -157,13 +157,13 @@ __global__ __launch_bounds__(kThreads) void b_spmm_at(const BJobDesc *__restrict
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(b_spmm_a, dim3(bgrid_sp(b.total1, 4096)), dim3(kThreads), 0, st, b.jobs, b.njob, b.toff1, b.total1,
-                     b.clock);
+                     step_clock(b));
   return hipGetLastError();
 }
 
 hipError_t launch_b_spmm_at(const BBatch &b, hipStream_t st) {
   hipLaunchKernelGGL(b_spmm_at, dim3(bgrid_sp(b.total2, 4096)), dim3(kThreads), 0, st, b.jobs, b.njob, b.toff2, b.total2,
-                     b.clock);
+                     step_clock(b));
   return hipGetLastError();
 }
 

@@ -262,7 +262,7 @@ enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
 template <int LP>
 __global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__restrict__ jobs, int njob,
                                                       const int *__restrict__ toff,
-                                                      int64_t clock) {
+                                                      StepClock clock) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
   __shared__ double Ys[kPanel * kPSMax];
   constexpr int L2 = LP * LP, NT = LP / 16;
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__rest
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
   if (J.Lp != LP) return;
-  const int k = (int)(clock - J.start_clock);
+  const int k = (int)(sclock(clock) - J.start_clock);
   if (k >= J.Kstop) return;
   if (gp(J.flags)[1]) return;  // one-pass step
   const int vb = g - toff[j];
@@ -303,14 +303,14 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__rest
 template <int LP>
 __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff,
-                                                     int64_t clock) {
+                                                     StepClock clock) {
   __shared__ double S1[LP * kSS], S2[LP * kSS];
   constexpr int L2 = LP * LP;
   const int g = blockIdx.x;
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
   if (J.Lp != LP) return;
-  const int k = (int)(clock - J.start_clock);
+  const int k = (int)(sclock(clock) - J.start_clock);
   if (k >= J.Kstop) return;
   const int vb = g - toff[j];
   const int w = threadIdx.x >> 6;
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restr
 // 1, ...) through LDS and stored as the workgroup's partial sums.
 template <int LP, int MODE, int NTH>
 __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void bs_tall_rg(
-    const BJobDesc *__restrict__ jobs, int njob, const int *__restrict__ toff, int64_t clock,
+    const BJobDesc *__restrict__ jobs, int njob, const int *__restrict__ toff, StepClock clock,
     int grams) {
   static_assert(MODE == kTallAlpha || MODE == kTallBeta, "alpha and beta passes");
   constexpr int NT = LP / 16, L2 = LP * LP, NW = NTH / 64;
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
   const int j = bfind2(toff, njob, g);
   const BJobDesc &J = jobs[j];
   if (J.Lp != LP) return;
-  const int k = (int)(clock - J.start_clock);
+  const int k = (int)(sclock(clock) - J.start_clock);
   if (k >= J.Kstop) return;
   const int vb = g - toff[j];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
@@ -454,11 +454,11 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
 // in order.  Grid (njob, 2 * 64 * 64 / 32); block = 32 outputs x 8 groups.
 // The workgroup count of the tall kernels is at most kBlockMaxVB.
 __global__ __launch_bounds__(kThreads) void bs_reduce(const BJobDesc *__restrict__ jobs,
-                                                      int64_t clock, int m0, int nm, int d0,
+                                                      StepClock clock, int m0, int nm, int d0,
                                                       int second) {
   __shared__ double part[8][32];
   const BJobDesc &J = jobs[blockIdx.x];
-  const int k = (int)(clock - J.start_clock);
+  const int k = (int)(sclock(clock) - J.start_clock);
   if (k >= J.Kstop) return;
   if (second && gp(J.flags)[1]) return;  // one-pass step: no second Gram
   const int L2 = J.Lp * J.Lp;
@@ -825,7 +825,7 @@ __device__ void chol_inv_blocked(double *A, double *X, const double *thr, int *d
 // G3 (upper tiles); scr = R1, R1^-1, T
 template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict__ jobs,
-                                                      int64_t clock) {
+                                                      StepClock clock) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
   __shared__ double Pm[LP * SS], Cm[LP * SS], As[LP * SS], Xs[LP * SS];
   __shared__ double Tmp[4 * 16 * 17];
@@ -833,7 +833,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
   if (J.Lp != LP) return;
-  const int k = (int)(clock - J.start_clock);
+  const int k = (int)(sclock(clock) - J.start_clock);
   if (k >= J.Kstop) return;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, rl = l & 15, q = l >> 4;
   const bool act = w < NT;
@@ -934,7 +934,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
 
 template <int LP>
 __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict__ jobs,
-                                                      int64_t clock) {
+                                                      StepClock clock) {
   constexpr int NT = LP / 16, L2 = LP * LP, SS = LP + 1;
   __shared__ double As[LP * SS], Xs[LP * SS], Os[LP * SS];
   __shared__ double Tmp[4 * 16 * 17];
@@ -942,7 +942,7 @@ __global__ __launch_bounds__(kThreads) void bs_small2(const BJobDesc *__restrict
   __shared__ double thr[kBlockMaxLp];
   const BJobDesc &J = jobs[blockIdx.x];
   if (J.Lp != LP) return;
-  const int k = (int)(clock - J.start_clock);
+  const int k = (int)(sclock(clock) - J.start_clock);
   if (k >= J.Kstop) return;
   if (gp(J.flags)[1]) return;  // one-pass step: small1 wrote M, N and B
   const int t = threadIdx.x, w = t >> 6;
@@ -1019,13 +1019,13 @@ hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, hipStream_t st) 
 #define CSVD_TALL(LPV)                                                                                           \
   if (mode == kTallAlpha)                                                                                        \
     hipLaunchKernelGGL((bs_tall_rg<LPV, kTallAlpha, 512>), dim3(b.totalr), dim3(512), 0, st, b.jobs, b.njob,     \
-                       b.toffr, b.clock, grams);                                                                 \
+                       b.toffr, step_clock(b), grams);                                                                 \
   else if (mode == kTallBeta)                                                                                    \
     hipLaunchKernelGGL((bs_tall_rg<LPV, kTallBeta, (LPV == 64 ? 256 : 512)>), dim3(b.totalr),                    \
-                       dim3(LPV == 64 ? 256 : 512), 0, st, b.jobs, b.njob, b.toffr, b.clock, grams);             \
+                       dim3(LPV == 64 ? 256 : 512), 0, st, b.jobs, b.njob, b.toffr, step_clock(b), grams);             \
   else                                                                                                           \
     hipLaunchKernelGGL(bs_gamma0<LPV>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr,       \
-                       b.clock);
+                       step_clock(b));
   if (b.lpmask & 1) CSVD_TALL(16)
   if (b.lpmask & 2) CSVD_TALL(32)
   if (b.lpmask & 4) CSVD_TALL(64)
@@ -1035,31 +1035,31 @@ hipError_t launch_bs_tall(const BBatch &b, int mode, int grams, hipStream_t st) 
 
 hipError_t launch_bs_gamma(const BBatch &b, hipStream_t st) {
   if (b.lpmask & 1)
-    hipLaunchKernelGGL(bs_gamma<16>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock);
+    hipLaunchKernelGGL(bs_gamma<16>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, step_clock(b));
   if (b.lpmask & 2)
-    hipLaunchKernelGGL(bs_gamma<32>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock);
+    hipLaunchKernelGGL(bs_gamma<32>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, step_clock(b));
   if (b.lpmask & 4)
-    hipLaunchKernelGGL(bs_gamma<64>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, b.clock);
+    hipLaunchKernelGGL(bs_gamma<64>, dim3(b.totalr), dim3(kTallThreads), 0, st, b.jobs, b.njob, b.toffr, step_clock(b));
   return hipGetLastError();
 }
 
 hipError_t launch_bs_reduce(const BBatch &b, int m0, int nm, int d0, int second, hipStream_t st) {
   hipLaunchKernelGGL(bs_reduce, dim3(b.njob, 2 * kBlockMaxLp * kBlockMaxLp / 32), dim3(kThreads), 0, st, b.jobs,
-                     b.clock, m0, nm, d0, second);
+                     step_clock(b), m0, nm, d0, second);
   return hipGetLastError();
 }
 
 hipError_t launch_bs_small1(const BBatch &b, hipStream_t st) {
-  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small1<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
-  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small1<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
-  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small1<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
+  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small1<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, step_clock(b));
+  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small1<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, step_clock(b));
+  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small1<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, step_clock(b));
   return hipGetLastError();
 }
 
 hipError_t launch_bs_small2(const BBatch &b, hipStream_t st) {
-  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small2<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
-  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small2<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
-  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small2<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, b.clock);
+  if (b.lpmask & 1) hipLaunchKernelGGL(bs_small2<16>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, step_clock(b));
+  if (b.lpmask & 2) hipLaunchKernelGGL(bs_small2<32>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, step_clock(b));
+  if (b.lpmask & 4) hipLaunchKernelGGL(bs_small2<64>, dim3(b.njob), dim3(kThreads), 0, st, b.jobs, step_clock(b));
   return hipGetLastError();
 }
 

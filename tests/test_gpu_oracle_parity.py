@@ -468,3 +468,44 @@ def test_resid_target_drops_and_reports():
     assert np.array_equal(kept[0], full[0][keep]) and np.array_equal(kept[3], full[3][keep])
     assert np.array_equal(kept[1], full[1][:, keep]) and np.array_equal(kept[2], full[2][:, keep])
     assert info.max_triplet_resid <= target
+
+
+def test_step_graph_replays_equal_eager_steps():
+    """The block steps replayed from the captured step graph
+    (CSVD_STEP_GRAPH=1: the kernels read the step clock from device memory)
+    give the same bits as eager launches: moments and triplets, alone and
+    batched."""
+    import os
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 12)
+    probs = [(synth.random_sparse(m, m // 2, 8, config=98, instance=i), i) for i, m in enumerate((3000, 4400))]
+    out = {}
+    for mode in ("graph", "eager"):
+        if mode == "graph":
+            os.environ["CSVD_STEP_GRAPH"] = "1"
+        try:
+            ctx = make_ctx(I)
+            try:
+                p = cs.csvd_params_default(L=8, M=4, N=16, norm_a=1.0, solver=cs.CSVD_SOLVER_BLOCK)
+                assert cs.csvd_solve_interval(ctx, I.a, I.b, p, V) == cs.CSVD_OK
+                res = list(cs.csvd_get_triplets(ctx, I.m, I.n)) + [cs.csvd_get_moment(ctx, k, I.n, 8) for k in range(5)]
+            finally:
+                cs.csvd_destroy(ctx)
+            ctxs = [make_ctx(J) for J, _ in probs]
+            try:
+                ev = [np.linalg.eigvalsh(J.dense().T @ J.dense()) for J, _ in probs]
+                ab = [synth.interval_by_count(e, e.size // 2, 6) for e in ev]
+                pb = [cs.csvd_params_default(L=16, M=4, N=16, solver=cs.CSVD_SOLVER_BLOCK) for _ in probs]
+                st = cs.csvd_solve_batch(ctxs, [x[0] for x in ab], [x[1] for x in ab], pb,
+                                         [synth.v_in(J.n, 16, 13, i) for J, i in probs])
+                assert all(x == cs.CSVD_OK for x in st)
+                for c, (J, _) in zip(ctxs, probs):
+                    res += list(cs.csvd_get_triplets(c, J.m, J.n))
+            finally:
+                for c in ctxs:
+                    cs.csvd_destroy(c)
+        finally:
+            os.environ.pop("CSVD_STEP_GRAPH", None)
+        out[mode] = res
+    for x, y in zip(out["graph"], out["eager"]):
+        assert np.array_equal(x, y)
