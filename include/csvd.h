@@ -264,7 +264,8 @@ void csvd_destroy(csvd_ctx *ctx);
 /* Frees the device memory kept between solves on the context's device: the
  * idle chunks of stored block bases (csvd_params.keep_basis), which the next
  * solve of the same size would reuse (a solve that needs room frees idle
- * chunks of other sizes by itself).  Waits for the context's stream first.
+ * chunks of other sizes by itself), and the context's workspace of the dense
+ * steps 3-5.  Waits for the context's stream first.
  * Returns CSVD_OK, CSVD_EINVAL (NULL) or CSVD_EDEVICE. */
 int csvd_trim(csvd_ctx *ctx);
 

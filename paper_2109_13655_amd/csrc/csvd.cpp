@@ -555,6 +555,15 @@ int run_after_round(SolveRun &R, bool *more) {
   return CSVD_OK;
 }
 
+// Epilogue buffers live in the context's workspace slots and are only
+// reallocated when a solve needs more room than the last one (hipFree would
+// wait for the device; csvd_trim and csvd_destroy free them).
+static hipError_t ws_grow(DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.p && b.bytes >= bytes) return hipSuccess;
+  return b.alloc(bytes);
+}
+
 // Steps 1-2 (moments) and 3-5 (dense) after the last round, on `stream`
 // (default: the context's stream).
 int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
@@ -584,12 +593,12 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   double t0 = R.t_solve_end;
   const int LM = L * M;
   // ---- step 3: QR of S-hat (Householder), SVD of R by one-sided Jacobi on R^T
-  DevBuf Xq, tau1;
-  HIPCHK(ctx, Xq.alloc(sizeof(double) * npad * LM));
-  HIPCHK(ctx, tau1.alloc(sizeof(double) * LM));
+  DevBuf &Xq = ctx->ws[0]; DevBuf &tau1 = ctx->ws[1];
+  HIPCHK(ctx, ws_grow(Xq, sizeof(double) * npad * LM));
+  HIPCHK(ctx, ws_grow(tau1, sizeof(double) * LM));
   HIPCHK(ctx, hipMemcpyAsync(Xq.p, ctx->d_S.p, sizeof(double) * npad * LM, hipMemcpyDeviceToDevice, st));
-  DevBuf ws1;
-  HIPCHK(ctx, ws1.alloc(sizeof(double) * hh_blocked_ws_doubles(LM)));
+  DevBuf &ws1 = ctx->ws[2];
+  HIPCHK(ctx, ws_grow(ws1, sizeof(double) * hh_blocked_ws_doubles(LM)));
   HIPCHK(ctx, hh_qr_blocked(Xq.as<double>(), npad, (int)n, LM, tau1.as<double>(), ws1.as<double>(), st));
   // R (LM x LM upper) to the host, R^T back as a column-major LMe x LMe block
   const int LMe = jacobi_padded_cols(LM);  // zero columns to a whole number of Jacobi block pairs
@@ -599,11 +608,11 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   for (int c = 0; c < LM; ++c)
     for (int r = 0; r <= c; ++r) Rt[(size_t)r * LMe + c] = Rh[(size_t)c * LM + r];  // Rt[c, r] = R[r, c]
   for (int i = 0; i < LMe; ++i) Jm[(size_t)i * LMe + i] = 1.0;
-  DevBuf dRt, dJ, dcnt, dnorm;
-  HIPCHK(ctx, dRt.alloc(sizeof(double) * Rt.size()));
-  HIPCHK(ctx, dJ.alloc(sizeof(double) * Jm.size()));
-  HIPCHK(ctx, dcnt.alloc(sizeof(int)));
-  HIPCHK(ctx, dnorm.alloc(sizeof(double) * (LMe + 1)));
+  DevBuf &dRt = ctx->ws[3]; DevBuf &dJ = ctx->ws[4]; DevBuf &dcnt = ctx->ws[5]; DevBuf &dnorm = ctx->ws[6];
+  HIPCHK(ctx, ws_grow(dRt, sizeof(double) * Rt.size()));
+  HIPCHK(ctx, ws_grow(dJ, sizeof(double) * Jm.size()));
+  HIPCHK(ctx, ws_grow(dcnt, sizeof(int)));
+  HIPCHK(ctx, ws_grow(dnorm, sizeof(double) * (LMe + 1)));
   HIPCHK(ctx, hipMemcpyAsync(dRt.p, Rt.data(), sizeof(double) * Rt.size(), hipMemcpyHostToDevice, st));
   HIPCHK(ctx, hipMemcpyAsync(dJ.p, Jm.data(), sizeof(double) * Jm.size(), hipMemcpyHostToDevice, st));
   // one-sided Jacobi; a pair is rotated while |a_p^T a_q| > sqrt(rows) eps
@@ -652,16 +661,16 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   info.sigma_s1 = s1;
   info.rank = r;
   // V~ = Q [U_R(:, perm[0:r]); 0]
-  DevBuf Vt;
-  HIPCHK(ctx, Vt.alloc(sizeof(double) * npad * std::max(r, 1)));
-  HIPCHK(ctx, hipMemsetAsync(Vt.p, 0, Vt.bytes, st));
+  DevBuf &Vt = ctx->ws[7];
+  HIPCHK(ctx, ws_grow(Vt, sizeof(double) * npad * std::max(r, 1)));
+  HIPCHK(ctx, hipMemsetAsync(Vt.p, 0, sizeof(double) * npad * std::max(r, 1), st));
   if (r > 0) {
     std::vector<double> Z((size_t)LM * r);
     for (int c = 0; c < r; ++c)
       for (int i = 0; i < LM; ++i) Z[(size_t)c * LM + i] = Jm[(size_t)perm[c] * LMe + i];
     XFER(h2d_cols(ctx, Vt.as<double>(), npad, Z.data(), LM, r, st));
-    DevBuf wsr;
-    HIPCHK(ctx, wsr.alloc(sizeof(double) * hh_blocked_ws_doubles(r)));
+    DevBuf &wsr = ctx->ws[8];
+    HIPCHK(ctx, ws_grow(wsr, sizeof(double) * hh_blocked_ws_doubles(r)));
     HIPCHK(ctx, hh_apply_blocked(Xq.as<double>(), npad, (int)n, LM, ws1.as<double>(), Vt.as<double>(), npad, r,
                                  wsr.as<double>(), st));
     HIPCHK(ctx, hipStreamSynchronize(st));
@@ -669,19 +678,19 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   double t1 = now_ms();
   // ---- step 4: X = A V~, [U~, B] = qr(X)
   const int re = jacobi_padded_cols(r);
-  DevBuf Vrow, Xrow, Xa, tau2, ws2;
+  DevBuf &Vrow = ctx->ws[9]; DevBuf &Xrow = ctx->ws[10]; DevBuf &Xa = ctx->ws[11]; DevBuf &tau2 = ctx->ws[12]; DevBuf &ws2 = ctx->ws[13];
   std::vector<double> Bh;
   if (r > 0) {
-    HIPCHK(ctx, Vrow.alloc(sizeof(double) * n * r));
-    HIPCHK(ctx, Xrow.alloc(sizeof(double) * m * r));
-    HIPCHK(ctx, Xa.alloc(sizeof(double) * mpad * r));
-    HIPCHK(ctx, tau2.alloc(sizeof(double) * r));
-    HIPCHK(ctx, hipMemsetAsync(Xa.p, 0, Xa.bytes, st));
+    HIPCHK(ctx, ws_grow(Vrow, sizeof(double) * n * r));
+    HIPCHK(ctx, ws_grow(Xrow, sizeof(double) * m * r));
+    HIPCHK(ctx, ws_grow(Xa, sizeof(double) * mpad * r));
+    HIPCHK(ctx, ws_grow(tau2, sizeof(double) * r));
+    HIPCHK(ctx, hipMemsetAsync(Xa.p, 0, sizeof(double) * mpad * r, st));
     HIPCHK(ctx, launch_col_to_row((int)n, r, Vt.as<double>(), npad, Vrow.as<double>(), r, st));
     HIPCHK(ctx, launch_spmm_rowmajor((int)m, r, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
                                      Vrow.as<double>(), Xrow.as<double>(), st));
     HIPCHK(ctx, launch_row_to_col((int)m, r, Xrow.as<double>(), r, Xa.as<double>(), mpad, st));
-    HIPCHK(ctx, ws2.alloc(sizeof(double) * hh_blocked_ws_doubles(r)));
+    HIPCHK(ctx, ws_grow(ws2, sizeof(double) * hh_blocked_ws_doubles(r)));
     HIPCHK(ctx, hh_qr_blocked(Xa.as<double>(), mpad, (int)m, r, tau2.as<double>(), ws2.as<double>(), st));
     Bh.assign((size_t)r * r, 0.0);
     std::vector<double> Rb((size_t)r * r);
@@ -699,9 +708,9 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
     for (int c = 0; c < r; ++c)
       for (int i = 0; i < r; ++i) Be[(size_t)c * re + i] = Bh[(size_t)c * r + i];
     for (int i = 0; i < re; ++i) Ie[(size_t)i * re + i] = 1.0;
-    DevBuf dB, dQ;
-    HIPCHK(ctx, dB.alloc(sizeof(double) * Be.size()));
-    HIPCHK(ctx, dQ.alloc(sizeof(double) * Ie.size()));
+    DevBuf &dB = ctx->ws[14]; DevBuf &dQ = ctx->ws[15];
+    HIPCHK(ctx, ws_grow(dB, sizeof(double) * Be.size()));
+    HIPCHK(ctx, ws_grow(dQ, sizeof(double) * Ie.size()));
     HIPCHK(ctx, hipMemcpyAsync(dB.p, Be.data(), sizeof(double) * Be.size(), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(dQ.p, Ie.data(), sizeof(double) * Ie.size(), hipMemcpyHostToDevice, st));
     rc = jacobi(dB.as<double>(), re, re, dQ.as<double>(), re);
@@ -758,9 +767,9 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
         Ps[(size_t)c * r + j] = Bj[(size_t)i * re + j] / phi[i];
       }
     }
-    DevBuf dQs, dPs, dsig;
-    HIPCHK(ctx, dQs.alloc(sizeof(double) * Qs.size()));
-    HIPCHK(ctx, dsig.alloc(sizeof(double) * t));
+    DevBuf &dQs = ctx->ws[16]; DevBuf &dPs = ctx->ws[17]; DevBuf &dsig = ctx->ws[18];
+    HIPCHK(ctx, ws_grow(dQs, sizeof(double) * Qs.size()));
+    HIPCHK(ctx, ws_grow(dsig, sizeof(double) * t));
     HIPCHK(ctx, hipMemcpyAsync(dQs.p, Qs.data(), sizeof(double) * Qs.size(), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(dsig.p, ctx->sigma.data(), sizeof(double) * t, hipMemcpyHostToDevice, st));
     // V-hat = V~ Q_sel (MFMA GEMM);  U-hat = Q_X [P_sel; 0]
@@ -769,19 +778,19 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
                             ctx->d_V.as<double>(), npad, st));
     HIPCHK(ctx, hipMemsetAsync(ctx->d_U.p, 0, ctx->d_U.bytes, st));
     XFER(h2d_cols(ctx, ctx->d_U.as<double>(), mpad, Ps.data(), r, t, st));
-    DevBuf wsu;
-    HIPCHK(ctx, wsu.alloc(sizeof(double) * hh_blocked_ws_doubles(t)));
+    DevBuf &wsu = ctx->ws[19];
+    HIPCHK(ctx, ws_grow(wsu, sizeof(double) * hh_blocked_ws_doubles(t)));
     HIPCHK(ctx, hh_apply_blocked(Xa.as<double>(), mpad, (int)m, r, ws2.as<double>(), ctx->d_U.as<double>(), mpad, t,
                                  wsu.as<double>(), st));
     HIPCHK(ctx, launch_sign_fix(ctx->d_U.as<double>(), mpad, (int)m, ctx->d_V.as<double>(), npad, (int)n, t, st));
     // residuals: ||A v - s u|| and ||A^T u - s v||
-    DevBuf vr, ur, av, atu, o1, o2;
-    HIPCHK(ctx, vr.alloc(sizeof(double) * n * t));
-    HIPCHK(ctx, ur.alloc(sizeof(double) * m * t));
-    HIPCHK(ctx, av.alloc(sizeof(double) * m * t));
-    HIPCHK(ctx, atu.alloc(sizeof(double) * n * t));
-    HIPCHK(ctx, o1.alloc(sizeof(double) * t));
-    HIPCHK(ctx, o2.alloc(sizeof(double) * t));
+    DevBuf &vr = ctx->ws[20]; DevBuf &ur = ctx->ws[21]; DevBuf &av = ctx->ws[22]; DevBuf &atu = ctx->ws[23]; DevBuf &o1 = ctx->ws[24]; DevBuf &o2 = ctx->ws[25];
+    HIPCHK(ctx, ws_grow(vr, sizeof(double) * n * t));
+    HIPCHK(ctx, ws_grow(ur, sizeof(double) * m * t));
+    HIPCHK(ctx, ws_grow(av, sizeof(double) * m * t));
+    HIPCHK(ctx, ws_grow(atu, sizeof(double) * n * t));
+    HIPCHK(ctx, ws_grow(o1, sizeof(double) * t));
+    HIPCHK(ctx, ws_grow(o2, sizeof(double) * t));
     HIPCHK(ctx, launch_col_to_row((int)n, t, ctx->d_V.as<double>(), npad, vr.as<double>(), t, st));
     HIPCHK(ctx, launch_col_to_row((int)m, t, ctx->d_U.as<double>(), mpad, ur.as<double>(), t, st));
     HIPCHK(ctx, launch_spmm_rowmajor((int)m, t, ctx->rp.as<int>(), ctx->ci.as<int>(), ctx->va.as<double>(),
@@ -826,11 +835,11 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
           Qg[(size_t)c * r + j] = g * q;
         }
       }
-      DevBuf dZ, dQg, dE, dn;
-      HIPCHK(ctx, dZ.alloc(sizeof(double) * Z.size()));
-      HIPCHK(ctx, dQg.alloc(sizeof(double) * Qg.size()));
-      HIPCHK(ctx, dE.alloc(sizeof(double) * npad * t));
-      HIPCHK(ctx, dn.alloc(sizeof(double) * t));
+      DevBuf &dZ = ctx->ws[26]; DevBuf &dQg = ctx->ws[27]; DevBuf &dE = ctx->ws[28]; DevBuf &dn = ctx->ws[29];
+      HIPCHK(ctx, ws_grow(dZ, sizeof(double) * Z.size()));
+      HIPCHK(ctx, ws_grow(dQg, sizeof(double) * Qg.size()));
+      HIPCHK(ctx, ws_grow(dE, sizeof(double) * npad * t));
+      HIPCHK(ctx, ws_grow(dn, sizeof(double) * t));
       HIPCHK(ctx, hipMemcpyAsync(dZ.p, Z.data(), sizeof(double) * Z.size(), hipMemcpyHostToDevice, st));
       HIPCHK(ctx, hipMemcpyAsync(dQg.p, Qg.data(), sizeof(double) * Qg.size(), hipMemcpyHostToDevice, st));
       // E = S_+ Z - V~ (g Q_sel) on the matrix cores, then column norms
@@ -1108,6 +1117,7 @@ int csvd_trim(csvd_ctx *ctx) {
   ctx->err.clear();
   if (hipStreamSynchronize(ctx->st) != hipSuccess) return set_err(ctx, CSVD_EDEVICE, "stream synchronize failed");
   csvd::release_idle_chunks();
+  for (csvd::DevBuf &b : ctx->ws) b.release();
   return CSVD_OK;
 }
 

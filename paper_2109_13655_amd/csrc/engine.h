@@ -187,6 +187,7 @@ struct csvd_ctx {
   std::vector<double> sigma, resid;  // t_hat
   std::vector<double> resid_est;     // t_hat: residual estimates of Sec. 3.4.1
   double resid_all_max = 0.0;        // largest residual before resid_target drops
+  csvd::DevBuf ws[32];               // epilogue workspace (steps 3-5), kept between solves
   csvd_info info{};
   std::unique_ptr<csvd::Job> job;    // last round's job (solutions), single-vector solver
   double norm_est = 0.0;             // cached ||A||_2 estimate
