@@ -31,12 +31,12 @@ HBM_PEAK_GBS = 8000.0
 # (FETCH x2.00, WRITE x1.00); valid only for the kernel source they were
 # measured on (sha256 of csrc/k_bspmm.hip) and for the c2 workload.
 SPMM_TRAFFIC_C2 = {"source": "k_bspmm.hip",
-                   "sha256": "3d71087b9640299886c0da92f52699a046a8d2d4f4f855f829b5512d9fd5854e",
-                   "bytes": (244876.3 * 2.0 + 100000.9 + 252112.4 * 2.0 + 50017.9) * 1024.0}
+                   "sha256": "a31e1fa5f629bbe37807b5c50680d73b4885b209526bb831e2e4eef65c08b341",
+                   "bytes": (244827.3 * 2.0 + 100001.0 + 252059.4 * 2.0 + 50017.9) * 1024.0}
 # the same for one full 16-block launch of b_moments (sha256 of csrc/k_block.hip)
 MOMENTS_TRAFFIC_C2 = {"source": "k_block.hip",
-                      "sha256": "045b8779d602205c40b26fd964dac385dbedd30ce48e5e2046096bd13ea5a6a3",
-                      "bytes": (1323882.0 * 2.0 + 450000.0) * 1024.0}
+                      "sha256": "0943d3c52c3d3ae36dbd0101ac045c07758a6200cd2448f1f6e7f3dd1a24af3c",
+                      "bytes": (1324573.5 * 2.0 + 450000.0) * 1024.0}
 
 
 def log(*a):
