@@ -3,9 +3,11 @@
 #include "block.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <vector>
 
 namespace csvd {
 
@@ -104,7 +106,7 @@ size_t BlockJob::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, 
   b += 8 * (size_t)((kMomWindow + 2 + 2) * n * Lp);  // Q ring, W, Vpad
   b += 8 * (size_t)(nvb * 2 * L2);                 // partial Gram matrices
   b += 8 * (size_t)(7 * L2);                       // reduced Gram matrices, R1, R1^-1, T
-  b += 8 * (size_t)(4 * (Kcap + 1) * L2);          // A, B, M, N histories
+  b += 8 * (size_t)(5 * (Kcap + 1) * L2);          // A, B, M, N, P histories
   b += 16 * (size_t)(2 * S * (Kcap + 1) * L2);     // Hinv, Z histories
   b += 16 * (size_t)(2 * S * L2);                  // complex scratch
   b += 8 * (size_t)(S * Lp) + 8 * Lp + 16 * 4;     // res, beta0, counters
@@ -161,6 +163,7 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.Bh = (double *)take(8 * (size_t)((Kcap + 1) * L2));
   J.Mh = (double *)take(8 * (size_t)((Kcap + 1) * L2));
   J.Nh = (double *)take(8 * (size_t)((Kcap + 1) * L2));
+  J.Ph = (double *)take(8 * (size_t)((Kcap + 1) * L2));
   J.Hinv = (double2 *)take(16 * (size_t)(S * (Kcap + 1) * L2));
   J.Zh = (double2 *)take(16 * (size_t)(S * (Kcap + 1) * L2));
   J.ctmp = (double2 *)take(16 * (size_t)(2 * S * L2));
@@ -398,6 +401,24 @@ hipError_t BEngine::start(BlockJob *j) {
   // one-pass flag, counter and robust-step mark of this round start at zero
   if ((e = hipMemsetAsync(J.flags + 1, 0, 3 * sizeof(int), st_)) != hipSuccess) return e;
   if ((e = start_block(j, true)) != hipSuccess) return e;
+  // A numerically rank-deficient starting block (a filtered block with fewer
+  // values than columns, a starting guess close to an invariant subspace of
+  // lower dimension) makes the first new blocks tiny and ill conditioned,
+  // beyond what Cholesky QR resolves: its first steps orthonormalise by
+  // Householder QR.  (Rounds after the first always do.)  The test reads the
+  // diagonal of B_0 = R from the QR of the starting block.
+  if (j->robust_steps == 0) {
+    std::vector<double> r((size_t)J.Lp * J.Lp);
+    if ((e = hipMemcpyAsync(r.data(), J.Bh, 8 * r.size(), hipMemcpyDeviceToHost, st_)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st_)) != hipSuccess) return e;
+    double dmax = 0.0, dmin = HUGE_VAL;
+    for (int i = 0; i < J.Lp; ++i) {
+      const double d = std::fabs(r[(size_t)i * J.Lp + i]);
+      dmax = std::max(dmax, d);
+      dmin = std::min(dmin, d);
+    }
+    if (!(dmin > kRankTol * dmax)) j->robust_steps = kRobustSteps;
+  }
   if ((e = launch_b_store32(J, 0, st_)) != hipSuccess) return e;
   BBatch b = j->solo;
   b.clock = clock_;
@@ -441,7 +462,56 @@ hipError_t BEngine::start_block(BlockJob *j, bool first) {
   return orth_block(j, J.Vpad, j->block_ptr(0), first ? J.Bh : nullptr, first ? J.beta0 : nullptr);
 }
 
-// After gamma wrote W3 = W' - Q_k (P + C) into block k + 1 of a robust step:
+// Step 0 of a round without Householder steps.  A starting block close to an
+// invariant subspace (a good starting guess) gives new directions many orders
+// smaller than the products they come from, and one that mixes invariant and
+// other directions gives a first new block of widely different column
+// sizes; Cholesky QR of such a block loses the accuracy the shifted solves
+// need.  From the reduced Gram matrices of step 0: per column, ||w2_c||^2 =
+// G2(c, c) against the squared norm before the projection, ||P(:, c)||^2 +
+// G2(c, c) (below kInvTol^2: nearly invariant), and the pivots of the
+// Cholesky factorisation of G2 - C^T C = W3^T W3 (smallest over largest
+// below kInvTol^2: cond(W3) above 1 / kInvTol).  Either makes the job take
+// Householder steps from step 0 on.
+hipError_t BEngine::check_first_block(BlockJob *j) {
+  const BJobDesc &J = j->h;
+  const int Lp = J.Lp;
+  const size_t L2 = (size_t)Lp * Lp;
+  std::vector<double> red(3 * L2);
+  hipError_t e = hipMemcpyAsync(red.data(), J.red, 8 * red.size(), hipMemcpyDeviceToHost, st_);
+  if (e != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(st_)) != hipSuccess) return e;
+  const double *P = red.data(), *C = red.data() + L2, *G2 = red.data() + 2 * L2;
+  // G2 holds its upper 16 x 16 tiles: entry (r, c) at (r, c) when the tile of
+  // r is not below the tile of c, else at (c, r)
+  auto g2 = [&](int r, int c) { return (r >> 4) <= (c >> 4) ? G2[(size_t)r * Lp + c] : G2[(size_t)c * Lp + r]; };
+  double worst = HUGE_VAL;
+  for (int c = 0; c < Lp; ++c) {
+    double own = g2(c, c);
+    for (int i = 0; i < Lp; ++i) own += P[(size_t)i * Lp + c] * P[(size_t)i * Lp + c];
+    if (own > 0.0) worst = std::min(worst, g2(c, c) / own);
+  }
+  std::vector<double> M(L2);
+  for (int r = 0; r < Lp; ++r)
+    for (int c = 0; c < Lp; ++c) {
+      double v = g2(r, c);
+      for (int i = 0; i < Lp; ++i) v -= C[(size_t)i * Lp + r] * C[(size_t)i * Lp + c];
+      M[(size_t)r * Lp + c] = v;
+    }
+  double pmin = HUGE_VAL, pmax = 0.0;
+  for (int c = 0; c < Lp; ++c) {  // right-looking Cholesky, pivots only
+    const double d = M[(size_t)c * Lp + c];
+    pmin = std::min(pmin, d);
+    pmax = std::max(pmax, d);
+    if (!(d > 0.0)) break;
+    for (int r = c + 1; r < Lp; ++r)
+      for (int q = c + 1; q < Lp; ++q) M[(size_t)r * Lp + q] -= M[(size_t)r * Lp + c] * M[(size_t)c * Lp + q] / d;
+  }
+  if (worst < kInvTol * kInvTol || !(pmin > kInvTol * kInvTol * pmax)) j->robust_steps = kRobustSteps;
+  return hipSuccess;
+}
+
+// After gamma wrote W3 = W2 - Q_k C into block k + 1 of a robust step:
 // Q_{k+1} and (first pass) B_{k+1} = R by Householder QR.
 hipError_t BEngine::robust_finish(std::vector<BlockJob *> &v, bool first_pass) {
   for (BlockJob *j : v) {
@@ -598,6 +668,7 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
       if ((e = launch_bs_reduce(b, 0, 2, 1, 0, st_)) != hipSuccess) return e;
       for (BlockJob *j : p1_) {  // mark the robust steps for small1
         const int k = (int)(clock_ - j->h.start_clock);
+        if (k == 0 && j->robust_steps == 0 && (e = check_first_block(j)) != hipSuccess) return e;
         if (j->robust_steps > 0 && (k == 0 || k == j->robust_steps) &&
             (e = hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(j->h.flags + 3), k == 0 ? 1 : 0, 1, st_)) !=
                 hipSuccess)
@@ -633,7 +704,8 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = long_rows(p2_, 1)) != hipSuccess) return e;
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
     if ((e = long_rows(p2_, 2)) != hipSuccess) return e;
-    if ((e = launch_bs_tall(b, 0, 0, st_)) != hipSuccess) return e;
+    if ((e = launch_bs_tall(b, 0, 0, st_)) != hipSuccess) return e;  // W'
+    if ((e = launch_bs_tall(b, 1, 0, st_)) != hipSuccess) return e;  // W2 = W' - Q_k P_k
     if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
     if ((e = robust_finish(p2_, false)) != hipSuccess) return e;
   }
@@ -651,6 +723,7 @@ bool BEngine::graph_step_ok() const {
   if (!graphs_ || !p2_.empty()) return false;
   for (const BlockJob *j : p1_) {
     const int k = (int)(clock_ - j->h.start_clock);
+    if (k == 0) return false;  // the first step of a pass reads its Gram matrices on the host
     if (j->robust_steps > 0 && k <= j->robust_steps) return false;
     if (j->h.nseg1 + j->h.nseg2 > 0) return false;
   }

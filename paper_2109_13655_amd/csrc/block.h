@@ -44,8 +44,8 @@ struct BlockJob {
   int deflated_last = 0;   // deflated columns and one-pass steps at step K - 1 of the last pass 1
   int one_pass_last = 0;
   int robust_steps = 0;    // steps 0 .. robust_steps - 1 of each pass orthonormalise the new block by
-                           // Householder QR (rounds after the first start from a filtered block
-                           // whose first Krylov block is numerically rank deficient)
+                           // Householder QR (a filtered or otherwise nearly invariant starting block
+                           // makes the first Krylov blocks tiny and numerically rank deficient)
   double *block_ptr(int k) const {  // Q_k in the basis storage (host view of the basis table)
     return qtab[(k / h.qC) % h.qT] + (size_t)(k % h.qC) * h.n * h.Lp;
   }
@@ -105,6 +105,9 @@ class BEngine {
   // robust steps of the jobs in v after their gamma (Q_{k+1} from W3)
   hipError_t robust_finish(std::vector<BlockJob *> &v, bool first_pass);
   hipError_t launch_shift(const BBatch &b, int init);
+  // step 0 of a round without Householder steps: takes them when the
+  // starting block is close to an invariant subspace
+  hipError_t check_first_block(BlockJob *j);
   // long rows of the jobs in v for one product (side 1: A, side 2: A^T)
   hipError_t long_rows(const std::vector<BlockJob *> &v, int side);
   // The shift recurrences of the steps since the last poll, launched together

@@ -120,6 +120,7 @@ struct BJobDesc {
   double *red;                     // 4 x Lp x Lp reduced Gram matrices (P, C, G2, G3)
   double *scr;                     // 3 x Lp x Lp: R1, R1^-1, T of the current step
   double *Ah, *Bh, *Mh, *Nh;       // (Kcap + 1) x Lp x Lp step histories
+  double *Ph;                      // (Kcap + 1) x Lp x Lp: P = Q_k^T W' of each step (second pass)
   double2 *Hinv, *Zh;              // S x (Kcap + 1) x Lp x Lp
   double2 *ctmp;                   // S x 2 x Lp x Lp complex scratch
   double *res;                     // S x Lp residual estimates
@@ -196,7 +197,11 @@ constexpr int kBlockMaxVB = 256;  // workgroups per job in the tall kernels
 constexpr int kBlockPollSteps = 4;  // block steps between convergence polls
 constexpr int kMomWindow = 16;   // second-pass steps per moment accumulation (basis ring = window + 2)
 constexpr double kDeflTol = 1e-10;  // relative size below which a new basis direction is deflated
-constexpr int kRobustSteps = 2;      // Householder-orthonormalised steps at the start of rounds after the first
+constexpr int kRobustSteps = 2;      // Householder-orthonormalised steps at the start of a round (rounds after
+                                     // the first, a rank-deficient or nearly invariant starting block)
+constexpr double kRankTol = 1e-6;    // min |R_ii| <= kRankTol max |R_ii| of the starting block: rank deficient
+constexpr double kInvTol = 1e-4;     // first new block: a direction below kInvTol of its product (nearly invariant
+                                     // start) or cond above 1 / kInvTol takes Householder steps
 constexpr double kOnePassRho = 1.5;  // one Cholesky pass when ||R1||_F ||R1^-1||_F <= 1.5 Lp
 
 hipError_t launch_b_spmm_a(const BBatch &b, hipStream_t st);

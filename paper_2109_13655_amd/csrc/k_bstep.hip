@@ -1,19 +1,26 @@
 // Block Lanczos step on the n x Lp blocks (Lp = 16, 32 or 64), FP64 MFMA.
 //
 // Step k turns W = A^T A Q_k into Q_{k+1} by block classical Gram-Schmidt
-// against Q_k, applied twice (the first projection explicitly, so that a
-// new block much smaller than W is still resolved), and CholeskyQR2:
+// against Q_k, applied twice, and CholeskyQR2:
 //
 //   alpha:  W' = W - Q_{k-1} B_k^T (in place);  P = Q_k^T W'
-//   beta:   W2 = W' - Q_k P (not stored);  C = Q_k^T W2,  G2 = W2^T W2
-//   small1: A_k = sym(P);  R1 = chol(G2 - C^T C);  T = (P + C) R1^-1
-//   gamma0: Y = W' R1^-1 - Q_k T (not stored);  G3 = Y^T Y
+//   beta:   W2 = W' - Q_k P (in place);  C = Q_k^T W2,  G2 = W2^T W2
+//   small1: A_k = sym(P);  R1 = chol(G2 - C^T C);  T = C R1^-1
+//   gamma0: Y = W2 R1^-1 - Q_k T (not stored);  G3 = Y^T Y
 //   small2: R2 = chol(G3);  M = R1^-1 R2^-1;  N = T R2^-1;  B_{k+1} = R2 R1
-//   gamma:  Q_{k+1} = Y R2^-1 = W' M - Q_k N
+//   gamma:  Q_{k+1} = Y R2^-1 = W2 M - Q_k N
+//
+// The first projection is applied explicitly and stored, and the second one
+// (C, of the size of the rounding errors of the first) acts on W2: the new
+// block is then exact to working precision relative to its own size.  With
+// the two coefficients combined (W' - Q_k (P + C)) the result carries errors
+// of eps ||W'|| along Q_k, which dominate when the new block is much smaller
+// than W' (a nearly invariant starting block: rounds after the first, or a
+// good starting guess) and spoil the solutions at the 1e-8 level.
 //
 // When the first Cholesky factor is well conditioned (rho = ||R1||_F
 // ||R1^-1||_F / Lp <= onepass_rho, no deflated column; rho >= 1, and rho
-// close to 1 bounds cond(R1) close to 1), Y = W' R1^-1 - Q_k T is already
+// close to 1 bounds cond(R1) close to 1), Y = W2 R1^-1 - Q_k T is already
 // orthonormal to working accuracy: small1 then takes M = R1^-1, N = T,
 // B_{k+1} = R1 and marks the step (flags[1]), and gamma0, its reduction and
 // small2 return at once.
@@ -22,8 +29,8 @@
 // squared norm before the projection is rounding noise (the space is
 // exhausted) and is deflated: zero row in R, zero column of Q_{k+1}.  The
 // second pass of the method (regenerating Q_k for the moments) runs alpha
-// without Gram matrices and gamma, the same kernels, so the basis is
-// reproduced bit for bit.
+// and beta without Gram matrices (beta with P from the history of the first
+// pass) and gamma, the same kernels, so the basis is reproduced bit for bit.
 //
 // Tall kernels: a job's rows are cut into 128-row chunks; each of its nvb
 // workgroups (8 waves, one 16-row panel each, two waves per SIMD) walks the
@@ -252,8 +259,9 @@ __device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, bo
 // ---------------------------------------------------------- tall passes
 // kTallAlpha: W' = W - Q_{k-1} B_k^T stored in place; Gram Q_k^T W' (when
 //   grams = 1).
-// kTallBeta:  W2 = W' - Q_k P (not stored); Grams Q_k^T W2 and W2^T W2.
-// kTallGamma0: Y = W' R1^-1 - Q_k T (not stored); Gram Y^T Y.
+// kTallBeta:  W2 = W' - Q_k P stored in place; Grams Q_k^T W2 and W2^T W2
+//   (grams = 1, P reduced from alpha's Gram; grams = 0: P from the history).
+// kTallGamma0: Y = W2 R1^-1 - Q_k T (not stored); Gram Y^T Y.
 enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
 
 // gamma0 (the second Cholesky QR pass); its Gram tiles are staged through
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(kTallThreads) void bs_gamma0(const BJobDesc *__rest
 }
 
 // ------------------------------------------------------------------ gamma
-// Q_{k+1} = W' M_k - Q_k N_k
+// Q_{k+1} = W2 M_k - Q_k N_k
 template <int LP>
 __global__ __launch_bounds__(kTallThreads) void bs_gamma(const BJobDesc *__restrict__ jobs, int njob,
                                                      const int *__restrict__ toff,
@@ -372,7 +380,7 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
   if (MODE == kTallAlpha) {
     if (useQ) stage_mat<LP, NTH>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
   } else {
-    stage_mat<LP, NTH>(gp(J.red), false, true, S2);  // -P
+    stage_mat<LP, NTH>(grams ? gp(J.red) : gp(J.Ph) + (int64_t)k * L2, false, true, S2);  // -P
   }
   __syncthreads();
   v4d acc[NA];
@@ -384,7 +392,7 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
     v4d D[4];
     load_dl<LP>(X, r0, n, D);
     if (useQ) panel_mm<LP>(MODE == kTallAlpha ? Pv : Qc, r0, n, S2, D);
-    if (MODE == kTallAlpha && useQ) store_dl<LP>(X, r0, n, D);
+    if (MODE == kTallAlpha && useQ) store_dl<LP>(X, r0, n, D);  // W' in place
     if (grams) {
       __builtin_amdgcn_sched_barrier(0);  // Q_k panel loads after the update (register pressure)
       if (NF) {
@@ -407,6 +415,7 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
             for (int v = 0; v < 4; ++v) acc[u] = mfma4(D[ti][v], D[tj][v], acc[u]);
       }
     }
+    if (MODE == kTallBeta) store_dl<LP>(X, r0, n, D);  // W2 in place
   }
   if (!grams) return;
   // fixed-order sum of the waves' tiles in LDS (the staged matrices are done)
@@ -857,10 +866,11 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
     thr[t] = fmax(kDeflTol * kDeflTol * own, flo);
   }
   {
-    GLB double *Ak = gp(J.Ah) + (int64_t)k * L2;
+    GLB double *Ak = gp(J.Ah) + (int64_t)k * L2, *Pk = gp(J.Ph) + (int64_t)k * L2;
     for (int e = t; e < L2; e += kThreads) {
       const int r = e / LP, c = e - r * LP;
       Ak[e] = 0.5 * (Pm[r * SS + c] + Pm[c * SS + r]);
+      Pk[e] = Pm[r * SS + c];  // for beta of the second pass
     }
     mm_lds<LP, true>(Cm, Cm, -1.0, D);  // G2 - C^T C
   }
@@ -868,7 +878,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
   __syncthreads();
   chol_inv_blocked<LP>(As, Xs, thr, dead, Tmp);
   // a step marked robust (flags[3], set by the host) leaves the new block to a
-  // Householder QR after gamma: M = I, N = P + C make gamma write W3
+  // Householder QR after gamma: M = I, N = C make gamma write W3 = W2 - Q_k C
   const bool robust = gp(J.flags)[3] != 0;
   // one-pass test: rho = ||R1||_F ||R1^-1||_F / Lp, sums in a fixed order
   __shared__ int one_pass;
@@ -899,7 +909,7 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
         one_pass = op;
         gp(J.flags)[1] = op;
         if (op) gp(J.flags)[0] = 0;
-        gp(J.flags)[2] += op;  // one-pass steps of this round
+        gp(J.flags)[2] += (op && !robust) ? 1 : 0;  // one-pass Cholesky QR steps of this round
       }
     }
     __syncthreads();
@@ -916,17 +926,15 @@ __global__ __launch_bounds__(kThreads) void bs_small1(const BJobDesc *__restrict
       if (!robust) Bn[e] = rv;
       Mk[e] = robust ? (r == c ? 1.0 : 0.0) : Xs[r * SS + c];
     }
-    Pm[r * SS + c] += Cm[r * SS + c];  // P + C
   }
-  __syncthreads();
   if (robust) {
     GLB double *Nk = gp(J.Nh) + (int64_t)k * L2;
-    for (int e = t; e < L2; e += kThreads) Nk[e] = Pm[(e / LP) * SS + (e % LP)];
+    for (int e = t; e < L2; e += kThreads) Nk[e] = Cm[(e / LP) * SS + (e % LP)];
   }
   if (act) {
 #pragma unroll
     for (int tj = 0; tj < NT; ++tj) D[tj] = v4d{0.0, 0.0, 0.0, 0.0};
-    mm_lds<LP, false>(Pm, Xs, 1.0, D);
+    mm_lds<LP, false>(Cm, Xs, 1.0, D);  // T = C R1^-1
   }
   regs_to_glb<LP>(D, T);
   if (op && !robust) regs_to_glb<LP>(D, gp(J.Nh) + (int64_t)k * L2);

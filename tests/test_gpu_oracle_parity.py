@@ -551,3 +551,41 @@ def test_served_results_against_oracle():
         cs.csvd_server_destroy(srv)
         for c in ctxs:
             cs.csvd_destroy(c)
+
+
+def test_block_nearly_invariant_start():
+    """A second round starts from the filtered block of the first, which is
+    nearly invariant: its new Krylov blocks are about 1e-8 of the products
+    they come from, so the second projection must act on the explicitly
+    projected block (with the two projections combined the moments carried
+    errors near 1e-8 and the triplets 6e-8 on this problem), and a warm
+    start (ell = 1 from the oracle's exact filtered block, as many values in
+    the interval as columns) needs Householder QR for its first steps (with
+    Cholesky QR: 7.5e-8).  Both against the exact values and the FP64
+    residual target."""
+    I, t = synth.batch_pool(count=8)[7]
+    A = I.dense()
+    G = A.T @ A
+    # the interval of the batched workload: about t values near the median,
+    # read off a same-distribution sample (here 32 values for t = 31)
+    k = max(1, int(round(I.nnz / I.n)))
+    a, b, _, _ = synth.interval_from_sample(I.m, I.n, k, t, scale=max(1, I.n // 1000), config=3)
+    s_t, _, _, sall = truth.dense_truth(I, a, b)
+    V = synth.v_in(I.n, 32, 3, 7)
+    sh, c = method.Q.moment_coeffs(a, b, 16, 4, 0.1, method.Q.PLAIN)
+    R = method.moment_sums(method.shifted_solves(G, sh, V), c[:, :1])[0]
+    ctx = make_ctx(I)
+    try:
+        for name, ell, Vin in (("ell 2", 2, V), ("warm start", 1, np.ascontiguousarray(R))):
+            p = cs.csvd_params_default(L=32, M=4, N=16, ell=ell, solver=cs.CSVD_SOLVER_BLOCK)
+            st = cs.csvd_solve_interval(ctx, a, b, p, Vin)
+            sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+            info = cs.csvd_get_info(ctx)
+            say(name, "status", st, "steps", info.iterations_total, "t_hat", sig.size, "max resid", res.max())
+            assert st == cs.CSVD_OK
+            assert sig.size == s_t.size
+            np.testing.assert_allclose(sig, s_t, rtol=1e-9, atol=0)
+            r_host = check_device_residuals(I, sig, U, Vv, res, sall[0])
+            assert r_host.max() <= 1e-8
+    finally:
+        cs.csvd_destroy(ctx)
