@@ -194,7 +194,7 @@ constexpr int kBlockMaxLp = 64;   // widest block of the block Lanczos engine
 constexpr int kBlockMinLp = 16;   // narrowest (MFMA tile width)
 constexpr int kBlockPanel = 64;   // rows per chunk of the tall kernels
 constexpr int kBlockMaxVB = 256;  // workgroups per job in the tall kernels
-constexpr int kBlockPollSteps = 4;  // block steps between convergence polls
+constexpr int kBlockPollSteps = 8;  // block steps between convergence polls
 constexpr int kMomWindow = 16;   // second-pass steps per moment accumulation (basis ring = window + 2)
 constexpr double kDeflTol = 1e-10;  // relative size below which a new basis direction is deflated
 constexpr int kRobustSteps = 2;      // Householder-orthonormalised steps at the start of a round (rounds after
