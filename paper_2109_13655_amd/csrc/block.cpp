@@ -704,8 +704,7 @@ hipError_t BEngine::step(KernelTimer *timer, bool sample) {
     if ((e = long_rows(p2_, 1)) != hipSuccess) return e;
     if ((e = launch_b_spmm_at(b, st_)) != hipSuccess) return e;
     if ((e = long_rows(p2_, 2)) != hipSuccess) return e;
-    if ((e = launch_bs_tall(b, 0, 0, st_)) != hipSuccess) return e;  // W'
-    if ((e = launch_bs_tall(b, 1, 0, st_)) != hipSuccess) return e;  // W2 = W' - Q_k P_k
+    if ((e = launch_bs_tall(b, 0, 0, st_)) != hipSuccess) return e;  // W2 = W - Q_{k-1} B_k^T - Q_k P_k
     if ((e = launch_bs_gamma(b, st_)) != hipSuccess) return e;
     if ((e = robust_finish(p2_, false)) != hipSuccess) return e;
   }

@@ -29,8 +29,9 @@
 // squared norm before the projection is rounding noise (the space is
 // exhausted) and is deflated: zero row in R, zero column of Q_{k+1}.  The
 // second pass of the method (regenerating Q_k for the moments) runs alpha
-// and beta without Gram matrices (beta with P from the history of the first
-// pass) and gamma, the same kernels, so the basis is reproduced bit for bit.
+// without Gram matrices, which then also forms W2 with P from the history of
+// the first pass, and gamma: the same products in the same order, so the
+// basis is reproduced bit for bit.
 //
 // Tall kernels: a job's rows are cut into 128-row chunks; each of its nvb
 // workgroups (8 waves, one 16-row panel each, two waves per SIMD) walks the
@@ -257,10 +258,10 @@ __device__ __forceinline__ void stage_mat(const GLB double *__restrict__ src, bo
 }
 
 // ---------------------------------------------------------- tall passes
-// kTallAlpha: W' = W - Q_{k-1} B_k^T stored in place; Gram Q_k^T W' (when
-//   grams = 1).
-// kTallBeta:  W2 = W' - Q_k P stored in place; Grams Q_k^T W2 and W2^T W2
-//   (grams = 1, P reduced from alpha's Gram; grams = 0: P from the history).
+// kTallAlpha: W' = W - Q_{k-1} B_k^T stored in place and its Gram Q_k^T W'
+//   (grams = 1, first pass); grams = 0 (second pass): W2 = W' - Q_k P_k
+//   with P_k from the history, stored in place (beta's work, fused).
+// kTallBeta:  W2 = W' - Q_k P stored in place; Grams Q_k^T W2 and W2^T W2.
 // kTallGamma0: Y = W2 R1^-1 - Q_k T (not stored); Gram Y^T Y.
 enum { kTallAlpha = 0, kTallBeta = 1, kTallGamma0 = 2 };
 
@@ -379,8 +380,9 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
   const bool useQ = (MODE != kTallAlpha || k > 0);
   if (MODE == kTallAlpha) {
     if (useQ) stage_mat<LP, NTH>(gp(J.Bh) + (int64_t)k * L2, true, true, S2);  // -B_k^T
+    if (!grams) stage_mat<LP, NTH>(gp(J.Ph) + (int64_t)k * L2, false, true, S1);  // -P_k (second pass)
   } else {
-    stage_mat<LP, NTH>(grams ? gp(J.red) : gp(J.Ph) + (int64_t)k * L2, false, true, S2);  // -P
+    stage_mat<LP, NTH>(gp(J.red), false, true, S2);  // -P
   }
   __syncthreads();
   v4d acc[NA];
@@ -392,7 +394,14 @@ __global__ __launch_bounds__(NTH, (MODE == kTallBeta && LP == 64) ? 1 : 2) void 
     v4d D[4];
     load_dl<LP>(X, r0, n, D);
     if (useQ) panel_mm<LP>(MODE == kTallAlpha ? Pv : Qc, r0, n, S2, D);
-    if (MODE == kTallAlpha && useQ) store_dl<LP>(X, r0, n, D);  // W' in place
+    if (MODE == kTallAlpha && !grams) {
+      // second pass: W2 = W' - Q_k P_k with the products and their order of
+      // beta in the first pass, so the stored W2 is the same bits
+      panel_mm<LP>(Qc, r0, n, S1, D);
+      store_dl<LP>(X, r0, n, D);
+    } else if (MODE == kTallAlpha && useQ) {
+      store_dl<LP>(X, r0, n, D);  // W' in place
+    }
     if (grams) {
       __builtin_amdgcn_sched_barrier(0);  // Q_k panel loads after the update (register pressure)
       if (NF) {
