@@ -617,22 +617,28 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   HIPCHK(ctx, hipMemcpyAsync(dJ.p, Jm.data(), sizeof(double) * Jm.size(), hipMemcpyHostToDevice, st));
   // one-sided Jacobi; a pair is rotated while |a_p^T a_q| > sqrt(rows) eps
   // ||a_p|| ||a_q|| (the rounding level of the dot product itself, as in
-  // LAPACK's one-sided Jacobi): below it a rotation only moves noise
-  // (square A and V of jacobi_padded_cols columns: pairs of column blocks
-  // in LDS where the size allows, else one launch per column pairing)
+  // LAPACK's one-sided Jacobi): below it a rotation only moves noise.  Columns
+  // with ||a_p|| <= eps^2 ||A||_F (fro2 = ||A||_F^2, from the host copy) are
+  // not rotated: they lie far under the rank cut delta s_1 of every useful
+  // delta and can only lose norm, while a rank-deficient S-hat leaves columns
+  // whose squared norms are denormal, on which rotations need not converge.
+  // Square A and V of jacobi_padded_cols columns: pairs of column blocks in
+  // LDS where the size allows, else one launch per column pairing.
   bool sweeps_exhausted = false;
-  auto jacobi = [&](double *A, int rows, int ncol_even, double *V, int vrows) -> int {
-    const double tol = std::sqrt((double)rows) * 2.220446049250313e-16;
+  auto jacobi = [&](double *A, int rows, int ncol_even, double *V, int vrows, double fro2) -> int {
+    constexpr double eps = 2.220446049250313e-16;
+    const double tol = std::sqrt((double)rows) * eps;
+    const double floor2 = eps * eps * eps * eps * fro2;
     const int w = jacobi_block_width(ncol_even);
     const int nsteps = w ? ncol_even / w - 1 : ncol_even - 1;
     for (int sweep = 0; sweep < 60; ++sweep) {
       HIPCHK(ctx, hipMemsetAsync(dcnt.p, 0, sizeof(int), st));
       for (int s2 = 0; s2 < nsteps; ++s2) {
         if (w)
-          HIPCHK(ctx, launch_jacobi_blk(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol, dcnt.as<int>(),
-                                        st));
+          HIPCHK(ctx, launch_jacobi_blk(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol, floor2,
+                                        dcnt.as<int>(), st));
         else
-          HIPCHK(ctx, launch_jacobi_step(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol,
+          HIPCHK(ctx, launch_jacobi_step(A, ncol_even, rows, ncol_even, V, ncol_even, vrows, s2, tol, floor2,
                                          dcnt.as<int>(), st));
       }
       int cnt = 0;
@@ -643,7 +649,9 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
     sweeps_exhausted = true;  // reported in csvd_info and by the solve's status
     return CSVD_OK;
   };
-  int rc = jacobi(dRt.as<double>(), LMe, LMe, dJ.as<double>(), LMe);
+  double fro2R = 0.0;
+  for (double x : Rt) fro2R += x * x;
+  int rc = jacobi(dRt.as<double>(), LMe, LMe, dJ.as<double>(), LMe, fro2R);
   if (rc) return rc;
   std::vector<double> sS(LMe);
   HIPCHK(ctx, launch_col_norms(dRt.as<double>(), LMe, LMe, LMe, dnorm.as<double>(), st));
@@ -713,7 +721,9 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
     HIPCHK(ctx, ws_grow(dQ, sizeof(double) * Ie.size()));
     HIPCHK(ctx, hipMemcpyAsync(dB.p, Be.data(), sizeof(double) * Be.size(), hipMemcpyHostToDevice, st));
     HIPCHK(ctx, hipMemcpyAsync(dQ.p, Ie.data(), sizeof(double) * Ie.size(), hipMemcpyHostToDevice, st));
-    rc = jacobi(dB.as<double>(), re, re, dQ.as<double>(), re);
+    double fro2B = 0.0;
+    for (double x : Be) fro2B += x * x;
+    rc = jacobi(dB.as<double>(), re, re, dQ.as<double>(), re, fro2B);
     if (rc) return rc;
     phi.assign(re, 0.0);
     HIPCHK(ctx, launch_col_norms(dB.as<double>(), re, re, re, dnorm.as<double>(), st));

@@ -293,14 +293,14 @@ hipError_t launch_hh_step(double *X, int64_t ld, int rows, int cols, int j, doub
 hipError_t launch_hh_apply(const double *Xr, int64_t ldr, int rows, int j, const double *tau, double *Z,
                            int64_t ldz, int zcols, hipStream_t st);
 hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, double *V, int64_t ldv,
-                              int vrows, int step, double tol, int *counter, hipStream_t st);
+                              int vrows, int step, double tol, double floor2, int *counter, hipStream_t st);
 // Block-pair Jacobi (k_dense.hip): columns in blocks of jacobi_block_width(n)
 // (0: use the per-column kernel); ncol must be jacobi_padded_cols(n), rows
 // and vrows at most 4096 / width; one sweep is steps 0 .. ncol / width - 2.
 int jacobi_block_width(int n);
 int jacobi_padded_cols(int n);
 hipError_t launch_jacobi_blk(double *A, int64_t lda, int rows, int ncol, double *V, int64_t ldv, int vrows, int step,
-                             double tol, int *counter, hipStream_t st);
+                             double tol, double floor2, int *counter, hipStream_t st);
 constexpr int kHB = 32;  // panel width of the blocked Householder QR
 // workspace (doubles) of the blocked QR of a rows x cols matrix: partial sums,
 // W, V^T V and the T factors of every panel (kept for hh_apply_blocked)

@@ -127,10 +127,22 @@ hipError_t launch_hh_apply(const double *Xr, int64_t ldr, int rows, int nref_dir
 }
 
 // ------------------------------------------------------------------ Jacobi
+// A pair is rotated while |a_p^T a_q| > tol ||a_p|| ||a_q|| and both squared
+// norms exceed floor2.  The norms multiply after their square roots, so the
+// test cannot underflow; floor2 (the caller passes (eps^2 ||A||_F)^2, and
+// rotations leave ||A||_F unchanged) keeps columns far below the rounding
+// level of the whole matrix out of rotations: in denormal arithmetic a
+// rotation need not reduce |a_p^T a_q|, and a sweep would never end
+// rotation-free.  Above the floor |zeta| < 1 / (2 tol eps^2), which is finite.
+__device__ inline bool rotate_pair(double app, double aqq, double apq, double tol, double floor2) {
+  return apq != 0.0 && app > floor2 && aqq > floor2 && fabs(apq) > tol * (sqrt(app) * sqrt(aqq));
+}
+
 // Round-robin pairing over n (even) columns: index n-1 stays, the others
 // rotate; step s pairs (n-1, s) and ((s+b) mod (n-1), (s-b) mod (n-1)).
 __global__ __launch_bounds__(kThreads) void k_jacobi(double *A, int64_t lda, int rows, int ncol, double *V,
-                                                     int64_t ldv, int vrows, int step, double tol, int *counter) {
+                                                     int64_t ldv, int vrows, int step, double tol, double floor2,
+                                                     int *counter) {
   __shared__ double r0[4], r1[4], r2[4];
   const int b = blockIdx.x;
   const int n1 = ncol - 1;
@@ -168,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_jacobi(double *A, int64_t lda, int
   const double app = (r0[0] + r0[1]) + (r0[2] + r0[3]);
   const double aqq = (r1[0] + r1[1]) + (r1[2] + r1[3]);
   const double apq = (r2[0] + r2[1]) + (r2[2] + r2[3]);
-  if (apq == 0.0 || !(fabs(apq) > tol * sqrt(app * aqq))) return;
+  if (!rotate_pair(app, aqq, apq, tol, floor2)) return;
   const double zeta = (aqq - app) / (2.0 * apq);
   const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
   const double c = 1.0 / sqrt(1.0 + tt * tt);
@@ -188,9 +200,9 @@ __global__ __launch_bounds__(kThreads) void k_jacobi(double *A, int64_t lda, int
 }
 
 hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, double *V, int64_t ldv, int vrows,
-                              int step, double tol, int *counter, hipStream_t st) {
+                              int step, double tol, double floor2, int *counter, hipStream_t st) {
   hipLaunchKernelGGL(k_jacobi, dim3(cols_even / 2), dim3(kThreads), 0, st, A, lda, rows, cols_even, V, ldv, vrows,
-                     step, tol, counter);
+                     step, tol, floor2, counter);
   return hipGetLastError();
 }
 
@@ -205,7 +217,8 @@ hipError_t launch_jacobi_step(double *A, int64_t lda, int rows, int cols_even, d
 // test are those of k_jacobi.
 template <int W, int RMAX>
 __global__ __launch_bounds__(W * 64) void k_jacobi_blk(double *A, int64_t lda, int rows, int ncol, double *V,
-                                                       int64_t ldv, int vrows, int step, double tol, int *counter) {
+                                                       int64_t ldv, int vrows, int step, double tol, double floor2,
+                                                       int *counter) {
   static_assert(RMAX % 64 == 0, "whole rows per lane");
   constexpr int KR = RMAX / 64;  // rows per lane
   __shared__ double As[2 * W * RMAX], Vs[2 * W * RMAX];
@@ -296,7 +309,7 @@ __global__ __launch_bounds__(W * 64) void k_jacobi_blk(double *A, int64_t lda, i
     const double app = wave_sum0(spp);
     const double aqq = wave_sum0(sqq);
     const double apq = wave_sum0(spq);
-    if (apq != 0.0 && fabs(apq) > tol * sqrt(app * aqq)) {
+    if (rotate_pair(app, aqq, apq, tol, floor2)) {
       const double zeta = (aqq - app) / (2.0 * apq);
       const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double c = 1.0 / sqrt(1.0 + tt * tt);
@@ -350,16 +363,16 @@ int jacobi_padded_cols(int n) {
 }
 
 hipError_t launch_jacobi_blk(double *A, int64_t lda, int rows, int ncol, double *V, int64_t ldv, int vrows, int step,
-                             double tol, int *counter, hipStream_t st) {
+                             double tol, double floor2, int *counter, hipStream_t st) {
   const int w = jacobi_block_width(ncol);  // the width the columns were padded for
   if (w == 0 || ncol % (2 * w) != 0 || rows > 4096 / w || vrows > 4096 / w || step < 0 || step >= ncol / w - 1)
     return hipErrorInvalidValue;
   if (w == 16)
     hipLaunchKernelGGL((k_jacobi_blk<16, 256>), dim3(ncol / 32), dim3(1024), 0, st, A, lda, rows, ncol, V, ldv, vrows,
-                       step, tol, counter);
+                       step, tol, floor2, counter);
   else
     hipLaunchKernelGGL((k_jacobi_blk<8, 512>), dim3(ncol / 16), dim3(512), 0, st, A, lda, rows, ncol, V, ldv, vrows,
-                       step, tol, counter);
+                       step, tol, floor2, counter);
   return hipGetLastError();
 }
 

@@ -589,3 +589,43 @@ def test_block_nearly_invariant_start():
             assert r_host.max() <= 1e-8
     finally:
         cs.csvd_destroy(ctx)
+
+
+def test_block_rank_deficient_starting_block():
+    """A starting block with a repeated and a zero column is numerically rank
+    deficient: the first steps take Householder QR (the rank test on B_0),
+    the repeated column's moments equal its twin's and the zero column's are
+    zero, and moments and triplets match the oracle's direct solves from the
+    same block and the exact spectrum."""
+    I = synth.random_sparse(4000, 2000, 10, config=97)
+    A = I.dense()
+    G = A.T @ A
+    ev = np.linalg.eigvalsh(G)
+    a, b = synth.interval_by_count(ev, ev.size // 2, 12)
+    L, M, N = 16, 4, 16
+    V = synth.v_in(I.n, L, 23)
+    V[:, 5] = V[:, 3]
+    V[:, 9] = 0.0
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=L, M=M, N=N, solve_rtol=1e-12, solver=cs.CSVD_SOLVER_BLOCK)
+        st = cs.csvd_solve_interval(ctx, a, b, p, V)
+        info = cs.csvd_get_info(ctx)
+        say("rank-deficient start: status", st, cs.csvd_last_error(ctx), "steps", info.iterations, "deflated",
+            info.deflated, "t_hat", info.t_hat, "converged", info.converged, "sweeps", info.svd_sweeps_exhausted)
+        assert st == cs.CSVD_OK and info.solver == cs.CSVD_SOLVER_BLOCK
+        Sg = [cs.csvd_get_moment(ctx, k, I.n, L) for k in range(M + 1)]
+        sig, U, Vv, res = cs.csvd_get_triplets(ctx, I.m, I.n)
+    finally:
+        cs.csvd_destroy(ctx)
+    o = method.ss_svd(I, a, b, V, L, M, N, G=G)
+    ymax = max(np.linalg.norm(o["Y"][j]) for j in range(N // 2))
+    for k in range(M + 1):
+        scale = 2 * np.abs(o["c"][:, k]).sum() * ymax
+        assert np.linalg.norm(Sg[k] - o["S"][k]) <= 1e-9 * scale, k
+        assert np.linalg.norm(Sg[k][:, 5] - Sg[k][:, 3]) <= 1e-9 * scale, k
+        assert np.linalg.norm(Sg[k][:, 9]) <= 1e-12 * scale, k
+    s_t, U_t, V_t, sall = truth.dense_truth(I, a, b)
+    assert s_t.size == 12
+    compare_with_oracle(I, sig, U, Vv, res, (o["sigma"], o["U"], o["V"]), 1e-9, 1e-8, sall[0])
+    np.testing.assert_allclose(sig, s_t, rtol=1e-9)
