@@ -242,7 +242,8 @@ def bench_c3(args, cs, torch):
         a, b = sample_interval(I, t, 3)
         probs.append((I, a, b, synth.v_in(I.n, 32, 3, i)))
     log("c3 pool", len(probs), "problems, n from", min(P[0].n for P in probs), "to", max(P[0].n for P in probs))
-    p = cs.csvd_params_default(L=32, M=4, N=16, ell=args.ell)
+    extra = dict(ell_adaptive=1, resid_target=1e-8) if args.adaptive else {}
+    p = cs.csvd_params_default(L=32, M=4, N=16, ell=args.ell, **extra)
     ctxs = [cs.csvd_create(I.m, I.n, I.rowptr, I.colidx, I.vals) for I, _, _, _ in probs]
 
     def resid_of(c, I):
@@ -277,6 +278,7 @@ def bench_c3(args, cs, torch):
     stored_bat = sum(int(cs.csvd_get_info(c).basis_stored) for c in ctxs)
     log(f"batched: {t_bat:.3f}s, max resid {r_bat:.2e}")
     t_hat = [int(cs.csvd_get_info(c).t_hat) for c in ctxs]
+    rounds = [int(cs.csvd_get_info(c).rounds) for c in ctxs]
     for c in ctxs:
         cs.csvd_destroy(c)
     n = len(probs)
@@ -287,12 +289,13 @@ def bench_c3(args, cs, torch):
         "ms_per_step": t_bat * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"c3_pool_{n}_random_sparse_m5000-50000_n=m/2_8-16nnz_per_col", "N": 16, "L": 32,
-                   "M": 4, "ell": args.ell, "problems": n},
+                   "M": 4, "ell": args.ell, "ell_adaptive": int(args.adaptive), "problems": n},
         "sequential_value": ok_seq / t_seq, "batch_over_sequential": t_seq / t_bat,
         "meeting_target": {"batch": ok_bat, "sequential": ok_seq, "of": n},
         "all_solves_per_s": {"batch": n / t_bat, "sequential": n / t_seq},
         "max_rel_residual": max(r_seq, r_bat), "status_batch": st_bat, "status_sequential": st_seq,
         "t_hat_range": [min(t_hat), max(t_hat)], "basis_stored": {"sequential": stored_seq, "batch": stored_bat},
+        "problems_per_rounds": {str(r): rounds.count(r) for r in sorted(set(rounds))},
     }
     print(json.dumps(out), flush=True)
 
@@ -331,7 +334,8 @@ def bench_c4(args, cs, torch):
         now = time.perf_counter() - t0
         while nxt < len(reqs) and reqs[nxt]["arrival"] <= now:
             q = reqs[nxt]
-            p = cs.csvd_params_default(L=q["L"], M=4, N=16, ell=args.ell, resid_target=args.resid_target)
+            p = cs.csvd_params_default(L=q["L"], M=4, N=16, ell=args.ell, resid_target=args.resid_target,
+                                       ell_adaptive=int(args.adaptive))
             ids[nxt] = cs.csvd_server_submit(srv, ctxs[nxt], q["a"], q["b"], p)
             nxt += 1
         active = cs.csvd_server_step(srv, 32)
@@ -373,7 +377,8 @@ def bench_c4(args, cs, torch):
         "ms_per_step": t_end / len(reqs) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"c4_pool_{len(pool)}_random_sparse_n1e4-3e5_m=1.5n_12nnz_per_col",
-                   "arrival_rate": args.rate, "requests": len(reqs), "N": 16, "M": 4, "ell": args.ell},
+                   "arrival_rate": args.rate, "requests": len(reqs), "N": 16, "M": 4, "ell": args.ell,
+                   "ell_adaptive": int(args.adaptive)},
         "p50_ms": pct(0.5), "p99_ms": pct(0.99), "max_rel_residual": max(res),
         "meeting_target": ok, "all_requests_per_s": len(reqs) / t_end,
         "status": status, "makespan_s": t_end, "resid_target": args.resid_target,
@@ -531,13 +536,16 @@ def main():
                     help="c4: served requests drop triplets above this relative residual (0: keep all)")
     ap.add_argument("--ell", type=int, default=1,
                     help="c3 / c4: rounds of the moment iteration (the configs' value is 1)")
+    ap.add_argument("--adaptive", action="store_true",
+                    help="c3 / c4: with --ell > 1, a round after the first runs only for a problem whose "
+                         "triplets miss the 1e-8 target (ell_adaptive)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (a kernel of known traffic for "
                          "scaling the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path is single-GPU by design "
-              "(shift sharding across GPUs is described in DESIGN.md, not built)", file=sys.stderr)
+              "(sharding the shifts across GPUs is documented, not built)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

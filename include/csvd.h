@@ -110,6 +110,12 @@ typedef struct {
                           /* returned; csvd_info.dropped counts them and the solve        */
                           /* returns CSVD_ENOTCONV.  0 (default): every triplet in [a, b] */
                           /* that passes the spurious test is returned (Algorithm 1)     */
+  int32_t ell_adaptive;   /* 1: steps 3-5 run after every round of eq. iter1/iter2, and a */
+                          /* further round (from that round's S_0, at most ell rounds in  */
+                          /* all) runs only while some triplet's relative residual       */
+                          /* exceeds resid_target, which must then be > 0; every round   */
+                          /* accumulates all M+1 moments.  0 (default): exactly ell      */
+                          /* rounds, steps 3-5 after the last                            */
 } csvd_params;
 
 enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
@@ -117,7 +123,8 @@ enum { CSVD_SOLVER_AUTO = 0, CSVD_SOLVER_BLOCK = 1, CSVD_SOLVER_SINGLE = 2 };
 /* Fills *p with the paper's defaults: L=16, M=8, N=32, ell=1, delta=1e-20,
  * alpha=0.1, PLAIN, FP64, solve_rtol=1e-10, max_iters=1000000,
  * spurious_eps=1e-12, seed=2109, norm_a=0, window=0, check_solves=0,
- * solver=CSVD_SOLVER_AUTO, keep_basis=1, cholqr_passes=0, resid_target=0. */
+ * solver=CSVD_SOLVER_AUTO, keep_basis=1, cholqr_passes=0, resid_target=0,
+ * ell_adaptive=0. */
 int csvd_params_default(csvd_params *p);
 
 /* Creates a context holding a device copy of A in CSR form (and of A^T,
@@ -209,6 +216,8 @@ typedef struct {
   double  mixed_resid_fp32;  /* CSVD_MIXED with an FP32 stored basis: the largest relative */
                              /* triplet residual of the result from the FP32 basis (before */
                              /* any refinement); 0 otherwise                               */
+  int32_t rounds;            /* rounds of eq. iter1/iter2 that ran: ell, or fewer with    */
+                             /* csvd_params.ell_adaptive                                  */
 } csvd_info;
 
 int csvd_get_info(csvd_ctx *ctx, csvd_info *info);

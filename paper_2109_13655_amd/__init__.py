@@ -45,6 +45,7 @@ class csvd_params(C.Structure):
         ("spurious_eps", C.c_double), ("seed", C.c_uint64), ("norm_a", C.c_double),
         ("window", C.c_int32), ("check_solves", C.c_int32), ("solver", C.c_int32),
         ("keep_basis", C.c_int32), ("cholqr_passes", C.c_int32), ("resid_target", C.c_double),
+        ("ell_adaptive", C.c_int32),
     ]
 
 
@@ -63,7 +64,7 @@ class csvd_info(C.Structure):
         ("rest_ms", C.c_double), ("basis_stored", C.c_int32), ("one_pass_steps", C.c_int32),
         ("moments_ms", C.c_double), ("svd_sweeps_exhausted", C.c_int32),
         ("column_groups", C.c_int32), ("mixed_refined", C.c_int32), ("dropped", C.c_int32),
-        ("mixed_resid_fp32", C.c_double),
+        ("mixed_resid_fp32", C.c_double), ("rounds", C.c_int32),
     ]
 
     def as_dict(self):

@@ -210,6 +210,9 @@ int check_params(csvd_ctx *ctx, double a, double b, const csvd_params *p) {
   if (p->cholqr_passes != 0 && p->cholqr_passes != 2)
     return set_err(ctx, CSVD_EINVAL, "cholqr_passes must be 0 or 2");
   if (!(p->resid_target >= 0.0)) return set_err(ctx, CSVD_EINVAL, "resid_target must be >= 0");
+  if (p->ell_adaptive != 0 && p->ell_adaptive != 1) return set_err(ctx, CSVD_EINVAL, "ell_adaptive must be 0 or 1");
+  if (p->ell_adaptive && !(p->resid_target > 0.0))
+    return set_err(ctx, CSVD_EINVAL, "ell_adaptive needs resid_target > 0");
   return CSVD_OK;
 }
 
@@ -327,8 +330,9 @@ static int estimate_norm(csvd_ctx *ctx, double *out) {
 // Uploads the padded starting block of every column group: its columns
 // soff .. soff + Lg - 1 of V (column-major, leading dimension ldv, host),
 // padding columns from pad_cols.
-static int upload_vpad(SolveRun &R, const double *V, int64_t ldv) {
+static int upload_vpad(SolveRun &R, const double *V, int64_t ldv, hipStream_t st = nullptr) {
   csvd_ctx *ctx = R.ctx;
+  if (!st) st = ctx->st;
   const int64_t n = ctx->n;
   const std::vector<BlockJob *> gs = R.groups();
   for (size_t g = 0; g < gs.size(); ++g) {
@@ -339,8 +343,8 @@ static int upload_vpad(SolveRun &R, const double *V, int64_t ldv) {
       for (int l = 0; l < L; ++l) Vp[(size_t)i * Lp + l] = V[(size_t)(l0 + l) * ldv + i];
       for (int l = L; l < Lp; ++l) Vp[(size_t)i * Lp + l] = R.pad_cols[g][(size_t)(l - L) * n + i];
     }
-    HIPCHK(ctx, hipMemcpyAsync(B.h.Vpad, Vp.data(), 8 * Vp.size(), hipMemcpyHostToDevice, ctx->st));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->st));
+    HIPCHK(ctx, hipMemcpyAsync(B.h.Vpad, Vp.data(), 8 * Vp.size(), hipMemcpyHostToDevice, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
   }
   return CSVD_OK;
 }
@@ -381,7 +385,10 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
   HIPCHK(ctx, hipMemcpyAsync(R.d_coef.p, cc.data(), sizeof(double) * cc.size(), hipMemcpyHostToDevice, ctx->st));
   R.block = use_block(p, ctx->n, groups_ok);
   if (R.block) {
-    const int Kmom = (p->ell == 1) ? M + 1 : 1;
+    // a round that may be the last accumulates every moment; the others only
+    // S_0, the next round's right-hand side (eq. iter1)
+    const bool all_moments = (p->ell == 1) || p->ell_adaptive;
+    const int Kmom = all_moments ? M + 1 : 1;
     // the deflation test of the basis is relative to ||A^T A||
     double na = p->norm_a;
     if (!(na > 0)) {
@@ -390,7 +397,7 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
     }
     const int64_t npad = round_up(n, kRowPad);
     HIPCHK(ctx, ctx->d_S.alloc(sizeof(double) * npad * (size_t)(M + 1) * L));
-    if (p->ell > 1) HIPCHK(ctx, R.d_Stmp.alloc(sizeof(double) * npad * (size_t)L));
+    if (!all_moments) HIPCHK(ctx, R.d_Stmp.alloc(sizeof(double) * npad * (size_t)L));
     // column groups of at most kBlockMaxLp columns (one group when L fits)
     const int ng = (L + kBlockMaxLp - 1) / kBlockMaxLp;
     R.bextra.clear();
@@ -411,7 +418,7 @@ int run_begin(SolveRun &R, csvd_ctx *ctx, double a, double b, const csvd_params 
       B->h.dscale = na * na;
       B->h.sL = L;
       B->h.soff = l0;
-      B->h.Sout = (p->ell > 1) ? R.d_Stmp.as<double>() : ctx->d_S.as<double>();
+      B->h.Sout = all_moments ? ctx->d_S.as<double>() : R.d_Stmp.as<double>();
       R.pad_cols[g].assign((size_t)n * (Lp - Lg), 0.0);
       if (Lp > Lg)
         gaussian_block(p->seed ^ (0xA5A5F00DCAFEULL + (uint64_t)g * 0x9E3779B97F4A7C15ULL),
@@ -490,7 +497,7 @@ static int run_after_round_block(SolveRun &R, bool *more) {
   R.gdone = 0;
   *more = false;
   const csvd_params &p = R.spec.p;
-  if (R.round + 1 < p.ell) {
+  if (R.round + 1 < p.ell && !p.ell_adaptive) {
     // eq. iter1: S_0^(nu) becomes the next right-hand side
     const int L = p.L;
     const int64_t n = ctx->n, npad = R.bjob->h.npad;
@@ -526,7 +533,7 @@ int run_after_round(SolveRun &R, bool *more) {
   if (rc) return rc;
   *more = false;
   const csvd_params &p = R.spec.p;
-  if (R.round + 1 < p.ell) {
+  if (R.round + 1 < p.ell && !p.ell_adaptive) {
     // eq. iter1: S_0^(nu) = 2 sum_j Re(w_j Y_j) becomes the next right-hand side
     const int64_t npad = R.job->h.npad;
     DevBuf nr;
@@ -552,6 +559,45 @@ int run_after_round(SolveRun &R, bool *more) {
     HIPCHK(ctx, launch_job_init(R.job->h, R.d_rhs.as<double>(), R.rhs_ld, ctx->st));
     *more = true;
   }
+  return CSVD_OK;
+}
+
+// ell_adaptive: called after steps 3-5 of a round.  When a triplet missed
+// resid_target (largest residual before drops) and rounds remain, the next
+// round of eq. iter1 starts from this round's S_0 (the first L columns of
+// the moments) and *more is set; the caller restarts the round's jobs.
+// Host copies go through `stream` (default: the context's stream).
+static int run_next_round(SolveRun &R, bool *more, hipStream_t stream = nullptr) {
+  csvd_ctx *ctx = R.ctx;
+  hipStream_t st = stream ? stream : ctx->st;
+  const csvd_params &p = R.spec.p;
+  *more = false;
+  if (!p.ell_adaptive || R.round + 1 >= p.ell || !(ctx->resid_all_max > p.resid_target)) return CSVD_OK;
+  const int L = p.L;
+  const int64_t n = ctx->n, npad = round_up(n, kRowPad);
+  if (R.block) {
+    std::vector<double> S0((size_t)npad * L);
+    HIPCHK(ctx, hipMemcpyAsync(S0.data(), ctx->d_S.p, sizeof(double) * S0.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    int rc = upload_vpad(R, S0.data(), npad, st);
+    if (rc) return rc;
+    for (BlockJob *B : R.groups()) B->robust_steps = kRobustSteps;  // see run_after_round_block
+  } else {
+    DevBuf nr;
+    HIPCHK(ctx, nr.alloc(sizeof(double) * npad * L));
+    HIPCHK(ctx, hipMemcpyAsync(nr.p, ctx->d_S.p, sizeof(double) * npad * L, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    std::swap(R.d_rhs.p, nr.p);
+    std::swap(R.d_rhs.bytes, nr.bytes);
+    R.rhs_ld = npad;
+    R.job->iters = 0;
+    R.job->finished = false;
+    R.job->converged = false;
+    HIPCHK(ctx, launch_job_init(R.job->h, R.d_rhs.as<double>(), R.rhs_ld, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+  }
+  R.round += 1;
+  *more = true;
   return CSVD_OK;
 }
 
@@ -904,6 +950,7 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   info.dropped = t - t_out;
   double t3 = now_ms();
   info.svd_sweeps_exhausted = sweeps_exhausted ? 1 : 0;
+  info.rounds = R.round + 1;
   info.iterations = R.block ? R.iters_last : R.job->iters;
   info.iterations_total = R.iters_total;
   info.t_hat = t_out;
@@ -1050,6 +1097,7 @@ int csvd_params_default(csvd_params *p) {
   p->keep_basis = 1;
   p->cholqr_passes = 0;
   p->resid_target = 0.0;
+  p->ell_adaptive = 0;
   return CSVD_OK;
 }
 
@@ -1148,76 +1196,94 @@ int csvd_solve_interval(csvd_ctx *ctx, double a, double b, const csvd_params *p,
   if (rc) return rc;
   KernelTimer timer;
   std::unique_ptr<BEngine> beng;
+  std::unique_ptr<Engine> seng;
   if (R->block) {
     // every column group is one job of the engine; a round ends when all have
     beng.reset(new BEngine(ctx->st));
-    BEngine &eng = *beng;
-    const std::vector<BlockJob *> gs = R->groups();
-    HIPCHK(ctx, eng.init());
-    for (BlockJob *B : gs) HIPCHK(ctx, eng.start(B));
-    int64_t step = 0;
-    while (true) {
-      for (int q = 0; q < kBlockPoll; ++q, ++step) HIPCHK(ctx, eng.step(&timer, (step % 8) == 3));
-      std::vector<BlockJob *> fin;
-      HIPCHK(ctx, eng.poll(&fin));
-      R->gdone += (int)fin.size();
-      if (R->gdone == (int)gs.size()) {
-        bool more = false;
-        rc = run_after_round(*R, &more);
-        if (rc) return rc;
-        if (more) {
-          for (BlockJob *B : gs) HIPCHK(ctx, eng.start(B));
-          continue;
-        }
-        break;
-      }
-    }
+    HIPCHK(ctx, beng->init());
+    for (BlockJob *B : R->groups()) HIPCHK(ctx, beng->start(B));
   } else {
-    Engine eng(ctx->st, W, mixed);
-    HIPCHK(ctx, eng.init());
-    HIPCHK(ctx, eng.add(R->job.get()));
-    while (true) {
-      HIPCHK(ctx, eng.run_window(&timer, 64));
-      std::vector<Job *> fin;
-      HIPCHK(ctx, eng.collect(&fin));
-      if (!fin.empty()) {
-        bool more = false;
-        rc = run_after_round(*R, &more);
-        if (rc) return rc;
-        if (more) {
-          HIPCHK(ctx, eng.add(R->job.get()));
-          continue;
-        }
-        break;
-      }
-    }
+    seng.reset(new Engine(ctx->st, W, mixed));
+    HIPCHK(ctx, seng->init());
+    HIPCHK(ctx, seng->add(R->job.get()));
   }
-  rc = run_finalize(*R);
-  if (rc) return rc;
-  const bool mixed_stored = R->block && R->bjob->mixed && R->bjob->stored_last;
-  const double resid_fp32 = ctx->resid_all_max;  // before any resid_target drop
-  if (mixed_stored && !(resid_fp32 <= kMixedResidTarget)) {
-    // FP64 refinement of a mixed-precision solve whose triplets miss the
-    // mixed target: the moments are accumulated again from the basis
-    // regenerated in FP64 (the histories and coefficients of the last round
-    // are kept), then steps 3-5 run again
-    int pending = 0;
-    for (BlockJob *B : R->groups())
-      if (B->stored_last) {
-        HIPCHK(ctx, beng->regenerate(B));
-        ++pending;
+  // rounds of eq. iter1/iter2, then steps 3-5; with ell_adaptive steps 3-5
+  // follow every round and decide whether another one runs
+  while (true) {
+    if (R->block) {
+      BEngine &eng = *beng;
+      const std::vector<BlockJob *> gs = R->groups();
+      int64_t step = 0;
+      while (true) {
+        for (int q = 0; q < kBlockPoll; ++q, ++step) HIPCHK(ctx, eng.step(&timer, (step % 8) == 3));
+        std::vector<BlockJob *> fin;
+        HIPCHK(ctx, eng.poll(&fin));
+        R->gdone += (int)fin.size();
+        if (R->gdone == (int)gs.size()) {
+          bool more = false;
+          rc = run_after_round(*R, &more);
+          if (rc) return rc;
+          if (more) {
+            for (BlockJob *B : gs) HIPCHK(ctx, eng.start(B));
+            continue;
+          }
+          break;
+        }
       }
-    while (pending > 0) {
-      for (int q = 0; q < kBlockPoll; ++q) HIPCHK(ctx, beng->step(&timer, false));
-      std::vector<BlockJob *> fin;
-      HIPCHK(ctx, beng->poll(&fin));
-      pending -= (int)fin.size();
+    } else {
+      Engine &eng = *seng;
+      while (true) {
+        HIPCHK(ctx, eng.run_window(&timer, 64));
+        std::vector<Job *> fin;
+        HIPCHK(ctx, eng.collect(&fin));
+        if (!fin.empty()) {
+          bool more = false;
+          rc = run_after_round(*R, &more);
+          if (rc) return rc;
+          if (more) {
+            HIPCHK(ctx, eng.add(R->job.get()));
+            continue;
+          }
+          break;
+        }
+      }
     }
     rc = run_finalize(*R);
     if (rc) return rc;
-    ctx->info.mixed_refined = 1;
+    const bool mixed_stored = R->block && R->bjob->mixed && R->bjob->stored_last;
+    const double resid_fp32 = ctx->resid_all_max;  // before any resid_target drop
+    if (mixed_stored && !(resid_fp32 <= kMixedResidTarget)) {
+      // FP64 refinement of a mixed-precision solve whose triplets miss the
+      // mixed target: the moments are accumulated again from the basis
+      // regenerated in FP64 (the histories and coefficients of the last round
+      // are kept), then steps 3-5 run again
+      int pending = 0;
+      for (BlockJob *B : R->groups())
+        if (B->stored_last) {
+          HIPCHK(ctx, beng->regenerate(B));
+          ++pending;
+        }
+      while (pending > 0) {
+        for (int q = 0; q < kBlockPoll; ++q) HIPCHK(ctx, beng->step(&timer, false));
+        std::vector<BlockJob *> fin;
+        HIPCHK(ctx, beng->poll(&fin));
+        pending -= (int)fin.size();
+      }
+      rc = run_finalize(*R);
+      if (rc) return rc;
+      ctx->info.mixed_refined = 1;
+    }
+    if (mixed_stored) ctx->info.mixed_resid_fp32 = resid_fp32;
+    bool again = false;
+    rc = run_next_round(*R, &again);
+    if (rc) return rc;
+    if (!again) break;
+    R->gdone = 0;
+    if (R->block)
+      for (BlockJob *B : R->groups()) HIPCHK(ctx, beng->start(B));
+    else
+      HIPCHK(ctx, seng->add(R->job.get()));
   }
-  if (mixed_stored) ctx->info.mixed_resid_fp32 = resid_fp32;
   if (p->check_solves) {
     rc = check_solves(*R);
     if (rc) return rc;
@@ -1515,14 +1581,29 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
   if (use_block(&params[0], ctxs[0]->n)) {
     std::vector<std::unique_ptr<SolveRun>> runs(count);
     std::map<BlockJob *, int> owner;
+    // epilogues in flight on the workers, and problems whose epilogue started
+    // another round (ell_adaptive): only the loop below touches the engine
+    std::mutex rq_mu;
+    std::condition_variable rq_cv;
+    std::vector<int> requeue;
+    int in_epilogue = 0;
     auto finish_job = [&](int i, hipStream_t fst) {
       SolveRun &R = *runs[i];
       csvd_ctx *ctx = ctxs[i];
       int rc;
+      bool again = false;
       try {
         rc = run_finalize(R, fst);
+        if (!rc) rc = run_next_round(R, &again, fst);
       } catch (...) {
         rc = set_err(ctx, CSVD_ENOMEM, "host allocation failed in the epilogue");
+      }
+      if (!rc && again) {
+        std::lock_guard<std::mutex> g(rq_mu);
+        requeue.push_back(i);
+        --in_epilogue;
+        rq_cv.notify_all();
+        return;
       }
       if (rc) {
         status[i] = rc;
@@ -1531,6 +1612,9 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
         status[i] = finish_status(ctx);
       }
       R.bjob.reset();  // free the basis histories
+      std::lock_guard<std::mutex> g(rq_mu);
+      --in_epilogue;
+      rq_cv.notify_all();
     };
     FinishPool pool(std::min<int>(count, kFinishThreads), finish_job);
     BEngine eng(st);
@@ -1558,7 +1642,17 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
       owner[runs[i]->bjob.get()] = i;
       if (eng.start(runs[i]->bjob.get()) != hipSuccess) return CSVD_EDEVICE;
     }
-    while (eng.active() > 0) {
+    while (true) {
+      {
+        std::unique_lock<std::mutex> g(rq_mu);
+        if (eng.active() == 0) {  // nothing to step: wait for the epilogues
+          rq_cv.wait(g, [&] { return in_epilogue == 0 || !requeue.empty(); });
+          if (requeue.empty()) break;
+        }
+        for (int i : requeue)
+          if (eng.start(runs[i]->bjob.get()) != hipSuccess) return CSVD_EDEVICE;
+        requeue.clear();
+      }
       for (int q = 0; q < kBlockPoll; ++q)
         if (eng.step(nullptr, false) != hipSuccess) return CSVD_EDEVICE;
       std::vector<BlockJob *> fin;
@@ -1575,6 +1669,10 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
         if (more) {
           if (eng.start(j) != hipSuccess) return CSVD_EDEVICE;
           continue;
+        }
+        {
+          std::lock_guard<std::mutex> g(rq_mu);
+          ++in_epilogue;
         }
         pool.push(i);  // steps 3-5 on a worker while the others go on
       }
@@ -1748,9 +1846,14 @@ static void srv_release(csvd_server *s, csvd_server::Req &R) {
   }
 }
 
-// finishes a request whose solves are done: dense steps and bookkeeping
-static void srv_finish(csvd_server *s, csvd_server::Req &R) {
+// finishes a request whose solves are done: dense steps and bookkeeping.
+// Returns true instead when ell_adaptive started another round (the caller
+// restarts the request's job).
+static bool srv_finish(csvd_server *s, csvd_server::Req &R) {
   int r2 = run_finalize(*R.run);
+  bool again = false;
+  if (!r2) r2 = run_next_round(*R.run, &again);
+  if (!r2 && again) return true;
   if (!r2 && R.p.check_solves) r2 = check_solves(*R.run);
   if (!r2) {
     if (R.run->job) R.ctx->job = std::move(R.run->job);
@@ -1761,6 +1864,7 @@ static void srv_finish(csvd_server *s, csvd_server::Req &R) {
   R.state = 2;
   srv_release(s, R);
   R.run.reset();
+  return false;
 }
 
 extern "C" {
@@ -1835,15 +1939,20 @@ int csvd_server_step(csvd_server *s, int32_t steps, int32_t *n_active) {
           if (s->beng->start(j) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "block start failed");
           continue;
         }
-        s->bowner.erase(it);
         if (r2) {
+          s->bowner.erase(it);
           R.status = r2;
           R.state = 2;
           srv_release(s, R);
           R.run.reset();
           continue;
         }
-        srv_finish(s, R);
+        // srv_finish releases the request (and its entry in bowner) unless
+        // ell_adaptive started another round
+        if (srv_finish(s, R)) {
+          if (s->beng->start(j) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "block start failed");
+          continue;
+        }
       }
     }
     for (int ei = 0; ei < 2; ++ei) {
@@ -1866,7 +1975,16 @@ int csvd_server_step(csvd_server *s, int32_t steps, int32_t *n_active) {
           if (e.add(j) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "engine add failed");
           continue;
         }
-        if (!r2) r2 = run_finalize(*R.run);
+        if (!r2) {
+          r2 = run_finalize(*R.run);
+          bool again = false;
+          if (!r2) r2 = run_next_round(*R.run, &again);
+          if (!r2 && again) {  // another round (ell_adaptive)
+            s->owner[j] = rid;
+            if (e.add(j) != hipSuccess) return srv_err(s, CSVD_EDEVICE, "engine add failed");
+            continue;
+          }
+        }
         if (!r2 && R.p.check_solves) r2 = check_solves(*R.run);
         if (!r2) {
           R.ctx->job = std::move(R.run->job);

@@ -37,6 +37,7 @@ def test_params_default_are_the_papers():
     assert (p.L, p.M, p.N, p.ell) == (16, 8, 32, 1)
     assert p.delta == 1e-20 and p.alpha == 0.1
     assert p.transform == cs.CSVD_PLAIN and p.precision == cs.CSVD_FP64
+    assert p.resid_target == 0.0 and p.ell_adaptive == 0
 
 
 @pytest.mark.parametrize("transform", [cs.CSVD_PLAIN, cs.CSVD_EXP])

@@ -325,6 +325,107 @@ def test_givens_1200x1000_ell2():
         cs.csvd_destroy(ctx)
 
 
+def _adaptive_params(solver, **kw):
+    # N = 8 makes the filter weak, so every round of eq. iter1 gains orders of
+    # magnitude on the mid problem (largest residual after one, two and three
+    # rounds: the oracle's direct solves 4.0e-5, 3.0e-9, 1.8e-11; the block
+    # solver 4.0e-5, 5.9e-9, 1.1e-10)
+    return cs.csvd_params_default(L=8, M=4, N=8, norm_a=1.0, solve_rtol=1e-12, solver=solver, **kw)
+
+
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_BLOCK, cs.CSVD_SOLVER_SINGLE])
+def test_adaptive_rounds(solver):
+    """ell_adaptive stops after the first round whose triplets all meet
+    resid_target: a target met after one round gives the bits of ell = 1;
+    1e-7 takes two rounds and 1e-9 three, each matching the oracle's and the
+    device's fixed-ell results; with ell = 2 the rounds stop at the cap and
+    the triplets above 1e-9 are dropped."""
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 12)
+    ctx = make_ctx(I)
+
+    def run(**kw):
+        st = cs.csvd_solve_interval(ctx, I.a, I.b, _adaptive_params(solver, **kw), V)
+        info = cs.csvd_get_info(ctx)
+        trip = cs.csvd_get_triplets(ctx, I.m, I.n)
+        say("adaptive", solver, kw, "status", st, "rounds", info.rounds, "t_hat", info.t_hat, "dropped",
+            info.dropped, "resid", info.max_triplet_resid)
+        return st, info, trip
+
+    try:
+        fixed = {}
+        for ell in (1, 2, 3):
+            st, info, trip = run(ell=ell)
+            assert st == cs.CSVD_OK and info.rounds == ell
+            fixed[ell] = trip
+        st, info, trip = run(ell=3, ell_adaptive=1, resid_target=1e-3)
+        assert st == cs.CSVD_OK and info.rounds == 1 and info.dropped == 0
+        for x, y in zip(trip, fixed[1]):
+            assert np.array_equal(x, y)
+        for target, rounds in ((1e-7, 2), (1e-9, 3)):
+            st, info, (sig, U, Vv, res) = run(ell=3, ell_adaptive=1, resid_target=target)
+            assert st == cs.CSVD_OK and info.rounds == rounds and info.dropped == 0
+            assert 0 < res.max() <= target
+            o = method.ss_svd(I, I.a, I.b, V, 8, 4, 8, ell=rounds)
+            assert sig.size == o["sigma"].size == fixed[rounds][0].size
+            np.testing.assert_allclose(sig, o["sigma"], rtol=1e-9)
+            np.testing.assert_allclose(sig, fixed[rounds][0], rtol=1e-10)
+            assert truth.triplet_residuals(I, sig, U, Vv, normA=1.0).max() <= target
+        st, info, (sig, _, _, res) = run(ell=2, ell_adaptive=1, resid_target=1e-9)
+        assert info.rounds == 2 and info.dropped >= 1 and st == cs.CSVD_ENOTCONV
+        assert sig.size + info.dropped == fixed[2][0].size
+        assert res.size == 0 or res.max() <= 1e-9
+        with pytest.raises(cs.CsvdError) as e:  # the stop needs a target
+            cs.csvd_solve_interval(ctx, I.a, I.b, _adaptive_params(solver, ell=2, ell_adaptive=1), V)
+        assert e.value.code == cs.CSVD_EINVAL
+    finally:
+        cs.csvd_destroy(ctx)
+
+
+def test_adaptive_rounds_batched_and_served_equal_solo():
+    """Problems that stop after one, two and three rounds in one batch, and
+    served together, give the bits of their solo solves (a batch runs steps
+    3-5 on worker threads and hands a problem that needs another round back
+    to the engine)."""
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 12)
+    ps = [_adaptive_params(cs.CSVD_SOLVER_BLOCK, ell=3, ell_adaptive=1, resid_target=t) for t in (1e-3, 1e-7, 1e-9)]
+    ctxs = [make_ctx(I) for _ in ps]
+    srv = None
+    try:
+        solo = []
+        for p in ps:
+            assert cs.csvd_solve_interval(ctxs[0], I.a, I.b, p, V) == cs.CSVD_OK
+            solo.append((cs.csvd_get_info(ctxs[0]).rounds, cs.csvd_get_triplets(ctxs[0], I.m, I.n)))
+        assert [r for r, _ in solo] == [1, 2, 3]
+
+        def check(how):
+            for c, (rounds, ref) in zip(ctxs, solo):
+                assert cs.csvd_get_info(c).rounds == rounds, how
+                for x, y in zip(cs.csvd_get_triplets(c, I.m, I.n), ref):
+                    assert np.array_equal(x, y), how
+
+        say("adaptive batch of", len(ps))
+        st = cs.csvd_solve_batch(ctxs, [I.a] * 3, [I.b] * 3, ps, [V] * 3)
+        assert st == [cs.CSVD_OK] * 3
+        check("batched")
+        say("adaptive served")
+        srv = cs.csvd_server_create(8 << 30, 3)
+        reqs = [cs.csvd_server_submit(srv, c, I.a, I.b, p, V) for c, p in zip(ctxs, ps)]
+        for _ in range(10000):
+            if cs.csvd_server_step(srv, 64) == 0:
+                break
+        for r in reqs:
+            done, s = cs.csvd_server_poll(srv, r)
+            assert done and s == cs.CSVD_OK
+        check("served")
+    finally:
+        if srv is not None:
+            cs.csvd_server_destroy(srv)
+        for c in ctxs:
+            cs.csvd_destroy(c)
+
+
 def test_model1_plain_and_model2_exp():
     """Experiment II model problems with (L,M,N,ell,delta) = (20,4,32,1,1e-20)."""
     for kind, tr in ((1, cs.CSVD_PLAIN), (2, cs.CSVD_EXP)):
