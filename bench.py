@@ -327,6 +327,7 @@ def bench_c4(args, cs, torch):
     ids = [None] * len(reqs)
     done_at = [None] * len(reqs)
     status = [None] * len(reqs)
+    res, dropped, stored = [0.0] * len(reqs), 0, 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nxt = 0
@@ -348,21 +349,23 @@ def bench_c4(args, cs, torch):
                     status[i] = st
                     log(f"request {i} (n {reqs[i]['I'].n}, L {reqs[i]['L']}) done at {now:.2f}s, "
                         f"latency {now - reqs[i]['arrival']:.2f}s, status {st}")
+                    # the client reads its result and releases the context
+                    # (its results would otherwise hold device memory)
+                    q = reqs[i]
+                    if st in (0, -3):  # CSVD_OK, CSVD_ENOTCONV: results are readable
+                        _, _, _, r = cs.csvd_get_triplets(ctxs[i], q["I"].m, q["I"].n, want_vectors=False)
+                        inf = cs.csvd_get_info(ctxs[i])
+                        res[i] = float(r.max()) if r.size else 0.0
+                        dropped += int(inf.dropped)
+                        stored += int(inf.basis_stored)
+                    cs.csvd_destroy(ctxs[i])
+                    ctxs[i] = None
         if nxt == len(reqs) and all(x is not None for x in done_at):
             break
         if active == 0 and nxt < len(reqs):
             time.sleep(max(0.0, min(0.01, reqs[nxt]["arrival"] - now)))
     t_end = time.perf_counter() - t0
-    res, dropped, stored = [], 0, 0
-    for i, q in enumerate(reqs):
-        _, _, _, r = cs.csvd_get_triplets(ctxs[i], q["I"].m, q["I"].n, want_vectors=False)
-        res.append(float(r.max()) if r.size else 0.0)
-        inf = cs.csvd_get_info(ctxs[i])
-        dropped += int(inf.dropped)
-        stored += int(inf.basis_stored)
     cs.csvd_server_destroy(srv)
-    for c in ctxs:
-        cs.csvd_destroy(c)
     lat = sorted((d - q["arrival"]) * 1e3 for d, q in zip(done_at, reqs))
 
     def pct(x):

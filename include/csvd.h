@@ -301,7 +301,12 @@ typedef struct csvd_server csvd_server;
 
 /* budget_bytes: device memory the server may use for request state (the
  * matrices themselves live in their contexts).  max_batch: cap on
- * concurrently running requests. */
+ * concurrently running requests.  The results a finished request leaves in
+ * its context (moments, triplet vectors, epilogue buffers) are outside the
+ * budget until csvd_trim or csvd_destroy; while other requests run, a
+ * request is also admitted only when the device's free memory holds its
+ * footprint and 2 GiB more, and a request that cannot get its memory ends
+ * with CSVD_ENOMEM without stopping the others. */
 int csvd_server_create(csvd_server **srv, int64_t budget_bytes, int32_t max_batch, void *hip_stream);
 
 /* Queues a request.  The context must stay alive until the request is done.

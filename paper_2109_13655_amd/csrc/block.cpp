@@ -14,7 +14,8 @@ namespace csvd {
 // Chunks of stored bases that no solve is using, per device, kept for the
 // next solve: freeing and re-allocating tens of GB per solve stalls the
 // device while the driver clears the memory.  Idle chunks are freed when a
-// new allocation would not leave kStoreReserve free, and by csvd_trim.  The
+// new chunk would not leave kStoreReserve free, when any other device
+// allocation runs out of memory (DevBuf::alloc), and by csvd_trim.  The
 // pool lives until the process ends (never destroyed: it may hold device
 // memory past the runtime's own teardown).
 namespace {
@@ -111,7 +112,8 @@ size_t BlockJob::bytes_needed(int64_t m, int64_t n, int64_t nnz, int Lp, int S, 
   b += 16 * (size_t)(2 * S * L2);                  // complex scratch
   b += 8 * (size_t)(S * Lp) + 8 * Lp + 16 * 4;     // res, beta0, counters
   b += 8 * (size_t)((int64_t)Kcap * Kmom * L * Lp);  // moment coefficients
-  b += 256 * 32;
+  b += 8 * (size_t)(2 * n * Lp + Lp + 2 * hh_blocked_ws_doubles(Lp));  // Householder QR of a block
+  b += 256 * 40;
   return b;
 }
 
@@ -172,6 +174,11 @@ hipError_t BlockJob::create(const int *rp, const int *ci, const double *va, cons
   J.active = (int *)take(4 * 4);
   J.flags = (int *)take(4 * 4);
   J.F = (double *)take(8 * (size_t)((int64_t)Kcap * Kmom * L * Lp));
+  orth_x = (double *)take(8 * (size_t)(n * Lp));
+  orth_z = (double *)take(8 * (size_t)(n * Lp));
+  orth_tau = (double *)take(8 * (size_t)Lp);
+  orth_ws = (double *)take(8 * (size_t)hh_blocked_ws_doubles(Lp));
+  orth_ws2 = (double *)take(8 * (size_t)hh_blocked_ws_doubles(Lp));
   if (off > mem.bytes) return hipErrorOutOfMemory;
   J.tlong = lr ? kLongRow : 0x7fffffff;  // without segment tables every row is tiled
   if (lr) {
@@ -283,7 +290,7 @@ bool BlockJob::grow_store(int kneed, hipStream_t st) {
         }
         if (fr < bytes + kStoreReserve) return false;
         c.reset(new DevBuf());
-        if (c->alloc(bytes) != hipSuccess) return false;
+        if (c->alloc(bytes, false) != hipSuccess) return false;  // the pool's lock is held
       }
     }
     if (mixed) q32tab[chunks.size()] = c->as<float>();
@@ -432,27 +439,22 @@ hipError_t BEngine::start(BlockJob *j) {
 // the block is numerically rank deficient (a Cholesky QR of such a block
 // loses orthogonality).  Deterministic, so a second pass reproduces it bit
 // for bit.
+// The work buffers are the job's own (taken at create), so a Householder
+// step allocates nothing while the engine steps.
 hipError_t BEngine::orth_block(BlockJob *j, const double *src, double *dst, double *R, double *norms) {
   BJobDesc &J = j->h;
   const int64_t n = J.n;
   const int Lp = J.Lp;
-  DevBuf X, Z, tau, ws, ws2;
   hipError_t e;
-  if ((e = X.alloc(sizeof(double) * n * Lp)) != hipSuccess) return e;
-  if ((e = Z.alloc(sizeof(double) * n * Lp)) != hipSuccess) return e;
-  if ((e = tau.alloc(sizeof(double) * Lp)) != hipSuccess) return e;
-  if ((e = ws.alloc(sizeof(double) * hh_blocked_ws_doubles(Lp))) != hipSuccess) return e;
-  if ((e = ws2.alloc(sizeof(double) * hh_blocked_ws_doubles(Lp))) != hipSuccess) return e;
-  double *x = X.as<double>(), *z = Z.as<double>();
+  double *x = j->orth_x, *z = j->orth_z;
   if ((e = launch_row_to_col((int)n, Lp, src, Lp, x, n, st_)) != hipSuccess) return e;
   if (norms && (e = launch_col_norms(x, n, (int)n, Lp, norms, st_)) != hipSuccess) return e;
-  if ((e = hh_qr_blocked(x, n, (int)n, Lp, tau.as<double>(), ws.as<double>(), st_)) != hipSuccess) return e;
+  if ((e = hh_qr_blocked(x, n, (int)n, Lp, j->orth_tau, j->orth_ws, st_)) != hipSuccess) return e;
   if (R && (e = launch_b_r0(x, n, Lp, R, st_)) != hipSuccess) return e;
   if ((e = launch_b_eye(z, n, n, Lp, st_)) != hipSuccess) return e;
-  if ((e = hh_apply_blocked(x, n, (int)n, Lp, ws.as<double>(), z, n, Lp, ws2.as<double>(), st_)) != hipSuccess)
-    return e;
+  if ((e = hh_apply_blocked(x, n, (int)n, Lp, j->orth_ws, z, n, Lp, j->orth_ws2, st_)) != hipSuccess) return e;
   if ((e = launch_col_to_row((int)n, Lp, z, n, dst, Lp, st_)) != hipSuccess) return e;
-  return hipStreamSynchronize(st_);  // the work buffers are freed on return
+  return hipStreamSynchronize(st_);
 }
 
 // Q_0 (block 0 of the basis) and, on the first pass, B_0 and the column norms

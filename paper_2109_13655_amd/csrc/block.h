@@ -24,6 +24,8 @@ struct BlockJob {
   BJobDesc h{};
   DevBuf mem, d_shift, d_cmom, d_desc, d_toff, d_qtab, d_q32tab;
   DevBuf seg_part;  // partial rows of the long-row segments (both products)
+  // work buffers of the Householder QR of one block (inside `mem`)
+  double *orth_x = nullptr, *orth_z = nullptr, *orth_tau = nullptr, *orth_ws = nullptr, *orth_ws2 = nullptr;
   BBatch solo{};
   std::vector<double *> qtab;                  // host copy of the basis table
   std::vector<float *> q32tab;                 // host copy of the FP32 basis table (mixed precision)

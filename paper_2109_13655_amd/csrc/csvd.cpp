@@ -1785,6 +1785,8 @@ static int srv_err(csvd_server *s, int code, const std::string &m) {
   return code;
 }
 
+constexpr int64_t kSrvFreeReserve = 2LL << 30;  // device memory left free when admitting beside others
+
 static int srv_admit(csvd_server *s) {
   int running = 0;
   for (auto &kv : s->reqs)
@@ -1793,6 +1795,18 @@ static int srv_admit(csvd_server *s) {
     const int64_t id = s->queue.front();
     auto &R = s->reqs[id];
     if (s->used + R.bytes > s->budget) break;  // FIFO: wait for memory
+    // the budget counts live requests only: results that finished requests
+    // keep in their contexts (and other users of the device) take memory
+    // outside it.  While others run, a request that would not fit what is
+    // really free waits; with none running it is tried (run_begin then
+    // fails it alone with CSVD_ENOMEM if it does not fit)
+    if (running > 0) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess && (int64_t)fr < R.bytes + kSrvFreeReserve) {
+        release_idle_chunks();
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && (int64_t)fr < R.bytes + kSrvFreeReserve) break;
+      }
+    }
     s->queue.pop_front();
     const bool mixed = R.p.precision == CSVD_MIXED;
     Engine *e = s->eng[mixed ? 1 : 0].get();

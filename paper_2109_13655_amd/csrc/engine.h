@@ -16,7 +16,14 @@
 
 namespace csvd {
 
-// Device allocation helper: frees on destruction.
+// Frees the idle chunks of stored bases kept for reuse (block.cpp).
+void release_idle_chunks();
+
+// Device allocation helper: frees on destruction.  When the device is out of
+// memory, the idle stored-basis chunks are released and the allocation tried
+// once more (reclaim = false for callers that hold the chunk pool's lock).  A
+// failed hipMalloc's error is consumed here, so that a later launch check
+// (hipGetLastError) does not report it.
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
@@ -24,11 +31,17 @@ struct DevBuf {
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf() { release(); }
-  hipError_t alloc(size_t b) {
+  hipError_t alloc(size_t b, bool reclaim = true) {
     release();
     if (b == 0) b = 256;
     hipError_t e = hipMalloc(&p, b);
+    if (e == hipErrorOutOfMemory && reclaim) {
+      (void)hipGetLastError();
+      release_idle_chunks();
+      e = hipMalloc(&p, b);
+    }
     if (e != hipSuccess) {
+      (void)hipGetLastError();
       p = nullptr;
       return e;
     }
