@@ -43,6 +43,12 @@ int hip_code(hipError_t e) { return e == hipErrorOutOfMemory ? CSVD_ENOMEM : CSV
 // Column blocks between a device array with leading dimension ld and a
 // contiguous host array (rows x cols, column-major).  Strided transfers go
 // through a packed device copy and a plain 1-D transfer.
+// Host transfers of column blocks with a leading dimension go through a
+// staging buffer kept in the context (a fresh buffer per call would free
+// device memory, and hipFree waits for the whole device, in the middle of
+// other contexts' work on a batch).
+constexpr int kStagingSlot = 31;
+
 static int d2h_cols(csvd_ctx *ctx, double *host, const double *dev, int64_t ld, int64_t rows, int cols,
                     hipStream_t st) {
   if (rows <= 0 || cols <= 0) return CSVD_OK;
@@ -52,8 +58,8 @@ static int d2h_cols(csvd_ctx *ctx, double *host, const double *dev, int64_t ld, 
     HIPCHK(ctx, hipStreamSynchronize(st));
     return CSVD_OK;
   }
-  DevBuf tmp;
-  HIPCHK(ctx, tmp.alloc(bytes));
+  DevBuf &tmp = ctx->ws[kStagingSlot];
+  if (!tmp.p || tmp.bytes < bytes) HIPCHK(ctx, tmp.alloc(bytes));
   HIPCHK(ctx, launch_copy_block(dev, ld, tmp.as<double>(), rows, rows, cols, st));
   HIPCHK(ctx, hipMemcpyAsync(host, tmp.p, bytes, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
@@ -64,8 +70,8 @@ static int h2d_cols(csvd_ctx *ctx, double *dev, int64_t ld, const double *host, 
                     hipStream_t st) {
   if (rows <= 0 || cols <= 0) return CSVD_OK;
   const size_t bytes = sizeof(double) * (size_t)rows * cols;
-  DevBuf tmp;
-  HIPCHK(ctx, tmp.alloc(bytes));
+  DevBuf &tmp = ctx->ws[kStagingSlot];
+  if (!tmp.p || tmp.bytes < bytes) HIPCHK(ctx, tmp.alloc(bytes));
   HIPCHK(ctx, hipMemcpyAsync(tmp.p, host, bytes, hipMemcpyHostToDevice, st));
   HIPCHK(ctx, launch_copy_block(tmp.as<double>(), rows, dev, ld, rows, cols, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
@@ -799,8 +805,9 @@ int run_finalize(SolveRun &R, hipStream_t stream = nullptr) {
   ctx->sigma.assign(t, 0.0);
   ctx->resid.assign(t, 0.0);
   ctx->resid_est.assign(t, 0.0);
-  HIPCHK(ctx, ctx->d_U.alloc(sizeof(double) * mpad * std::max(t, 1)));
-  HIPCHK(ctx, ctx->d_V.alloc(sizeof(double) * npad * std::max(t, 1)));
+  // triplet vectors (column stride mpad / npad); kept between solves
+  HIPCHK(ctx, ws_grow(ctx->d_U, sizeof(double) * mpad * std::max(t, 1)));
+  HIPCHK(ctx, ws_grow(ctx->d_V, sizeof(double) * npad * std::max(t, 1)));
   double normA = p.norm_a;
   if (!(normA > 0) && !R.block) {
     std::vector<double> d, e;
