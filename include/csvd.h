@@ -72,7 +72,8 @@ typedef struct {
                           /* so larger problems avoid the second pass); a solve whose   */
                           /* triplets miss 1e-6 is refined by accumulating the moments  */
                           /* again from the basis regenerated in FP64 (csvd_info.       */
-                          /* mixed_refined); csvd_solve_batch keeps FP64 bases.         */
+                          /* mixed_refined); csvd_solve_batch and served block solves   */
+                          /* keep FP64 bases.                                           */
                           /* Per-column solver: the per-shift solution/search vectors   */
                           /* and the window basis are FP32.  Target residual 1e-6       */
   double  solve_rtol;     /* per (shift, column) stop: ||V - (z I - A^T A) Y|| / ||V||     */

@@ -1828,9 +1828,12 @@ static int srv_admit(csvd_server *s) {
     }
     // a stored basis (no second pass) only when its largest possible size
     // (Kcap + 1 blocks, in whole chunks) also fits the budget; the budget
-    // then holds it until the request is done
+    // then holds it until the request is done.  Served block solves keep FP64
+    // bases, as batches do: the FP64 refinement of a mixed solve whose FP32
+    // basis misses the mixed target runs only in csvd_solve_interval
     if (R.run->bjob) {
       BlockJob &B = *R.run->bjob;
+      B.mixed = false;
       const int64_t blocks = ((int64_t)B.Kcap + 1 + kStoreChunk - 1) / kStoreChunk * kStoreChunk;
       const int64_t sb = blocks * B.h.n * B.h.Lp * (B.mixed ? 4 : 8);
       if (R.p.keep_basis != 0 && s->used + R.bytes + sb <= s->budget) {

@@ -774,6 +774,37 @@ def test_server_results_match_solo_and_cancel(solver):
             cs.csvd_destroy(c)
 
 
+def test_served_mixed_block_keeps_fp64_basis():
+    """A served block request in mixed precision keeps an FP64 basis (the
+    FP64 refinement of an FP32 basis runs only in csvd_solve_interval): its
+    triplets are those of the FP64 solve, bit for bit."""
+    I = _mid_problem()
+    V = synth.v_in(I.n, 8, 12)
+    ctxs = [make_ctx(I), make_ctx(I)]
+    srv = None
+    try:
+        base = dict(L=8, M=4, N=16, norm_a=1.0, solver=cs.CSVD_SOLVER_BLOCK)
+        assert cs.csvd_solve_interval(ctxs[0], I.a, I.b, cs.csvd_params_default(**base), V) == cs.CSVD_OK
+        ref = cs.csvd_get_triplets(ctxs[0], I.m, I.n)
+        srv = cs.csvd_server_create(8 << 30, 2)
+        req = cs.csvd_server_submit(srv, ctxs[1], I.a, I.b, cs.csvd_params_default(precision=cs.CSVD_MIXED, **base), V)
+        for _ in range(10000):
+            if cs.csvd_server_step(srv, 64) == 0:
+                break
+        done, st = cs.csvd_server_poll(srv, req)
+        assert done and st == cs.CSVD_OK
+        info = cs.csvd_get_info(ctxs[1])
+        say("served mixed block: solver", info.solver, "mixed_resid_fp32", info.mixed_resid_fp32)
+        assert info.solver == cs.CSVD_SOLVER_BLOCK and info.mixed_resid_fp32 == 0.0 and info.mixed_refined == 0
+        for x, y in zip(cs.csvd_get_triplets(ctxs[1], I.m, I.n), ref):
+            assert np.array_equal(x, y)
+    finally:
+        if srv is not None:
+            cs.csvd_server_destroy(srv)
+        for c in ctxs:
+            cs.csvd_destroy(c)
+
+
 @pytest.mark.parametrize("R,N,K", [(16, 16, 4), (70, 33, 21), (1024, 50, 110), (3, 200, 1)])
 def test_dense_gemm_mfma(R, N, K):
     """FP64 MFMA GEMM against the textbook product (edges and ragged tiles)."""
