@@ -196,6 +196,36 @@ def test_top_of_spectrum_and_multiple_value(solver):
             assert truth.subspace_gap(U[:, mine], I.U[:, sel]) <= 1e-7
 
 
+@pytest.mark.parametrize("solver", [cs.CSVD_SOLVER_BLOCK, cs.CSVD_SOLVER_SINGLE])
+def test_wide_interval_end_with_adaptive_rounds(solver):
+    """An interval reaching far past sigma_max (b = 1.5 over a spectrum ending
+    at 1) sizes the ellipse by [a^2, b^2], so the filter's transition at a is
+    wide and one round leaves the value nearest a at 1.0e-8 (block) or 3.4e-8
+    (per column).  With ell_adaptive and target 1e-8 a second round runs
+    where it is missed, and all ten values end within the target."""
+    sig = np.linspace(0.02, 1.0, 1100)
+    sig[540:544] = 0.5
+    sig = np.sort(sig)[::-1]
+    I = synth.givens_known(1300, 1100, sigma=sig, nrot=3000, config=94, a=0.98, b=1.5)
+    so = np.sort(I.sigma)
+    a, b = 0.5 * (so[-11] + so[-10]), 1.5
+    exact = np.sort(I.sigma[(I.sigma >= a) & (I.sigma <= b)])
+    ctx = make_ctx(I)
+    try:
+        p = cs.csvd_params_default(L=16, M=8, N=32, solve_rtol=1e-12, solver=solver, ell=2, ell_adaptive=1,
+                                   resid_target=1e-8)
+        st = cs.csvd_solve_interval(ctx, a, b, p, synth.v_in(I.n, 16, 94))
+        s, U, V, r = cs.csvd_get_triplets(ctx, I.m, I.n)
+        info = cs.csvd_get_info(ctx)
+    finally:
+        cs.csvd_destroy(ctx)
+    say("wide interval, solver", solver, "status", st, "rounds", info.rounds, "t_hat", s.size, "resid", r.max())
+    assert st == cs.CSVD_OK and info.dropped == 0 and s.size == exact.size == 10
+    assert info.rounds == 2 or (solver == cs.CSVD_SOLVER_BLOCK and info.rounds == 1)
+    np.testing.assert_allclose(s, exact, rtol=1e-12)
+    assert truth.triplet_residuals(I, s, U, V, normA=1.0).max() <= 1e-8
+
+
 def test_block_and_single_solvers_agree():
     """Both solvers give the same triplets on the same problem."""
     I = _mid_problem()
