@@ -2,8 +2,11 @@
 every function include/csvd.h declares, fills the paper's defaults, computes
 the quadrature of Sec. 4 like the oracle does, and rejects malformed input
 before touching the device."""
+import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -30,6 +33,34 @@ def test_library_exports_every_declared_symbol():
     assert "csvd_solve_interval" in names and "csvd_probe_gather" in names and len(names) >= 20
     for name in names:
         assert hasattr(lib, name), name
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes mirrors of csvd_params and csvd_info have the size
+    and the field offsets that the host C compiler gives the header's
+    structs."""
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if not cc:
+        pytest.skip("no host C compiler")
+    structs = (cs.csvd_params, cs.csvd_info)
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "csvd.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'  printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in st._fields_:
+            lines.append(f'  printf("{name}.{field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.splitlines() if line)
+    for st in structs:
+        name = st.__name__
+        assert int(got[f"{name} size"]) == ctypes.sizeof(st), name
+        for field, _ in st._fields_:
+            assert int(got[f"{name}.{field}"]) == getattr(st, field).offset, (name, field)
 
 
 def test_params_default_are_the_papers():
