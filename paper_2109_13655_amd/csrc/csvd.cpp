@@ -1650,16 +1650,17 @@ int csvd_solve_batch(int32_t count, csvd_ctx *const *ctxs, const double *a, cons
       if (eng.start(runs[i]->bjob.get()) != hipSuccess) return CSVD_EDEVICE;
     }
     while (true) {
+      std::vector<int> restart;
       {
         std::unique_lock<std::mutex> g(rq_mu);
         if (eng.active() == 0) {  // nothing to step: wait for the epilogues
           rq_cv.wait(g, [&] { return in_epilogue == 0 || !requeue.empty(); });
           if (requeue.empty()) break;
         }
-        for (int i : requeue)
-          if (eng.start(runs[i]->bjob.get()) != hipSuccess) return CSVD_EDEVICE;
-        requeue.clear();
+        restart.swap(requeue);
       }
+      for (int i : restart)
+        if (eng.start(runs[i]->bjob.get()) != hipSuccess) return CSVD_EDEVICE;
       for (int q = 0; q < kBlockPoll; ++q)
         if (eng.step(nullptr, false) != hipSuccess) return CSVD_EDEVICE;
       std::vector<BlockJob *> fin;
